@@ -1,0 +1,261 @@
+"""Seeded synthetic workloads (problem descriptions and initial states).
+
+This module holds no arithmetic of the kinetic scheme: it only describes the
+problems (grid, degree, law, kinetic velocities, omega, dt) and samples the
+initial conserved state W0 at the interpolation points.  Both the GPU path and
+the CPU oracle take their inputs from here; neither is imported by it.
+
+The meshes, experiments and data sets of the paper are not available; these
+seeded Cartesian problems stand in for them (periodic unit boxes).
+
+* ``time step``: dt = beta * h_min / lambda_max with h_min = volume/surface of
+  a cell (h / (2 d) on a cube) and lambda_max the largest wave speed of the
+  conservation law (definition of the CFL number in Sec. 6.1.2, eq:def_CFL).
+* ``kinetic velocities``: +-lambda e_i (D2Q4 / D3Q6); lambda is chosen above the
+  largest wave speed (sub-characteristic condition, Sec. 2.1), on the bound
+  lambda >= d * max spectral radius for acoustics and advection, and 1.1 times
+  that bound for Euler.
+
+Node coordinates for sampling are computed here with numpy's Legendre module
+(Gauss-Lobatto points = end points + roots of P_p'); they are input sampling
+positions only.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_BASE = 2212110100
+
+LAW_LINEAR = 0
+LAW_EULER = 1
+
+
+def gl_points(p: int) -> np.ndarray:
+    """Gauss-Lobatto points on [0, 1] (p + 1 points); p = 0 -> midpoint."""
+    if p == 0:
+        return np.array([0.5])
+    leg = np.polynomial.legendre.Legendre.basis(p).deriv()
+    inner = np.sort(np.real(leg.roots())) if p > 1 else np.array([])
+    x = np.concatenate(([-1.0], inner, [1.0]))
+    return 0.5 * (x + 1.0)
+
+
+def node_coords(spec: dict) -> np.ndarray:
+    """Physical coordinates, shape [n_cell, n_node, dim], cells and nodes x-fastest."""
+    d = spec["dim"]
+    N = spec["n_cells"][:d]
+    lo = np.asarray(spec["box_lo"][:d], dtype=np.float64)
+    hi = np.asarray(spec["box_hi"][:d], dtype=np.float64)
+    h = (hi - lo) / np.asarray(N)
+    xi = gl_points(spec["degree"])
+    P = len(xi)
+    # cell coordinate grids (x fastest) and node offsets (x fastest)
+    cidx = np.indices(tuple(reversed(N))).reshape(d, -1)[::-1]  # [d, ncell]
+    nidx = np.indices((P,) * d).reshape(d, -1)[::-1]              # [d, nn]
+    X = np.empty((cidx.shape[1], nidx.shape[1], d))
+    for a in range(d):
+        X[:, :, a] = lo[a] + h[a] * (cidx[a][:, None] + xi[nidx[a]][None, :])
+    return X
+
+
+def d2q4(lam: float) -> list[float]:
+    return [lam, 0.0, -lam, 0.0, 0.0, lam, 0.0, -lam]
+
+
+def d3q6(lam: float) -> list[float]:
+    v = []
+    for a in range(3):
+        for s in (1.0, -1.0):
+            e = [0.0, 0.0, 0.0]
+            e[a] = s * lam
+            v += e
+    return v
+
+
+def _box(d):
+    return [0.0] * 3, [1.0 if a < d else 1.0 for a in range(3)]
+
+
+def _pad3(x, fill=1):
+    x = list(x)
+    return x + [fill] * (3 - len(x))
+
+
+def _dt(beta, h, d, lam_max):
+    return beta * (h / (2.0 * d)) / lam_max
+
+
+# --------------------------------------------------------------------------
+# initial states (recipes stated in the design doc)
+# --------------------------------------------------------------------------
+
+def _min_image(dx):
+    return dx - np.round(dx)
+
+
+def w0_advection(X, rng):
+    """Gaussian pulse at (1/2, 1/2), width 0.08, plus 8 Fourier modes."""
+    r2 = np.sum(_min_image(X - 0.5) ** 2, axis=-1)
+    w = np.exp(-r2 / (2 * 0.08 ** 2))
+    for _ in range(8):
+        A = rng.uniform(-0.1, 0.1)
+        while True:
+            k = rng.integers(-4, 5, size=X.shape[-1])
+            if np.any(k != 0):
+                break
+        phi = rng.uniform(0, 2 * np.pi)
+        w = w + A * np.sin(2 * np.pi * (X @ k) + phi)
+    return w[..., None]
+
+
+def w0_acoustics(X, rng):
+    """Sum of 16 Gaussian pressure pulses; zero velocity."""
+    d = X.shape[-1]
+    pr = np.zeros(X.shape[:-1])
+    for _ in range(16):
+        a = rng.uniform(0.5, 1.0)
+        c = rng.uniform(0.0, 1.0, size=d)
+        s = rng.uniform(0.01, 0.03)
+        r2 = np.sum(_min_image(X - c) ** 2, axis=-1)
+        pr += a * np.exp(-r2 / (2 * s * s))
+    W = np.zeros(X.shape[:-1] + (1 + d,))
+    W[..., 0] = pr
+    return W
+
+
+def w0_euler(X, rng, gamma=1.4):
+    """rho = 1 + 0.2 s/max|s|, p = 1, u = 0.1 v/max|v| with v divergence-free."""
+    d = X.shape[-1]
+    s = np.zeros(X.shape[:-1])
+    v = np.zeros(X.shape[:-1] + (d,))
+    for _ in range(8):
+        while True:
+            k = rng.integers(-3, 4, size=d)
+            if np.any(k != 0):
+                break
+        phi = rng.uniform(0, 2 * np.pi)
+        s += np.sin(2 * np.pi * (X @ k) + phi)
+    for _ in range(8):
+        while True:
+            k = rng.integers(-3, 4, size=d)
+            if np.any(k != 0):
+                break
+        phi = rng.uniform(0, 2 * np.pi)
+        r = rng.normal(size=d)
+        e = r - (r @ k) / (k @ k) * k        # component orthogonal to k
+        e = e / np.linalg.norm(e)
+        v += e * np.cos(2 * np.pi * (X @ k) + phi)[..., None]
+    rho = 1.0 + 0.2 * s / np.max(np.abs(s))
+    u = 0.1 * v / np.max(np.linalg.norm(v, axis=-1))
+    pr = np.ones_like(rho)
+    W = np.empty(X.shape[:-1] + (d + 2,))
+    W[..., 0] = rho
+    W[..., 1:1 + d] = rho[..., None] * u
+    W[..., d + 1] = pr / (gamma - 1.0) + 0.5 * rho * np.sum(u * u, axis=-1)
+    return W
+
+
+def euler_speeds(W, d, gamma=1.4):
+    """(max |u| + c, max_i |u_i| + c) over the sampled nodes."""
+    rho = W[..., 0]
+    u = W[..., 1:1 + d] / rho[..., None]
+    pr = (gamma - 1.0) * (W[..., d + 1] - 0.5 * rho * np.sum(u * u, axis=-1))
+    c = np.sqrt(gamma * pr / rho)
+    return float(np.max(np.linalg.norm(u, axis=-1) + c)), float(np.max(np.abs(u).max(axis=-1) + c))
+
+
+# --------------------------------------------------------------------------
+# problem descriptions
+# --------------------------------------------------------------------------
+
+def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=None,
+                  beta=None, omega=None, n_iter=3, theta=0.5, seed=None,
+                  precision="fp32"):
+    """Return (spec, W0) for workload ``cfg`` (1..4), optionally resized.
+
+    spec is a plain dict (problem description); W0 has shape [cell, node, m].
+    """
+    seed = SEED_BASE + cfg if seed is None else seed
+    rng = np.random.default_rng(seed)
+    if cfg == 1:
+        d, p, m = 2, 1, 1
+        N = n_cells or [32, 32]
+        S = sub_cells or list(N)
+        beta = 4.0 if beta is None else beta
+        omega = 1.9 if omega is None else omega
+        steps = 20 if steps is None else steps
+        a = (1.0, 0.5)
+        params = [a[0], a[1]]          # A^x = [a_x], A^y = [a_y]  (m = 1)
+        lam = 2.0
+        lam_max = math.hypot(*a)
+        law = LAW_LINEAR
+        vel = d2q4(lam)
+        name = "advection2d_q1"
+    elif cfg == 2:
+        d, p, m = 2, 2, 3
+        N = n_cells or [256, 256]
+        S = sub_cells or [32, 32]
+        beta = 10.0 if beta is None else beta
+        omega = 2.0 if omega is None else omega
+        steps = 100 if steps is None else steps
+        c = 1.0
+        Ax = [[0, c, 0], [c, 0, 0], [0, 0, 0]]
+        Ay = [[0, 0, c], [0, 0, 0], [c, 0, 0]]
+        params = [float(v) for row in Ax + Ay for v in row]
+        lam = 2.0 * c
+        lam_max = c
+        law = LAW_LINEAR
+        vel = d2q4(lam)
+        name = "acoustics2d_q2"
+    elif cfg in (3, 4):
+        d, m = 3, 5
+        p = 2 if cfg == 3 else 3
+        N = n_cells or ([128] * 3 if cfg == 3 else [96] * 3)
+        S = sub_cells or ([16] * 3 if cfg == 3 else [12] * 3)
+        beta = (8.0 if cfg == 3 else 20.0) if beta is None else beta
+        omega = 1.9 if omega is None else omega
+        steps = 50 if steps is None else steps
+        params = [1.4]
+        law = LAW_EULER
+        lam = None
+        name = "euler3d_q%d" % p
+    else:
+        raise ValueError("unknown workload %r" % cfg)
+    if degree is not None:
+        p = degree
+    N = list(N)
+    S = list(S)
+    spec = {
+        "name": name, "cfg": cfg, "dim": d, "n_cells": _pad3(N), "sub_cells": _pad3(S),
+        "box_lo": [0.0, 0.0, 0.0], "box_hi": [1.0, 1.0, 1.0], "degree": p, "m": m,
+        "law": law, "law_params": params, "omega": float(omega), "theta": float(theta),
+        "n_iter": int(n_iter), "steps": int(steps), "beta": float(beta), "seed": seed,
+        "precision": precision,
+    }
+    X = node_coords(spec)
+    if cfg == 1:
+        W0 = w0_advection(X, rng)
+    elif cfg == 2:
+        W0 = w0_acoustics(X, rng)
+    else:
+        W0 = w0_euler(X, rng)
+        lam_max, lam_axis = euler_speeds(W0, d)
+        lam = 1.1 * d * lam_axis
+        vel = d3q6(lam)
+    h = 1.0 / N[0]
+    spec["lam"] = float(lam)
+    spec["lam_max"] = float(lam_max)
+    spec["vel"] = [float(v) for v in vel]
+    spec["n_vel"] = len(vel) // d
+    spec["dt"] = float(_dt(beta, h, d, lam_max))
+    spec["kinetic_courant"] = float(lam * spec["dt"] / h)
+    return spec, np.ascontiguousarray(W0, dtype=np.float64)
+
+
+def unknowns(spec: dict) -> int:
+    """U = cells * nodes * m * n_vel (scalar kinetic unknowns per step)."""
+    d = spec["dim"]
+    ncell = int(np.prod(spec["n_cells"][:d]))
+    return ncell * (spec["degree"] + 1) ** d * spec["m"] * spec["n_vel"]

@@ -1,0 +1,464 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics (closed forms, exact polynomial reproduction, brute-force global
+solves, Fourier amplification factors, conservation, relaxation identities,
+convergence orders, stability).  CPU only."""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2212_11010_amd import workloads as wl
+from tests import brute_force as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def spec1d(N=16, S=None, p=1, V=1.0, nu=2.0, theta=0.5, K=3, m=1, omega=1.0):
+    """Scalar 1-D transport problem on [0,1], kinetic velocities +-V."""
+    h = 1.0 / N
+    dt = nu * h / abs(V)
+    return {
+        "dim": 1, "n_cells": [N, 1, 1], "sub_cells": [S or N, 1, 1],
+        "box_lo": [0.0] * 3, "box_hi": [1.0] * 3, "degree": p, "m": m,
+        "law": wl.LAW_LINEAR, "law_params": [0.0] * (m * m), "n_vel": 2,
+        "vel": [V, -V], "omega": omega, "dt": dt, "theta": theta, "n_iter": K,
+    }
+
+
+# ---------------------------------------------------------------- GL tables
+
+def _golden_gl():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "gauss_lobatto.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        p, j, x, w = line.split()
+        ev = lambda s: eval(s, {"sqrt": math.sqrt})  # noqa: E731  (fixture expressions)
+        rows.append((int(p), int(j), ev(x), ev(w)))
+    return rows
+
+
+def test_gl_closed_forms(orc):
+    for p, j, x, w in _golden_gl():
+        xi, wt = orc.gl(p)
+        assert abs(xi[j] - x) < 1e-15 and abs(wt[j] - w) < 1e-15
+
+
+@pytest.mark.parametrize("p", range(1, 7))
+def test_gl_quadrature_exact_to_degree_2p_minus_1(orc, p):
+    xi, w = orc.gl(p)
+    for q in range(2 * p):
+        assert abs(np.sum(w * xi ** q) - 1.0 / (q + 1)) < 1e-14
+    assert abs(np.sum(w * xi ** (2 * p)) - 1.0 / (2 * p + 1)) > 1e-9  # not exact at 2p
+
+
+@pytest.mark.parametrize("p", range(1, 7))
+def test_derivative_matrix_exact_on_polynomials(orc, p):
+    xi, _ = orc.gl(p)
+    D = orc.deriv(p)
+    for q in range(p + 1):
+        exact = q * xi ** (q - 1) if q else np.zeros_like(xi)
+        assert np.max(np.abs(D @ xi ** q - exact)) < 1e-12
+
+
+# ---------------------------------------------------------- cell residual
+
+def test_p1_operator_matches_hand_derivation(orc):
+    """Golden: the 1-D p=1 operator derived by hand from eq:dg_imp."""
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "dg_p1_operator.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, *nums = line.split()
+        vals[key] = np.array([float(v) for v in nums])
+    V, h = 1.7, 0.25
+    spec = spec1d(N=4, p=1, V=V)
+    cfg = orc.Config(spec)
+    L = np.zeros((2, 2))
+    for j in range(2):
+        e = np.zeros(2)
+        e[j] = 1
+        L[:, j] = orc.cell_residual(cfg, [V], e, np.zeros(4))
+    assert np.allclose(L, (V / h) * vals["L"].reshape(2, 2), rtol=0, atol=1e-13)
+    tr = np.zeros((2, 2))
+    tr[0, :] = 1.0      # face (axis 0, side 0) = inflow face for V > 0
+    r = orc.cell_residual(cfg, [V], np.zeros(2), tr.ravel())
+    assert np.allclose(r, (V / h) * vals["lift"], atol=1e-13)
+
+
+def _poly_eval(coef, X):
+    """Tensor polynomial sum_c coef[c] prod_a x_a^{e_a}; returns value, grad."""
+    d = X.shape[-1]
+    val = np.zeros(X.shape[:-1])
+    grad = np.zeros(X.shape)
+    for expo, c in coef.items():
+        term = c * np.prod([X[..., a] ** expo[a] for a in range(d)], axis=0)
+        val += term
+        for a in range(d):
+            if expo[a] == 0:
+                continue
+            g = c * expo[a] * X[..., a] ** (expo[a] - 1)
+            for b in range(d):
+                if b != a:
+                    g = g * X[..., b] ** expo[b]
+            grad[..., a] += g
+    return val, grad
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+def test_cell_residual_reproduces_exact_derivative(orc, dim, p):
+    """For a polynomial g of degree <= p in each variable, continuous across the
+    faces, the DG residual equals V . grad g at every node (exact GL
+    integration of the volume term, exactness of collocation)."""
+    rng = np.random.default_rng(10 * dim + p)
+    h = [0.3, 0.2, 0.45][:dim]
+    spec = {
+        "dim": dim, "n_cells": [4, 5, 3][:dim] + [1] * (3 - dim), "sub_cells": [4, 5, 3][:dim] + [1] * (3 - dim),
+        "box_lo": [0.0] * 3, "box_hi": [h[a] * [4, 5, 3][a] if a < dim else 1.0 for a in range(3)],
+        "degree": p, "m": 1, "law": 0, "law_params": [0.0] * dim, "n_vel": 1,
+        "vel": [0.0] * dim, "omega": 1.0, "dt": 0.1, "theta": 0.5, "n_iter": 1,
+    }
+    cfg = orc.Config(spec)
+    xi, _ = orc.gl(p)
+    P = p + 1
+    nidx = np.indices((P,) * dim).reshape(dim, -1)[::-1].T  # x fastest
+    lo = rng.uniform(-1, 1, size=dim)
+    X = np.stack([lo[a] + h[a] * xi[nidx[:, a]] for a in range(dim)], axis=-1)
+    import itertools
+    coef = {e: rng.normal() for e in itertools.product(range(p + 1), repeat=dim)}
+    g, grad = _poly_eval(coef, X)
+    for trial in range(4):
+        V = rng.normal(size=dim) * 2
+        if trial == 0:
+            V[0] = 0.0
+        if trial == 1 and dim == 3:
+            V = math.sqrt(3) * np.array([-1.0, 1.0, -1.0])   # a D3Q4 velocity
+        tr = np.tile(g, (2 * dim, 1))  # continuous: neighbour value = g at the node
+        r = orc.cell_residual(cfg, V, g, tr.ravel())
+        assert np.max(np.abs(r - grad @ V)) < 1e-10 * (1 + np.max(np.abs(grad @ V)))
+
+
+# ------------------------------------------------------- transport solves
+
+def test_degree0_fourier_amplification(orc):
+    """Degree 0 is the implicit upwind finite-volume scheme; its theta-scheme
+    amplification factor is G = (1 - (1-th) nu z) / (1 + th nu z),
+    z = 1 - exp(-i phi).  Converged subdomain iteration (K large)."""
+    N, nu = 16, 2.5
+    for th in (0.5, 1.0):
+        spec = spec1d(N=N, S=4, p=0, nu=nu, theta=th, K=60)
+        cfg = orc.Config(spec)
+        for kappa in (1, 3):
+            phi = 2 * np.pi * kappa / N
+            j = np.arange(N)
+            f0 = np.cos(phi * j)
+            f1 = orc.transport(cfg, 0, f0.reshape(N, 1)).ravel()
+            z = 1 - np.exp(-1j * phi)
+            G = (1 - (1 - th) * nu * z) / (1 + th * nu * z)
+            assert np.max(np.abs(f1 - np.real(G * np.exp(1j * phi * j)))) < 1e-13
+
+
+@pytest.mark.parametrize("dim,N,S,p,K,vel", [
+    (2, [6, 4], [3, 2], 1, 1, [1.3, 0.0]),
+    (2, [6, 4], [3, 2], 2, 2, [0.0, -0.9]),
+    (2, [6, 4], [3, 2], 1, 3, [1.1, -0.7]),
+    (2, [4, 4], [4, 4], 2, 3, [-0.8, 1.4]),
+    (3, [4, 2, 2], [2, 1, 2], 1, 3, [1.0, -1.0, 1.0]),
+])
+def test_sweep_equals_brute_force_global_solve(orc, dim, N, S, p, K, vel):
+    rng = np.random.default_rng(7)
+    spec = {
+        "dim": dim, "n_cells": N + [1] * (3 - dim), "sub_cells": S + [1] * (3 - dim),
+        "box_lo": [0.0] * 3, "box_hi": [1.0] * 3, "degree": p, "m": 1, "law": 0,
+        "law_params": [0.0] * dim, "n_vel": 1, "vel": vel, "omega": 1.0,
+        "dt": 0.37, "theta": 0.5, "n_iter": K,
+    }
+    cfg = orc.Config(spec)
+    f0 = rng.normal(size=(cfg.ncell, cfg.nn))
+    got = orc.transport(cfg, 0, f0)
+    ref = bf.global_transport(orc, cfg, 0, f0, K)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # theta = 1: the implicit Euler form printed as eq:dg_imp
+    spec["theta"] = 1.0
+    cfg = orc.Config(spec)
+    got = orc.transport(cfg, 0, f0)
+    ref = bf.global_transport(orc, cfg, 0, f0, K)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_converged_iteration_equals_fully_implicit_solve(orc):
+    rng = np.random.default_rng(3)
+    spec = {
+        "dim": 2, "n_cells": [8, 4, 1], "sub_cells": [2, 2, 1], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": 1, "m": 1, "law": 0, "law_params": [0.0, 0.0],
+        "n_vel": 1, "vel": [1.0, 0.6], "omega": 1.0, "dt": 0.2, "theta": 0.5, "n_iter": 80,
+    }
+    cfg = orc.Config(spec)
+    f0 = rng.normal(size=(cfg.ncell, cfg.nn))
+    got = orc.transport(cfg, 0, f0)
+    ref = bf.global_transport(orc, cfg, 0, f0, 1, lagged=False)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_aligned_chain_exact_after_nsub_iterations(orc):
+    """For V along x, one x-row split in n_s subdomains: the Jacobi iteration
+    only moves information downwind by one subdomain per iterate.  With the
+    periodic wrap lagged, iterate K differs from iterate K+1 only through the
+    wrap; at fixed inputs iterate n_s+1 and n_s+2 agree to within G^{n_s}."""
+    rng = np.random.default_rng(5)
+    base = spec1d(N=12, S=3, p=1, nu=0.8, K=4)
+    f0 = rng.normal(size=(12, 2))
+    outs = []
+    for K in (4, 5, 6, 30):
+        s = dict(base, n_iter=K)
+        outs.append(orc.transport(orc.Config(s), 0, f0))
+    d1 = np.max(np.abs(outs[0] - outs[3]))
+    d2 = np.max(np.abs(outs[1] - outs[3]))
+    d3 = np.max(np.abs(outs[2] - outs[3]))
+    assert d1 > d2 > d3  # geometric convergence towards the implicit solution
+
+
+def test_axis_aligned_transport_decouples_into_lines(orc):
+    """For V = +-lambda e_x the 3-D transport equals the 1-D transport of every
+    x-line (same cell size, subdomain split along x) -- no coupling through
+    faces with V.N = 0."""
+    rng = np.random.default_rng(11)
+    N, S, p = [6, 3, 2], [3, 3, 1], 2
+    spec3 = {
+        "dim": 3, "n_cells": N, "sub_cells": S, "box_lo": [0.0] * 3, "box_hi": [1.0] * 3,
+        "degree": p, "m": 1, "law": 0, "law_params": [0.0] * 3, "n_vel": 2,
+        "vel": [2.0, 0.0, 0.0, -2.0, 0.0, 0.0], "omega": 1.0, "dt": 0.3, "theta": 0.5, "n_iter": 3,
+    }
+    c3 = orc.Config(spec3)
+    f0 = rng.normal(size=(c3.ncell, c3.nn))
+    P = p + 1
+    spec1 = {
+        "dim": 1, "n_cells": [6, 1, 1], "sub_cells": [3, 1, 1], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": p, "m": 1, "law": 0, "law_params": [0.0], "n_vel": 2,
+        "vel": [2.0, -2.0], "omega": 1.0, "dt": 0.3, "theta": 0.5, "n_iter": 3,
+    }
+    c1 = orc.Config(spec1)
+    for k in (0, 1):
+        out3 = orc.transport(c3, k, f0).reshape(N[2], N[1], N[0], P, P, P)
+        f03 = f0.reshape(N[2], N[1], N[0], P, P, P)
+        for cz in range(N[2]):
+            for cy in range(N[1]):
+                for nz in range(P):
+                    for ny in range(P):
+                        line = f03[cz, cy, :, nz, ny, :]
+                        out1 = orc.transport(c1, k, line)
+                        assert np.max(np.abs(out1 - out3[cz, cy, :, nz, ny, :])) < 1e-14
+
+
+def test_translation_by_one_subdomain_is_exact(orc):
+    rng = np.random.default_rng(2)
+    spec = {
+        "dim": 2, "n_cells": [8, 6, 1], "sub_cells": [4, 3, 1], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": 1, "m": 1, "law": 0, "law_params": [0.0, 0.0],
+        "n_vel": 1, "vel": [1.0, -0.5], "omega": 1.0, "dt": 0.4, "theta": 0.5, "n_iter": 3,
+    }
+    cfg = orc.Config(spec)
+    f0 = rng.normal(size=(6, 8, 4))
+    out = orc.transport(cfg, 0, f0.reshape(48, 4)).reshape(6, 8, 4)
+    f0s = np.roll(np.roll(f0, 4, axis=1), 3, axis=0)
+    outs = orc.transport(cfg, 0, f0s.reshape(48, 4)).reshape(6, 8, 4)
+    assert np.array_equal(outs, np.roll(np.roll(out, 4, axis=1), 3, axis=0))
+
+
+def test_converged_transport_conserves_and_is_l2_nonexpansive(orc):
+    """Converged implicit upwind DG (theta in [1/2, 1]) is conservative and
+    non-expansive in the lumped-mass norm at any CFL."""
+    rng = np.random.default_rng(4)
+    for p in (1, 2, 3):
+        for nu in (0.5, 20.0):
+            for th in (0.5, 1.0):
+                spec = spec1d(N=10, S=5, p=p, nu=nu, theta=th, K=80 if nu < 1 else 1500)
+                cfg = orc.Config(spec)
+                _, w = orc.gl(p)
+                f0 = rng.normal(size=(10, p + 1))
+                f1 = orc.transport(cfg, 0, f0)
+                assert abs(np.sum(f1 * w) - np.sum(f0 * w)) < 1e-12 * np.sum(np.abs(f0))
+                assert np.sum(f1 ** 2 * w) <= np.sum(f0 ** 2 * w) * (1 + 1e-13)
+
+
+# -------------------------------------------------------- equilibria / flux
+
+def _d3q4_from_golden():
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "d3q4_maxwell.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, *nums = line.split()
+        vals[key] = nums
+    lam = eval(vals["lambda"][0], {"sqrt": math.sqrt})
+    V = np.array([[float(x) for x in vals["V%d" % k]] for k in range(4)]) * lam
+    return lam, V
+
+
+def _maxwell_params():
+    # Q(W, N) = (-N x H, N x E): Q^i = A^i W with W = (E, H)
+    A = np.zeros((3, 6, 6))
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        for col in range(3):
+            u = np.zeros(3)
+            u[col] = 1.0
+            A[i, 0:3, 3 + col] = -np.cross(e, u)
+            A[i, 3:6, col] = np.cross(e, u)
+    return A
+
+
+def test_d3q4_min_norm_equilibrium_is_papers_formula(orc):
+    lam, V = _d3q4_from_golden()
+    A = _maxwell_params()
+    spec = {
+        "dim": 3, "n_cells": [2, 2, 2], "sub_cells": [2, 2, 2], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": 1, "m": 6, "law": 0, "law_params": A.ravel().tolist(),
+        "n_vel": 4, "vel": V.ravel().tolist(), "omega": 1.0, "dt": 0.1, "theta": 0.5, "n_iter": 3,
+    }
+    cfg = orc.Config(spec)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        W = rng.normal(size=6)
+        M = orc.equilibrium(cfg, W)
+        E, H = W[:3], W[3:]
+        for k in range(4):
+            QV = np.concatenate([-np.cross(V[k], H), np.cross(V[k], E)])
+            assert np.allclose(M[k], W / 4 + QV / (4 * lam * lam), atol=1e-14)
+
+
+@pytest.mark.parametrize("cfgid", [1, 2, 3])
+def test_equilibrium_moment_conditions(orc, cfgid):
+    spec, W0 = wl.make_workload(cfgid, n_cells=[4, 4, 4][: (2 if cfgid < 3 else 3)],
+                                sub_cells=[2, 2, 2][: (2 if cfgid < 3 else 3)])
+    cfg = orc.Config(spec)
+    d = spec["dim"]
+    V = np.asarray(spec["vel"]).reshape(-1, d)
+    for W in W0.reshape(-1, spec["m"])[::7]:
+        M = orc.equilibrium(cfg, W)
+        Q = orc.flux(cfg, W)
+        assert np.allclose(M.sum(0), W, atol=1e-13)
+        for i in range(d):
+            assert np.allclose((V[:, i:i + 1] * M).sum(0), Q[i], atol=1e-13)
+        if cfgid < 3:  # D2Q4 closed form: M_{+-i} = W/4 +- Q^i/(2 lambda)
+            lam = spec["lam"]
+            for k in range(4):
+                ax, sg = divmod(k, 2)
+                assert np.allclose(M[k], W / 4 + (1 - 2 * sg) * Q[ax] / (2 * lam), atol=1e-14)
+
+
+def test_euler_flux_textbook(orc):
+    spec, _ = wl.make_workload(3, n_cells=[2, 2, 2], sub_cells=[2, 2, 2])
+    cfg = orc.Config(spec)
+    g = 1.4
+    rho, u, pr = 1.3, np.array([0.2, -0.4, 0.1]), 0.9
+    E = pr / (g - 1) + 0.5 * rho * u @ u
+    W = np.concatenate([[rho], rho * u, [E]])
+    Q = orc.flux(cfg, W)
+    for i in range(3):
+        exp = np.concatenate([[rho * u[i]], rho * u[i] * u + pr * np.eye(3)[i], [(E + pr) * u[i]]])
+        assert np.allclose(Q[i], exp, atol=1e-14)
+    # Jacobian eigenvalues in direction x: u - c, u (x3), u + c
+    J = np.zeros((5, 5))
+    eps = 1e-7
+    for j in range(5):
+        dW = np.zeros(5)
+        dW[j] = eps
+        J[:, j] = (orc.flux(cfg, W + dW)[0] - orc.flux(cfg, W - dW)[0]) / (2 * eps)
+    ev = np.sort(np.real(np.linalg.eigvals(J)))
+    c = math.sqrt(g * pr / rho)
+    assert np.allclose(ev, sorted([u[0] - c, u[0], u[0], u[0], u[0] + c]), atol=1e-6)
+
+
+# ----------------------------------------------------------- relaxation
+
+def test_relaxation_identities(orc):
+    """Sum_k F+ = W (W continuous in time); omega = 1 gives Y+ = 0; omega = 2
+    gives Y+ = -Y- (flux error Y of eq:def_Z_and_Y, Sec. 2.4)."""
+    spec, W0 = wl.make_workload(3, n_cells=[2, 2, 2], sub_cells=[2, 2, 2])
+    d, m = 3, 5
+    V = np.asarray(spec["vel"]).reshape(-1, d)
+    rng = np.random.default_rng(9)
+    for omega in (1.0, 1.9, 2.0):
+        s = dict(spec, omega=omega)
+        cfg = orc.Config(s)
+        F = orc.init(cfg, W0)
+        F = F + 0.01 * rng.normal(size=F.shape)   # a non-equilibrium kinetic state
+        W = orc.moments(cfg, F)
+        Fp = orc.relax(cfg, F)
+        assert np.allclose(orc.moments(cfg, Fp), W, rtol=0, atol=1e-13)
+        # flux errors at one node
+        node = (5, 3)
+        fk = F[:, :, node[0], node[1]]
+        fkp = Fp[:, :, node[0], node[1]]
+        M = orc.equilibrium(cfg, W[node[0], node[1]])
+        Ym = np.einsum("ki,kc->ic", V, fk - M)
+        Yp = np.einsum("ki,kc->ic", V, fkp - M)
+        if omega == 1.0:
+            assert np.max(np.abs(Yp)) < 1e-12
+        if omega == 2.0:
+            assert np.allclose(Yp, -Ym, atol=1e-12)
+
+
+# ---------------------------------------------------------- whole scheme
+
+def _advection_error(orc, N, omega, p=1, beta=2.0, T=0.5, a=0.5, lam=1.0):
+    h = 1.0 / N
+    dt = beta * (h / 2) / a        # eq:def_CFL with h_min = h / (2 d), d = 1
+    nsteps = int(round(T / dt))
+    dt = T / nsteps
+    spec = {
+        "dim": 1, "n_cells": [N, 1, 1], "sub_cells": [N // 4, 1, 1], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": p, "m": 1, "law": 0, "law_params": [a],
+        "n_vel": 2, "vel": [lam, -lam], "omega": omega, "dt": dt, "theta": 0.5, "n_iter": 3,
+    }
+    X = wl.node_coords(spec)
+    W0 = np.sin(2 * np.pi * X[..., 0])[..., None]
+    F, W = orc.run(spec, W0, nsteps)
+    exact = np.sin(2 * np.pi * (X[..., 0] - a * T))
+    _, w = orc.gl(p)
+    return math.sqrt(np.sum((W[..., 0] - exact) ** 2 * w[None, :]) * h)
+
+
+def test_convergence_orders_advection(orc):
+    """omega = 2 is second order, omega = 1 first order (Sec. 2.2/2.4); the
+    kinetic scheme converges to the exact translate W0(x - a t)."""
+    e2 = [_advection_error(orc, N, 2.0) for N in (32, 64, 128)]
+    e1 = [_advection_error(orc, N, 1.0) for N in (32, 64, 128)]
+    s2 = [math.log2(e2[i] / e2[i + 1]) for i in range(2)]
+    s1 = [math.log2(e1[i] / e1[i + 1]) for i in range(2)]
+    assert min(s2) > 1.8, s2
+    assert 0.8 < s1[-1] < 1.3, s1
+
+
+def test_full_step_conserves_w_in_converged_regime(orc):
+    """Config-1 family (one subdomain): the lagged wrap decays like g^S, so the
+    weighted sum of W is conserved to rounding over all steps."""
+    spec, W0 = wl.make_workload(1)
+    F, W = orc.run(spec, W0, 20, threads=4)
+    _, w = orc.gl(1)
+    ww = np.kron(w, w)
+    m0 = np.sum(W0[..., 0] * ww)
+    m1 = np.sum(W[..., 0] * ww)
+    assert abs(m1 - m0) < 1e-12 * np.sum(np.abs(W0[..., 0] * ww))
+
+
+def test_subdomain_iteration_stability_K1_vs_K3(orc):
+    """Analogue of the unit-cube experiment of Sec. 5.2 (fig:iterative-stability):
+    at a large time step (kinetic Courant number 8 = subdomain width) with 16
+    subdomains, one or two iterations blow up while three stay bounded."""
+    spec, W0 = wl.make_workload(2, n_cells=[32, 32], sub_cells=[8, 8], beta=16.0, omega=1.9, degree=2)
+    assert abs(spec["kinetic_courant"] - 8.0) < 1e-12
+    growth = {}
+    for K in (1, 2, 3):
+        s = dict(spec, n_iter=K)
+        F, W = orc.run(s, W0, 100, threads=8)
+        growth[K] = np.max(np.abs(W)) / np.max(np.abs(W0))
+    assert growth[1] > 1e6, growth
+    assert growth[2] > 10.0, growth
+    assert growth[3] < 1.0, growth
