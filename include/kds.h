@@ -1,0 +1,168 @@
+/* kds.h -- C ABI of libkds, the MI355X (gfx950) kinetic DG time step.
+ *
+ * Method: Gerhard, Helluy, Michel-Dansac, Weber, "Parallel kinetic schemes
+ * for conservation laws, with large time steps" (arXiv:2212.11010).
+ *
+ *   A system of m conservation laws in d dimensions (Sec. 2.1, eq:conslaw) is
+ *   represented by n_vel vectorial kinetic functions F_k transported at
+ *   constant velocities V_k, with W = sum_k F_k and equilibria M_k(W) that
+ *   satisfy the moment conditions (eq:maxwell_def).  One time step (Sec. 2.2)
+ *   transports every F_k for dt with the implicit upwind DG scheme (Sec. 3.1,
+ *   eq:dg_imp; theta-scheme, Crank-Nicolson by default), solved by downwind
+ *   sweeps inside subdomains (Sec. 3.2) coupled by the iterative subdomain
+ *   algorithm of Sec. 5.1 (eq:ibvp, n_iter iterations), and then applies the
+ *   over-relaxation F_k <- F_k + omega (M_k(W) - F_k) (eq:over_relaxation).
+ *
+ * Discretisation: periodic Cartesian box, n_cells[a] uniform cells per axis,
+ * tensor Gauss-Lobatto nodal basis of degree p ((p+1)^d nodes per cell),
+ * collocated Gauss-Lobatto quadrature.  Subdomains are boxes of sub_cells[a]
+ * cells.  Periodic wrap faces are always subdomain interfaces.
+ *
+ * Conventions for every call:
+ *   - Status codes only; no exception or abort crosses the ABI.  After an
+ *     error, kds_last_error() returns a message (for kds_create failures,
+ *     call kds_last_error(NULL): a thread-local message).
+ *   - Input arrays are read during the call; the caller keeps ownership.
+ *     Output arrays are caller-allocated.
+ *   - on_device = 1: the pointer is device memory on the problem's GPU, and
+ *     the transfer is ordered on the problem's stream (the call returns after
+ *     the stream has finished with the buffer).  on_device = 0: host memory.
+ *   - Cells are numbered x-fastest; nodes inside a cell x-fastest; the
+ *     component index is the fastest in W, F arrays.
+ *   - A problem is not thread safe; distinct problems are independent.
+ *   - The library allocates its own device memory (hipMalloc) in kds_create
+ *     and frees it in kds_destroy.
+ */
+#ifndef KDS_H
+#define KDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kds_problem kds_problem; /* opaque, library-owned */
+
+typedef enum {
+  KDS_OK = 0,
+  KDS_E_INVALID = 1,     /* argument or configuration rejected */
+  KDS_E_NOMEM = 2,       /* device allocation failed or would not fit */
+  KDS_E_DEVICE = 3,      /* a HIP runtime call failed */
+  KDS_E_STATE = 4,       /* call out of order (e.g. step before set_state) */
+  KDS_E_NONFINITE = 5,   /* NaN/Inf found by kds_check_finite */
+  KDS_E_UNSUPPORTED = 6  /* valid for the method, not implemented here */
+} kds_status;
+
+typedef enum {
+  KDS_LAW_LINEAR = 0, /* Q^i(W) = A^i W; law_params = A^1..A^d, each m*m row-major */
+  KDS_LAW_EULER = 1   /* compressible Euler, m = d + 2, W = (rho, rho u, E);
+                         law_params = {gamma} */
+} kds_law;
+
+typedef enum {
+  KDS_FP64 = 0,            /* transport and storage in FP64 */
+  KDS_FP32 = 1,            /* transport and storage in FP32; W and M_k in FP64 */
+  KDS_FP32_SPLIT_F16 = 2,  /* reserved (returns KDS_E_UNSUPPORTED) */
+  KDS_FP32_SPLIT_BF16 = 3  /* reserved (returns KDS_E_UNSUPPORTED) */
+} kds_prec;
+
+typedef enum {
+  KDS_SCHED_AUTO = 0,  /* the line schedule when the shape allows it, else plain */
+  KDS_SCHED_PLAIN = 1, /* literal sweep: one launch per subdomain iteration,
+                          one thread per (velocity, component, line, subdomain)
+                          walking its cells in downwind order */
+  KDS_SCHED_LINE = 2   /* all n_iter subdomain iterations of a whole grid line
+                          resolved in one pass by one wavefront (exact
+                          reformulation, see kds_step) */
+} kds_schedule;
+
+typedef struct {
+  int32_t dim;           /* d = 1, 2 or 3 */
+  int32_t n_cells[3];    /* cells per axis (entries beyond dim ignored) */
+  int32_t sub_cells[3];  /* subdomain size in cells; must divide n_cells */
+  int32_t periodic[3];   /* must be 1 on every used axis (periodic box) */
+  double box_lo[3];
+  double box_hi[3];
+  int32_t degree;        /* p = 0..3; p = 0 is the finite-volume limit */
+  int32_t m;             /* conserved components, 1..8 */
+  int32_t law;           /* kds_law */
+  const double* law_params;
+  int32_t n_law_params;
+  int32_t n_vel;         /* kinetic velocities, 1..8 */
+  const double* vel;     /* n_vel * dim; each must be parallel to an axis */
+  const double* eq_a;    /* n_vel weights, or NULL (see below) */
+  const double* eq_b;    /* n_vel * dim weights, or NULL */
+  double omega;          /* relaxation parameter, 0 <= omega <= 2 (Sec. 2.2) */
+  double dt;             /* time step, > 0 */
+  double theta;          /* 1/2 = Crank-Nicolson, 1 = implicit Euler; in [1/2, 1] */
+  int32_t n_iter;        /* subdomain iterations K >= 1 (Sec. 5.1) */
+  int32_t precision;     /* kds_prec */
+  int32_t schedule;      /* kds_schedule */
+} kds_config;
+/* Equilibria (eq:maxwell_def): M_k(W) = eq_a[k] W + sum_i eq_b[k*dim+i] Q^i(W).
+ * With eq_a = eq_b = NULL the minimum-norm weights satisfying the moment
+ * conditions for every W are used (for +-lambda e_i: M = W/(2d) +- Q^i/(2 lambda)). */
+
+/* Validate cfg, build the FP64 operator tables on the host, allocate the
+ * kinetic state on the current HIP device.  hip_stream: a hipStream_t of that
+ * device used for all work of this problem, or NULL (the library then creates
+ * its own stream).  Errors: KDS_E_INVALID (bad config), KDS_E_UNSUPPORTED
+ * (e.g. a velocity not parallel to an axis), KDS_E_NOMEM, KDS_E_DEVICE.
+ * Configuration is checked before any device call. */
+kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out);
+
+/* Initial kinetic state F_k = M_k(W) at every node (Sec. 2.2).
+ * W: FP64 [cell][node][c].  Resets the step counter. */
+kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device);
+
+/* n_steps time steps (Sec. 2.2): transport of every F_k (K subdomain
+ * iterations of the downwind sweep, eq:dg_imp / eq:ibvp) then relaxation
+ * (eq:over_relaxation).  Launched asynchronously on the problem's stream (a
+ * captured HIP graph per step); returns KDS_E_STATE before set_state. */
+kds_status kds_step(kds_problem* p, int32_t n_steps);
+
+/* Same steps launched one kernel at a time with HIP events around each kernel;
+ * waits for completion and writes the summed milliseconds per kernel kind into
+ * kernel_ms[KDS_N_KERNEL_KINDS] (sweep, relax).  For measurement. */
+#define KDS_N_KERNEL_KINDS 2
+kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
+
+/* W = sum_k F_k (FP64, Sec. 2.2 step 3) into W_out [cell][node][c]. */
+kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device);
+
+/* Checkpoint / resume of the kinetic state (F, not W: after the first step
+ * F_k != M_k(W), Sec. 2.2 remark).  F: FP64 [k][cell][node][c]. */
+kds_status kds_get_kinetic(kds_problem* p, double* F_out, int32_t on_device);
+kds_status kds_set_kinetic(kds_problem* p, const double* F, int32_t on_device);
+
+/* Scan the kinetic state for NaN/Inf: KDS_OK or KDS_E_NONFINITE. */
+kds_status kds_check_finite(kds_problem* p);
+
+/* Wait for all work of the problem's stream. */
+kds_status kds_synchronize(kds_problem* p);
+
+typedef struct {
+  int64_t n_unknowns;     /* cells * (p+1)^d * m * n_vel */
+  int64_t state_bytes;    /* device bytes of one kinetic state */
+  int32_t schedule;       /* schedule actually used (KDS_SCHED_PLAIN / LINE) */
+  int32_t precision;
+  int32_t steps_done;
+  int32_t cells_per_lane; /* line schedule: cells per lane (0 for plain) */
+  double max_kinetic_courant; /* max_k |V_k| dt / h_axis */
+  double min_subdomain_width; /* min over used axes of sub_cells * h */
+  int32_t proposition_ok; /* 1 if |V| dt <= subdomain width (Sec. 5.1 Proposition) */
+} kds_info_t;
+kds_status kds_info(const kds_problem* p, kds_info_t* info);
+
+/* Release device memory, graph and (own) stream.  NULL is allowed. */
+void kds_destroy(kds_problem* p);
+
+/* Last error message of p, or the thread-local kds_create message if p is NULL. */
+const char* kds_last_error(const kds_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDS_H */

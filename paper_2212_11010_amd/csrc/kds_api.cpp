@@ -1,0 +1,621 @@
+// kds_api.cpp -- the C ABI of libkds (declared in include/kds.h): problem
+// creation and validation, device buffers, the captured per-step HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kds_internal.h"
+
+using namespace kds;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct kds_problem {
+  // configuration
+  int dim = 0, N[3] = {1, 1, 1}, S[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+  int degree = 0, P = 1, nn = 1, m = 0, law = 0, nv = 0;
+  std::vector<double> law_params, vel, eq_a, eq_b;
+  double omega = 1, dt = 0, theta = 0.5;
+  int K = 1, prec = KDS_FP32, sched = KDS_SCHED_PLAIN;
+  int64_t ncell = 0;
+  Geom geom{};
+  // host tables
+  std::vector<unsigned char> eq_blob;
+  std::vector<unsigned char> sweep_blob;  // SweepTab<T>
+  LinePlan plan{};
+  double max_nu = 0, min_sub_width = 0;
+  bool proposition_ok = true;
+  // device
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t elem = 4;
+  void* f = nullptr;
+  void* f_tmp = nullptr;
+  void* tr[2] = {nullptr, nullptr};
+  double* stage = nullptr;  // FP64 staging for W / F transfers
+  size_t stage_bytes = 0;
+  int* flag = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  bool state_set = false;
+  int steps_done = 0;
+  std::string err;
+
+  int64_t plane() const { return ncell * nn; }
+  int64_t n_unknowns() const { return plane() * m * nv; }
+};
+
+namespace {
+
+kds_status fail(kds_problem* p, kds_status st, const std::string& msg) {
+  if (p) p->err = msg; else g_create_error = msg;
+  return st;
+}
+
+kds_status hip_fail(kds_problem* p, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(p, KDS_E_DEVICE, msg);
+}
+
+#define KDS_HIP(p, call)                                    \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((p), e_, #call);  \
+  } while (0)
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Validation of the configuration (no device call).
+kds_status validate(const kds_config* c, std::string& msg) {
+  if (!c) { msg = "cfg is NULL"; return KDS_E_INVALID; }
+  if (c->dim < 1 || c->dim > 3) { msg = "dim must be 1, 2 or 3"; return KDS_E_INVALID; }
+  for (int a = 0; a < c->dim; ++a) {
+    if (c->n_cells[a] < 1) { msg = "n_cells must be >= 1"; return KDS_E_INVALID; }
+    if (c->sub_cells[a] < 1 || c->n_cells[a] % c->sub_cells[a] != 0) {
+      msg = "sub_cells must be >= 1 and divide n_cells on every axis";
+      return KDS_E_INVALID;
+    }
+    if (c->periodic[a] != 1) { msg = "only periodic boxes are supported (periodic[a] = 1)"; return KDS_E_UNSUPPORTED; }
+    if (!finite(c->box_lo[a]) || !finite(c->box_hi[a]) || !(c->box_hi[a] > c->box_lo[a])) {
+      msg = "box_hi must exceed box_lo";
+      return KDS_E_INVALID;
+    }
+  }
+  if (c->degree < 0 || c->degree > kMaxP - 1) { msg = "degree must be 0..3"; return KDS_E_INVALID; }
+  if (c->m < 1 || c->m > kMaxM) { msg = "m must be 1..8"; return KDS_E_INVALID; }
+  if (c->n_vel < 1 || c->n_vel > kMaxVel) { msg = "n_vel must be 1..8"; return KDS_E_INVALID; }
+  if (!c->vel) { msg = "vel is NULL"; return KDS_E_INVALID; }
+  for (int i = 0; i < c->n_vel * c->dim; ++i)
+    if (!finite(c->vel[i])) { msg = "non-finite kinetic velocity"; return KDS_E_INVALID; }
+  if (c->law == KDS_LAW_LINEAR) {
+    if (!c->law_params || c->n_law_params < c->dim * c->m * c->m) {
+      msg = "linear law needs dim*m*m parameters (A^1..A^d)";
+      return KDS_E_INVALID;
+    }
+  } else if (c->law == KDS_LAW_EULER) {
+    if (c->m != c->dim + 2) { msg = "Euler needs m = dim + 2"; return KDS_E_INVALID; }
+    if (!c->law_params || c->n_law_params < 1 || !(c->law_params[0] > 1.0)) {
+      msg = "Euler needs law_params = {gamma > 1}";
+      return KDS_E_INVALID;
+    }
+  } else {
+    msg = "unknown law";
+    return KDS_E_INVALID;
+  }
+  if (!(c->omega >= 0.0 && c->omega <= 2.0)) { msg = "omega must be in [0, 2]"; return KDS_E_INVALID; }
+  if (!(c->dt > 0.0) || !finite(c->dt)) { msg = "dt must be > 0"; return KDS_E_INVALID; }
+  if (!(c->theta >= 0.5 && c->theta <= 1.0)) { msg = "theta must be in [1/2, 1]"; return KDS_E_INVALID; }
+  if (c->n_iter < 0) { msg = "n_iter must be >= 1"; return KDS_E_INVALID; }
+  if (c->n_iter == 0) { msg = "n_iter = 0 (iterate to convergence) is not implemented"; return KDS_E_UNSUPPORTED; }
+  if (c->precision == KDS_FP32_SPLIT_F16 || c->precision == KDS_FP32_SPLIT_BF16) {
+    msg = "split-precision storage is not implemented";
+    return KDS_E_UNSUPPORTED;
+  }
+  if (c->precision != KDS_FP64 && c->precision != KDS_FP32) { msg = "unknown precision"; return KDS_E_INVALID; }
+  if (c->schedule < KDS_SCHED_AUTO || c->schedule > KDS_SCHED_LINE) { msg = "unknown schedule"; return KDS_E_INVALID; }
+  for (int k = 0; k < c->n_vel; ++k) {
+    int nz = 0;
+    for (int a = 0; a < c->dim; ++a) nz += c->vel[k * c->dim + a] != 0.0;
+    if (nz != 1) {
+      msg = "every kinetic velocity must be parallel to one grid axis (and nonzero)";
+      return KDS_E_UNSUPPORTED;
+    }
+  }
+  return KDS_OK;
+}
+
+// Line schedule: choose the cells per lane Q (divides the subdomain width,
+// line fits one wavefront) maximising lane utilisation, and the bundle width
+// across the line for y / z sweeps.
+bool plan_lines(kds_problem* p, std::string& why) {
+  LinePlan& pl = p->plan;
+  std::memset(&pl, 0, sizeof(pl));
+  int max_lds = 0;
+  int max_waves = 1;
+  const int lds_cap = 48 * 1024 / (int)p->elem;
+  for (int k = 0; k < p->nv; ++k) {
+    int ax = 0;
+    for (int d = 0; d < p->dim; ++d)
+      if (p->vel[k * p->dim + d] != 0.0) ax = d;
+    const int Na = p->N[ax], S = p->S[ax];
+    int bestQ = 0;
+    double bestU = -1;
+    for (int Q = 1; Q <= kMaxQ; ++Q) {
+      if (S % Q) continue;
+      const int NL = Na / Q;
+      if (NL > 64) continue;
+      int l2 = 1;
+      while (l2 < NL) l2 <<= 1;
+      const double util = (double)NL / l2;
+      if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
+    }
+    if (!bestQ) {
+      why = "line schedule needs a cells-per-lane count Q <= 8 dividing the subdomain width with n_cells/Q <= 64";
+      return false;
+    }
+    const int NL = Na / bestQ;
+    int l2 = 1;
+    while (l2 < NL) l2 <<= 1;
+    pl.Q[k] = bestQ;
+    pl.lpl2[k] = l2;
+    int bw = 1;
+    if (ax != 0) {
+      // contiguous run of at least 256 bytes per row when the LDS allows
+      while (bw < p->N[0] && bw * p->nn * (int)p->elem < 256 && Na * (bw + 1) * p->nn <= lds_cap) ++bw;
+    }
+    pl.bw[k] = bw;
+    const int R = (ax == 0 ? 1 : bw) * p->nn;
+    if (Na * R > lds_cap) {
+      why = "line schedule: one bundle of lines does not fit the LDS budget";
+      return false;
+    }
+    max_lds = std::max(max_lds, Na * R);
+    const int lines = (ax == 0 ? 1 : bw) * (p->nn / p->P);
+    const int lw = 64 / l2;
+    max_waves = std::max(max_waves, std::min(4, (lines + lw - 1) / lw));
+  }
+  pl.lds_elems = max_lds;
+  pl.threads = 64 * max_waves;
+  int64_t acc = 0;
+  for (int k = 0; k < p->nv; ++k) {
+    int ax = 0;
+    for (int d = 0; d < p->dim; ++d)
+      if (p->vel[k * p->dim + d] != 0.0) ax = d;
+    int64_t nb;
+    if (ax == 0) nb = p->ncell / p->N[0];
+    else nb = (int64_t)((p->N[0] + pl.bw[k] - 1) / pl.bw[k]) * (p->ncell / p->N[0] / p->N[ax]);
+    for (int c = 0; c < p->m; ++c) {
+      pl.block_start[k * p->m + c] = acc;
+      acc += nb;
+    }
+  }
+  pl.block_start[p->nv * p->m] = acc;
+  if (acc > 0x7fffffffLL) { why = "line schedule: grid too large"; return false; }
+  return true;
+}
+
+template <typename T>
+void fill_sweep_tab(kds_problem* p, const Basis1D& basis) {
+  SweepTab<T> t;
+  std::memset(&t, 0, sizeof(t));
+  for (int k = 0; k < p->nv; ++k) {
+    int ax = 0;
+    double v = 0;
+    for (int d = 0; d < p->dim; ++d)
+      if (p->vel[k * p->dim + d] != 0.0) { ax = d; v = p->vel[k * p->dim + d]; }
+    const double nu = std::fabs(v) * p->dt / p->h[ax];
+    LineOp op = make_line_op(basis, nu, p->theta);
+    t.axis[k] = ax;
+    t.sign[k] = v > 0 ? 1 : -1;
+    for (int i = 0; i < p->P * p->P; ++i) t.C[k][i] = (T)op.C[i];
+    for (int i = 0; i < p->P; ++i) {
+      t.e1[k][i] = (T)((1.0 - p->theta) * op.e[i]);
+      t.eth[k][i] = (T)(p->theta * op.e[i]);
+    }
+  }
+  p->sweep_blob.resize(sizeof(t));
+  std::memcpy(p->sweep_blob.data(), &t, sizeof(t));
+}
+
+void free_device(kds_problem* p) {
+  if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  for (auto& e : p->ev)
+    if (e) { hipEventDestroy(e); e = nullptr; }
+  void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
+  p->stage = nullptr;
+  p->flag = nullptr;
+  if (p->own_stream && p->stream) hipStreamDestroy(p->stream);
+  p->stream = nullptr;
+}
+
+// Enqueue one time step (transport then relaxation) on the problem's stream.
+// With events, records ev[0] before the transport, ev[1] between transport and
+// relaxation, ev[2] after.
+kds_status enqueue_step(kds_problem* p, bool events) {
+  const Geom& g = p->geom;
+  if (events) KDS_HIP(p, hipEventRecord(p->ev[0], p->stream));
+  if (p->sched == KDS_SCHED_LINE) {
+    KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream));
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream));
+  } else {
+    for (int it = 1; it <= p->K; ++it) {
+      const void* tr_prev = it == 1 ? nullptr : p->tr[(it - 1) & 1];
+      void* f_new = it == p->K ? p->f_tmp : nullptr;
+      KDS_HIP(p, launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, f_new, tr_prev,
+                                    p->tr[it & 1], p->stream));
+    }
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f_tmp, p->f, p->stream));
+  }
+  if (events) KDS_HIP(p, hipEventRecord(p->ev[2], p->stream));
+  return KDS_OK;
+}
+
+kds_status ensure_graph(kds_problem* p) {
+  if (p->graph_exec) return KDS_OK;
+  KDS_HIP(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  kds_status st = enqueue_step(p, false);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &graph);
+  if (st != KDS_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(p, e, "hipStreamEndCapture");
+  p->graph = graph;
+  KDS_HIP(p, hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  return KDS_OK;
+}
+
+kds_status check_device_ptr(kds_problem* p, const void* ptr) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, KDS_E_INVALID, "on_device = 1 but the pointer is not HIP memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(p, KDS_E_INVALID, "on_device = 1 but the pointer is not device memory");
+  if (attr.type == hipMemoryTypeDevice && attr.device != p->device)
+    return fail(p, KDS_E_INVALID, "device pointer belongs to another GPU");
+  return KDS_OK;
+}
+
+kds_status ensure_stage(kds_problem* p, size_t bytes) {
+  if (p->stage_bytes >= bytes) return KDS_OK;
+  if (p->stage) hipFree(p->stage);
+  p->stage = nullptr;
+  p->stage_bytes = 0;
+  hipError_t e = hipMalloc((void**)&p->stage, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, KDS_E_NOMEM, "staging buffer allocation failed");
+  }
+  p->stage_bytes = bytes;
+  return KDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, KDS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  kds_status st = validate(cfg, msg);
+  if (st != KDS_OK) return fail(nullptr, st, msg);
+
+  kds_problem* p = new kds_problem();
+  p->dim = cfg->dim;
+  p->ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    p->N[a] = a < cfg->dim ? cfg->n_cells[a] : 1;
+    p->S[a] = a < cfg->dim ? cfg->sub_cells[a] : 1;
+    p->lo[a] = a < cfg->dim ? cfg->box_lo[a] : 0.0;
+    p->hi[a] = a < cfg->dim ? cfg->box_hi[a] : 1.0;
+    p->h[a] = (p->hi[a] - p->lo[a]) / p->N[a];
+    p->ncell *= p->N[a];
+  }
+  p->degree = cfg->degree;
+  p->P = cfg->degree + 1;
+  p->nn = 1;
+  for (int a = 0; a < p->dim; ++a) p->nn *= p->P;
+  p->m = cfg->m;
+  p->law = cfg->law;
+  p->nv = cfg->n_vel;
+  p->law_params.assign(cfg->law_params, cfg->law_params + cfg->n_law_params);
+  p->vel.assign(cfg->vel, cfg->vel + cfg->n_vel * cfg->dim);
+  p->omega = cfg->omega;
+  p->dt = cfg->dt;
+  p->theta = cfg->theta;
+  p->K = cfg->n_iter;
+  p->prec = cfg->precision;
+  p->elem = p->prec == KDS_FP64 ? 8 : 4;
+
+  std::vector<double> a, b;
+  if (!eq_weights(p->dim, p->nv, p->vel.data(), cfg->eq_a, cfg->eq_b, a, b, msg)) {
+    delete p;
+    return fail(nullptr, KDS_E_INVALID, msg);
+  }
+  if (!build_eq_blob(p->law, p->dim, p->m, p->nv, p->law_params, a, b, p->omega, p->eq_blob)) {
+    delete p;
+    return fail(nullptr, KDS_E_UNSUPPORTED,
+                "no compiled relaxation kernel for this (law, dim, m, n_vel) combination");
+  }
+  Basis1D basis = make_basis(p->degree);
+  if (p->prec == KDS_FP64) fill_sweep_tab<double>(p, basis);
+  else fill_sweep_tab<float>(p, basis);
+
+  Geom& g = p->geom;
+  g.dim = p->dim;
+  for (int ax = 0; ax < 3; ++ax) { g.N[ax] = p->N[ax]; g.S[ax] = p->S[ax]; }
+  g.P = p->P;
+  g.nn = p->nn;
+  g.ncell = p->ncell;
+  g.m = p->m;
+  g.nv = p->nv;
+  g.K = p->K;
+  g.tr_stride = 0;
+  p->max_nu = 0;
+  p->min_sub_width = 1e300;
+  for (int k = 0; k < p->nv; ++k) {
+    for (int ax = 0; ax < p->dim; ++ax) {
+      double v = std::fabs(p->vel[k * p->dim + ax]);
+      if (v == 0.0) continue;
+      double nu = v * p->dt / p->h[ax];
+      p->max_nu = std::max(p->max_nu, nu);
+      // Sec. 5.1 Proposition: |V| dt <= subdomain diameter along the velocity
+      if (v * p->dt > p->S[ax] * p->h[ax] * (1 + 1e-12)) p->proposition_ok = false;
+      int64_t lines = (p->ncell / p->N[ax]) * (p->nn / p->P) * (p->N[ax] / p->S[ax]);
+      g.tr_stride = std::max<int64_t>(g.tr_stride, lines);
+    }
+  }
+  for (int ax = 0; ax < p->dim; ++ax) p->min_sub_width = std::min(p->min_sub_width, p->S[ax] * p->h[ax]);
+
+  std::string why;
+  const bool line_ok = plan_lines(p, why);
+  if (cfg->schedule == KDS_SCHED_LINE && !line_ok) {
+    delete p;
+    return fail(nullptr, KDS_E_UNSUPPORTED, why);
+  }
+  p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok) ? KDS_SCHED_PLAIN : KDS_SCHED_LINE;
+
+  // ---------------------------------------------------------------- device
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(nullptr, KDS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  const size_t state_bytes = (size_t)p->n_unknowns() * p->elem;
+  size_t need = state_bytes;
+  if (p->sched == KDS_SCHED_PLAIN) need += state_bytes + 2 * (size_t)g.tr_stride * p->nv * p->m * p->elem;
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(nullptr, KDS_E_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+  }
+  if (need + (64u << 20) > free_b) {
+    delete p;
+    return fail(nullptr, KDS_E_NOMEM, "the kinetic state does not fit the free device memory");
+  }
+  auto alloc = [&](void** ptr, size_t bytes) -> bool {
+    hipError_t ee = hipMalloc(ptr, bytes);
+    if (ee != hipSuccess) { (void)hipGetLastError(); *ptr = nullptr; return false; }
+    return true;
+  };
+  bool ok = alloc(&p->f, state_bytes) && alloc((void**)&p->flag, sizeof(int));
+  if (ok && p->sched == KDS_SCHED_PLAIN) {
+    const size_t trb = std::max<size_t>(1, (size_t)g.tr_stride * p->nv * p->m * p->elem);
+    ok = alloc(&p->f_tmp, state_bytes) && alloc(&p->tr[0], trb) && alloc(&p->tr[1], trb);
+  }
+  if (!ok) {
+    free_device(p);
+    delete p;
+    return fail(nullptr, KDS_E_NOMEM, "device allocation failed");
+  }
+  if (hip_stream) {
+    p->stream = (hipStream_t)hip_stream;
+    p->own_stream = false;
+  } else {
+    // a blocking stream: ordered after work on the legacy default stream
+    e = hipStreamCreate(&p->stream);
+    if (e != hipSuccess) {
+      free_device(p);
+      delete p;
+      return fail(nullptr, KDS_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    p->own_stream = true;
+  }
+  for (auto& ev : p->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      free_device(p);
+      delete p;
+      return fail(nullptr, KDS_E_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+  }
+  if (p->sched == KDS_SCHED_LINE && (size_t)p->plan.lds_elems * p->elem > 64 * 1024) {
+    free_device(p);
+    delete p;
+    return fail(nullptr, KDS_E_UNSUPPORTED, "line schedule LDS tile too large");
+  }
+  *out = p;
+  return KDS_OK;
+}
+
+kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!W) return fail(p, KDS_E_INVALID, "W is NULL");
+  const size_t bytes = (size_t)p->plane() * p->m * sizeof(double);
+  const double* src = W;
+  if (on_device) {
+    kds_status st = check_device_ptr(p, W);
+    if (st != KDS_OK) return st;
+  } else {
+    kds_status st = ensure_stage(p, bytes);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, hipMemcpyAsync(p->stage, W, bytes, hipMemcpyHostToDevice, p->stream));
+    src = p->stage;
+  }
+  KDS_HIP(p, launch_init(p->prec, p->law, p->geom, p->eq_blob.data(), src, p->f, p->stream));
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  p->state_set = true;
+  p->steps_done = 0;
+  return KDS_OK;
+}
+
+kds_status kds_step(kds_problem* p, int32_t n_steps) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (n_steps < 0) return fail(p, KDS_E_INVALID, "n_steps must be >= 0");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step before kds_set_state / kds_set_kinetic");
+  if (n_steps == 0) return KDS_OK;
+  kds_status st = ensure_graph(p);
+  if (st != KDS_OK) return st;
+  for (int i = 0; i < n_steps; ++i) KDS_HIP(p, hipGraphLaunch(p->graph_exec, p->stream));
+  p->steps_done += n_steps;
+  return KDS_OK;
+}
+
+kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (n_steps < 0 || !kernel_ms) return fail(p, KDS_E_INVALID, "bad arguments");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step_timed before kds_set_state");
+  double acc[KDS_N_KERNEL_KINDS] = {0, 0};
+  for (int i = 0; i < n_steps; ++i) {
+    kds_status st = enqueue_step(p, true);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, hipEventSynchronize(p->ev[2]));
+    float t01 = 0, t12 = 0;
+    KDS_HIP(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
+    KDS_HIP(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
+    acc[0] += t01;
+    acc[1] += t12;
+  }
+  p->steps_done += n_steps;
+  for (int i = 0; i < KDS_N_KERNEL_KINDS; ++i) kernel_ms[i] = acc[i];
+  return KDS_OK;
+}
+
+kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!W_out) return fail(p, KDS_E_INVALID, "W_out is NULL");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_moments before kds_set_state");
+  const size_t bytes = (size_t)p->plane() * p->m * sizeof(double);
+  if (on_device) {
+    kds_status st = check_device_ptr(p, W_out);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, launch_moments(p->prec, p->geom, p->f, W_out, p->stream));
+    KDS_HIP(p, hipStreamSynchronize(p->stream));
+  } else {
+    kds_status st = ensure_stage(p, bytes);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, launch_moments(p->prec, p->geom, p->f, p->stage, p->stream));
+    KDS_HIP(p, hipMemcpyAsync(W_out, p->stage, bytes, hipMemcpyDeviceToHost, p->stream));
+    KDS_HIP(p, hipStreamSynchronize(p->stream));
+  }
+  return KDS_OK;
+}
+
+kds_status kds_get_kinetic(kds_problem* p, double* F_out, int32_t on_device) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!F_out) return fail(p, KDS_E_INVALID, "F_out is NULL");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_get_kinetic before kds_set_state");
+  const size_t bytes = (size_t)p->n_unknowns() * sizeof(double);
+  if (on_device) {
+    kds_status st = check_device_ptr(p, F_out);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, launch_get_kinetic(p->prec, p->geom, p->f, F_out, p->stream));
+  } else {
+    kds_status st = ensure_stage(p, bytes);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, launch_get_kinetic(p->prec, p->geom, p->f, p->stage, p->stream));
+    KDS_HIP(p, hipMemcpyAsync(F_out, p->stage, bytes, hipMemcpyDeviceToHost, p->stream));
+  }
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  return KDS_OK;
+}
+
+kds_status kds_set_kinetic(kds_problem* p, const double* F, int32_t on_device) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!F) return fail(p, KDS_E_INVALID, "F is NULL");
+  const size_t bytes = (size_t)p->n_unknowns() * sizeof(double);
+  const double* src = F;
+  if (on_device) {
+    kds_status st = check_device_ptr(p, F);
+    if (st != KDS_OK) return st;
+  } else {
+    kds_status st = ensure_stage(p, bytes);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, hipMemcpyAsync(p->stage, F, bytes, hipMemcpyHostToDevice, p->stream));
+    src = p->stage;
+  }
+  KDS_HIP(p, launch_set_kinetic(p->prec, p->geom, src, p->f, p->stream));
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  p->state_set = true;
+  return KDS_OK;
+}
+
+kds_status kds_check_finite(kds_problem* p) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_check_finite before kds_set_state");
+  int zero = 0, flag = 0;
+  KDS_HIP(p, hipMemcpyAsync(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  KDS_HIP(p, launch_check_finite(p->prec, p->geom, p->f, p->flag, p->stream));
+  KDS_HIP(p, hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  if (flag) return fail(p, KDS_E_NONFINITE, "kinetic state holds NaN or Inf");
+  return KDS_OK;
+}
+
+kds_status kds_synchronize(kds_problem* p) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  return KDS_OK;
+}
+
+kds_status kds_info(const kds_problem* p, kds_info_t* info) {
+  if (!p || !info) return fail(nullptr, KDS_E_INVALID, "NULL argument");
+  info->n_unknowns = p->n_unknowns();
+  info->state_bytes = (int64_t)p->n_unknowns() * (int64_t)p->elem;
+  info->schedule = p->sched;
+  info->precision = p->prec;
+  info->steps_done = p->steps_done;
+  info->cells_per_lane = p->sched == KDS_SCHED_LINE ? p->plan.Q[0] : 0;
+  info->max_kinetic_courant = p->max_nu;
+  info->min_subdomain_width = p->min_sub_width;
+  info->proposition_ok = p->proposition_ok ? 1 : 0;
+  return KDS_OK;
+}
+
+void kds_destroy(kds_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  free_device(p);
+  delete p;
+}
+
+const char* kds_last_error(const kds_problem* p) {
+  return p ? p->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

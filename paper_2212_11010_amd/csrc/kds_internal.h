@@ -1,0 +1,112 @@
+// kds_internal.h -- private declarations shared by the host setup, the
+// kernels and the C ABI of libkds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kds.h"
+
+namespace kds {
+
+constexpr int kMaxVel = 8;   // kinetic velocities
+constexpr int kMaxP = 4;     // nodes per axis (degree <= 3)
+constexpr int kMaxM = 8;     // conserved components
+constexpr int kMaxQ = 8;     // cells per lane in the line schedule
+
+// ---------------------------------------------------------------- host setup
+
+// 1-D nodal DG data on the reference cell [0, 1] (Gauss-Lobatto points).
+struct Basis1D {
+  int P = 0;                 // nodes per axis
+  std::vector<double> xi, w; // nodes, weights (sum 1)
+  std::vector<double> D;     // D[b*P + a] = l_a'(xi_b)
+};
+Basis1D make_basis(int degree);
+
+// Local (downwind-ordered) 1-D cell update for one velocity along an axis:
+//   f^n = C f^{n-1} + e ((1 - theta) t^{n-1} + theta t^n)
+// where t is the upwind neighbour's outflow node value (node P-1 of the
+// neighbour in downwind order) and node 0 is the inflow node.
+struct LineOp {
+  int P = 0;
+  double nu = 0;              // |V| dt / h
+  std::vector<double> C;      // P x P, row-major
+  std::vector<double> e;      // P
+};
+LineOp make_line_op(const Basis1D& b, double nu, double theta);
+
+// Minimum-norm equilibrium weights (a_k, b_{k,i}) or the caller's.
+bool eq_weights(int dim, int nv, const double* vel, const double* eq_a, const double* eq_b,
+                std::vector<double>& a, std::vector<double>& b, std::string& err);
+
+// ------------------------------------------------------- device parameters
+
+struct Geom {
+  int dim;
+  int N[3];
+  int S[3];
+  int P;
+  int nn;      // P^dim
+  int64_t ncell;
+  int m;
+  int nv;
+  int K;       // subdomain iterations
+  int64_t tr_stride;  // plain schedule: trace entries per (velocity, component)
+};
+
+template <typename T>
+struct SweepTab {
+  int axis[kMaxVel];
+  int sign[kMaxVel];
+  T C[kMaxVel][kMaxP * kMaxP];
+  T e1[kMaxVel][kMaxP];   // (1 - theta) e
+  T eth[kMaxVel][kMaxP];  // theta e
+};
+
+template <int D, int M, int NV>
+struct EqTab {
+  double A[D][M][M];  // linear law
+  double a[NV];
+  double b[NV][D];
+  double omega;
+  double gamma;       // Euler
+};
+
+// Line-schedule launch plan (per velocity axis).
+struct LinePlan {
+  int Q[kMaxVel];          // cells per lane
+  int lpl2[kMaxVel];       // lanes per line, power of two
+  int bw[kMaxVel];         // cells across the line per bundle (y/z axes)
+  int64_t block_start[kMaxVel * kMaxM + 1];  // prefix over (k, c) of bundles
+  int lds_elems;           // max tile elements
+  int threads;             // block size
+};
+
+// --------------------------------------------------------------- launchers
+
+
+hipError_t launch_init(int prec, int law, const Geom& g, const void* eq, const double* W,
+                       void* f, hipStream_t s);
+hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq, const void* fin,
+                        void* fout, hipStream_t s);
+hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s);
+hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s);
+hipError_t launch_set_kinetic(int prec, const Geom& g, const double* F, void* f, hipStream_t s);
+hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag, hipStream_t s);
+hipError_t launch_sweep_plain(int prec, const Geom& g, const void* tab, const void* f_old,
+                              void* f_new, const void* tr_prev, void* tr_out, hipStream_t s);
+hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const LinePlan& plan,
+                             void* f, hipStream_t s);
+
+// Equilibrium tables are built into a byte blob matching EqTab<D, M, NV> for
+// the (law, dim, m, nv) combination; returns false if the combination has no
+// compiled kernel.
+bool build_eq_blob(int law, int dim, int m, int nv, const std::vector<double>& law_params,
+                   const std::vector<double>& a, const std::vector<double>& b, double omega,
+                   std::vector<unsigned char>& blob);
+
+}  // namespace kds

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle,
+element by element, on the seeded workloads at reduced sizes that span
+several bundles, subdomains and ragged tails, plus full-size configurations
+where the oracle finishes in seconds.
+
+Tolerances (max |x_gpu - x_oracle| / max |x_oracle|, on W and on F):
+  FP64 storage: 1e-12;  FP32 storage: 1e-5 (FP32 rounding of the state at
+  every step, ~1e-7 per step, accumulated over the steps of the run).
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+MODES = [("fp64", "plain"), ("fp64", "line"), ("fp32", "plain"), ("fp32", "line")]
+
+CASES = {
+    # name: (cfg, overrides)
+    "cfg1_full": (1, {}),
+    "cfg2_ragged": (2, dict(n_cells=[42, 40], sub_cells=[14, 8], steps=6)),
+    "cfg2_q1_deg1": (2, dict(n_cells=[24, 36], sub_cells=[12, 12], degree=1, steps=5)),
+    "cfg3_small": (3, dict(n_cells=[12, 10, 8], sub_cells=[6, 5, 4], steps=3)),
+    "cfg4_small": (4, dict(n_cells=[12, 12, 6], sub_cells=[6, 4, 3], steps=2)),
+    "cfg3_k1": (3, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=2, n_iter=1)),
+    "cfg2_theta1": (2, dict(n_cells=[32, 16], sub_cells=[8, 16], steps=3, theta=1.0)),
+    "cfg2_full_2steps": (2, dict(steps=2)),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    from oracle import oracle
+    from paper_2212_11010_amd import workloads as wl
+    cfg, ov = CASES[name]
+    spec, W0 = wl.make_workload(cfg, **ov)
+    F, W = oracle.run(spec, W0, spec["steps"], threads=0)
+    Fabi = np.ascontiguousarray(F.transpose(0, 2, 3, 1))  # [k][cell][node][c]
+    return spec, W0, Fabi, W
+
+
+def run_gpu(spec, W0, prec, sched, steps=None):
+    import torch
+    from paper_2212_11010_amd import kds
+    steps = spec["steps"] if steps is None else steps
+    with kds.Problem(spec, precision=prec, schedule=sched) as pb:
+        info = pb.info()
+        assert info["schedule"] == {"plain": 1, "line": 2}[sched]
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(steps)
+        W = pb.moments()
+        F = pb.get_kinetic()
+    return W, F
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec,sched", MODES)
+def test_parity_against_oracle(name, prec, sched):
+    spec, W0, Fref, Wref = case(name)
+    print("case", name, prec, sched, spec["n_cells"], spec["sub_cells"], flush=True)
+    W, F = run_gpu(spec, W0, prec, sched)
+    ew, ef = relerr(W, Wref), relerr(F, Fref)
+    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
+    assert ew <= TOL[prec] and ef <= TOL[prec], (ew, ef)
+
+
+def test_plain_and_line_schedules_agree_fp64():
+    spec, W0, _, _ = case("cfg3_small")
+    Wp, Fp = run_gpu(spec, W0, "fp64", "plain")
+    Wl, Fl = run_gpu(spec, W0, "fp64", "line")
+    assert relerr(Fl, Fp) < 1e-13
+
+
+@pytest.mark.parametrize("sched", ["plain", "line"])
+def test_bitwise_determinism(sched):
+    spec, W0, _, _ = case("cfg2_ragged")
+    a = run_gpu(spec, W0, "fp32", sched)
+    b = run_gpu(spec, W0, "fp32", sched)
+    assert np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("sched", ["plain", "line"])
+def test_checkpoint_resume_bitwise(sched):
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, _, _ = case("cfg3_small")
+    with kds.Problem(spec, precision="fp32", schedule=sched) as pb:
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(3)
+        Fa = pb.get_kinetic()
+    with kds.Problem(spec, precision="fp32", schedule=sched) as pb:
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(1)
+        Fmid = pb.get_kinetic()
+    with kds.Problem(spec, precision="fp32", schedule=sched) as pb:
+        pb.set_kinetic(Fmid)
+        pb.step(2)
+        Fb = pb.get_kinetic()
+    assert np.array_equal(Fa, Fb)
+
+
+def test_graph_and_eager_steps_agree():
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, _, _ = case("cfg2_ragged")
+    out = []
+    for timed in (False, True):
+        with kds.Problem(spec, precision="fp32", schedule="line") as pb:
+            pb.set_state(torch.from_numpy(W0).cuda())
+            if timed:
+                ms = pb.step_timed(4)
+                assert all(t > 0 for t in ms)
+            else:
+                pb.step(4)
+            out.append(pb.get_kinetic())
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("prec,sched", MODES)
+def test_uniform_state_is_preserved(prec, sched):
+    from paper_2212_11010_amd import workloads as wl
+    spec, W0 = wl.make_workload(3, n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=3)
+    Wc = np.empty_like(W0)
+    Wc[...] = np.array([1.2, 0.1, -0.05, 0.02, 2.7])
+    W, F = run_gpu(spec, Wc, prec, sched)
+    # FP32: rows of C plus e sum to one only up to FP32 rounding of the
+    # coefficients (|C| entries grow with the Courant number), ~1e-6 per step
+    assert relerr(W, Wc) < (1e-13 if prec == "fp64" else 5e-6)
+
+
+def test_device_moments_and_host_moments_agree():
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, _, _ = case("cfg2_q1_deg1")
+    with kds.Problem(spec, precision="fp64", schedule="line") as pb:
+        pb.set_state(W0)
+        pb.step(2)
+        Wh = pb.moments()
+        Wd = torch.empty(Wh.shape, dtype=torch.float64, device="cuda")
+        pb.moments(Wd)
+        assert np.array_equal(Wh, Wd.cpu().numpy())
+
+
+def test_step_before_state_is_a_state_error():
+    from paper_2212_11010_amd import kds
+    spec, _, _, _ = case("cfg2_q1_deg1")
+    with kds.Problem(spec, precision="fp32") as pb:
+        with pytest.raises(kds.KdsError) as ei:
+            pb.step(1)
+        assert ei.value.status == kds.KDS_E_STATE
+
+
+def test_nonfinite_state_is_reported():
+    from paper_2212_11010_amd import kds
+    spec, W0, _, _ = case("cfg2_q1_deg1")
+    with kds.Problem(spec, precision="fp32") as pb:
+        pb.set_state(W0)
+        assert pb.check_finite()
+        F = pb.get_kinetic()
+        F[1, 5, 2, 0] = np.nan
+        pb.set_kinetic(F)
+        assert not pb.check_finite()
