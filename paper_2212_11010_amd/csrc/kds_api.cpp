@@ -142,21 +142,25 @@ bool plan_lines(kds_problem* p, std::string& why) {
   std::memset(&pl, 0, sizeof(pl));
   int max_lds = 0;
   int max_waves = 1;
-  const int lds_cap = 48 * 1024 / (int)p->elem;
+  const int lds_target = 32 * 1024 / (int)p->elem;  // bundles wider than one row stay below this
+  const int lds_cap = 64 * 1024 / (int)p->elem;     // hard limit per workgroup
   for (int k = 0; k < p->nv; ++k) {
     int ax = 0;
     for (int d = 0; d < p->dim; ++d)
       if (p->vel[k * p->dim + d] != 0.0) ax = d;
     const int Na = p->N[ax], S = p->S[ax];
+    // prefer many cells per lane (short scans, several lines per wavefront)
+    // as long as at least 3/4 of the lanes of a line group are busy
     int bestQ = 0;
     double bestU = -1;
-    for (int Q = 1; Q <= kMaxQ; ++Q) {
+    for (int Q = kMaxQ; Q >= 1; --Q) {
       if (S % Q) continue;
       const int NL = Na / Q;
       if (NL > 64) continue;
       int l2 = 1;
       while (l2 < NL) l2 <<= 1;
       const double util = (double)NL / l2;
+      if (util >= 0.74) { bestQ = Q; bestU = util; break; }
       if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
     }
     if (!bestQ) {
@@ -171,7 +175,7 @@ bool plan_lines(kds_problem* p, std::string& why) {
     int bw = 1;
     if (ax != 0) {
       // contiguous run of at least 256 bytes per row when the LDS allows
-      while (bw < p->N[0] && bw * p->nn * (int)p->elem < 256 && Na * (bw + 1) * p->nn <= lds_cap) ++bw;
+      while (bw < p->N[0] && bw * p->nn * (int)p->elem < 256 && Na * (bw + 1) * p->nn <= lds_target) ++bw;
     }
     pl.bw[k] = bw;
     const int R = (ax == 0 ? 1 : bw) * p->nn;

@@ -282,6 +282,124 @@ __global__ __launch_bounds__(256) void k_sweep_plain(const T* __restrict__ f_old
   tr_out[(int64_t)kc * g.tr_stride + (int64_t)seg * nlines + line] = t_new;
 }
 
+// Value of the lane `OFF` places lower in the same 16-lane row (DPP
+// row_shr); lanes without a source get 0.  Used only where every scan
+// segment lies inside one row.
+template <typename T, int OFF>
+__device__ __forceinline__ T dpp_row_shr(T v);
+
+template <>
+__device__ __forceinline__ float dpp_row_shr<float, 1>(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+}
+#define KDS_DPP_F32(OFF)                                                                        \
+  template <>                                                                                   \
+  __device__ __forceinline__ float dpp_row_shr<float, OFF>(float v) {                           \
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + (OFF), 0xf, \
+                                                      0xf, true));                              \
+  }                                                                                             \
+  template <>                                                                                   \
+  __device__ __forceinline__ double dpp_row_shr<double, OFF>(double v) {                        \
+    const long long b = __double_as_longlong(v);                                                \
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x110 + (OFF), 0xf,  \
+                                               0xf, true);                                      \
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + (OFF), 0xf, 0xf,      \
+                                               true);                                           \
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);                      \
+  }
+KDS_DPP_F32(2)
+KDS_DPP_F32(4)
+KDS_DPP_F32(8)
+#undef KDS_DPP_F32
+template <>
+__device__ __forceinline__ double dpp_row_shr<double, 1>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x111, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Copy between a bundle of rows (R contiguous values each, rows rowstride
+// apart, starting at rowbase) and the LDS tile (rows of R values, packed).
+// Vectors of VW elements when the rows allow it; addresses advance
+// incrementally (one division per thread) and U independent accesses are
+// issued before any is consumed, so global latency overlaps.
+template <typename T, int VW>
+struct VecT;
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<float, 2> { using type = float2; };
+template <> struct VecT<float, 4> { using type = float4; };
+template <> struct VecT<double, 1> { using type = double; };
+template <> struct VecT<double, 2> { using type = double2; };
+
+template <typename T, int VW, bool LOAD>
+__device__ __forceinline__ void copy_rows(T* __restrict__ f, T* tile, int64_t rowbase,
+                                          int64_t rowstride, int R, int rows) {
+  using VT = typename VecT<T, VW>::type;
+  constexpr int U = 8;
+  const int RV = R / VW;  // vectors per row
+  const int total = rows * RV;
+  const int bs = blockDim.x;
+  const int64_t rs = rowstride / VW;
+  VT* g = reinterpret_cast<VT*>(f + rowbase);
+  VT* t = reinterpret_cast<VT*>(tile);
+  int e = threadIdx.x;
+  int r = e / RV;
+  int q = e - r * RV;
+  const int dr = bs / RV;
+  const int dq = bs - dr * RV;
+  int64_t go = (int64_t)r * rs + q;
+  const int64_t gstep = (int64_t)dr * rs + dq;
+  const int64_t gwrap = rs - RV;
+  while (e < total) {
+    int64_t ga[U];
+    int ta[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ga[u] = go;
+      ta[u] = e;
+      e += bs;
+      go += gstep;
+      q += dq;
+      if (q >= RV) {
+        q -= RV;
+        go += gwrap;
+      }
+    }
+    if (LOAD) {
+      VT v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ta[u] < total) v[u] = g[ga[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ta[u] < total) t[ta[u]] = v[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ta[u] < total) g[ga[u]] = t[ta[u]];
+    }
+  }
+}
+
+template <typename T, bool LOAD>
+__device__ __forceinline__ void copy_tile(T* __restrict__ f, T* tile, int64_t rowbase,
+                                          int64_t rowstride, int R, int rows) {
+  // one contiguous block: treat as a single row
+  if (rowstride == R) {
+    R *= rows;
+    rows = 1;
+  }
+  constexpr int VMAX = 16 / sizeof(T);
+  if (VMAX >= 4 && R % 4 == 0 && rowbase % 4 == 0 && rowstride % 4 == 0) {
+    copy_rows<T, (VMAX >= 4 ? 4 : 1), LOAD>(f, tile, rowbase, rowstride, R, rows);
+  } else if (R % 2 == 0 && rowbase % 2 == 0 && rowstride % 2 == 0) {
+    copy_rows<T, 2, LOAD>(f, tile, rowbase, rowstride, R, rows);
+  } else {
+    copy_rows<T, 1, LOAD>(f, tile, rowbase, rowstride, R, rows);
+  }
+}
+
 // ======================================================= line sweep
 
 // All K subdomain iterations of whole grid lines in one pass.  One workgroup
@@ -346,12 +464,7 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
     n_lines = Bw * per;
   }
 
-  const int total = Na * R;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int r = e / R;
-    const int q = e - r * R;
-    tile[e] = f[rowbase + r * rowstride + q];
-  }
+  copy_tile<T, true>(f, tile, rowbase, rowstride, R, Na);
   __syncthreads();
 
   int ns = 1;
@@ -376,11 +489,14 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
   const int slot = lane / LPL2;
   const int lbase = slot * LPL2;
   const int j0 = lil * Q;
-  const bool seg_start = (j0 % S) == 0;
-  const int s_me = j0 / S;
+  const int Ls = S / Q;          // lanes per subdomain (Q divides S)
+  const int sl = lil % Ls;       // lane index inside its subdomain
+  const int s_me = lil / Ls;
   const int s_up = s_me == 0 ? nseg - 1 : s_me - 1;
-  const int end_up = lbase + (s_up + 1) * (S / Q) - 1;  // lane holding the upwind subdomain's end
+  const int end_up = lbase + (s_up + 1) * Ls - 1;  // lane holding the upwind subdomain's end
   const int src_prev = lbase + (lil == 0 ? NL - 1 : lil - 1);
+  const bool dpp_ok = Ls <= 16 && (16 % Ls) == 0;  // subdomains never straddle a 16-lane row
+  const T gQ = powi(gg, Q);
 
   for (int lb = wave * LW; lb < n_lines; lb += nwaves * LW) {
     const int l = lb + slot;
@@ -407,9 +523,9 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
     // old-time inflow of my first cell: outflow node of the upwind cell
     const T t_old0 = __shfl(last_old, src_prev, 64);
 
-    // chunk map x_out = mA x_in + mB of the zero-inflow recurrence
+    // zero-inflow recurrence over my cells: x <- beta + g x, x = 0 entering
+    // my chunk; mB = value leaving my chunk.
     T beta[kMaxQ];
-    T mA = seg_start ? T(0) : T(1);
     T mB = T(0);
     {
       T to = t_old0;
@@ -420,7 +536,6 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
 #pragma unroll
           for (int c = 0; c < P; ++c) bq += C[P - 1][c] * fo[q][c];
           beta[q] = bq;
-          mA = gg * mA;
           mB = gg * mB + bq;
           to = fo[q][P - 1];
         } else {
@@ -428,27 +543,46 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
         }
       }
     }
-    // inclusive scan of the maps over the lanes of the line
-    for (int off = 1; off < LPL2; off <<= 1) {
-      const T pA = __shfl_up(mA, off, LPL2);
-      const T pB = __shfl_up(mB, off, LPL2);
-      if (lil >= off) {
-        mB = mA * pB + mB;
-        mA = mA * pA;
+    // segmented inclusive scan over the lanes of each subdomain: a window of
+    // `off` lanes that does not reach the subdomain start multiplies the
+    // incoming value by g^(Q off)
+    {
+      T gw = gQ;
+      if (dpp_ok) {
+#define KDS_SCAN_STEP(OFF)                                  \
+  if ((OFF) < Ls) {                                         \
+    const T pB = dpp_row_shr<T, (OFF)>(mB);                 \
+    if (sl >= (OFF)) mB = gw * pB + mB;                     \
+    gw = gw * gw;                                           \
+  }
+        KDS_SCAN_STEP(1)
+        KDS_SCAN_STEP(2)
+        KDS_SCAN_STEP(4)
+        KDS_SCAN_STEP(8)
+#undef KDS_SCAN_STEP
+      } else {
+        for (int off = 1; off < Ls; off <<= 1) {
+          const T pB = __shfl_up(mB, off, LPL2);
+          if (sl >= off) mB = gw * pB + mB;
+          gw = gw * gw;
+        }
       }
     }
-    T x_in = __shfl_up(mB, 1, LPL2);
-    if (lil == 0 || seg_start) x_in = T(0);
+    T x_in = dpp_ok ? dpp_row_shr<T, 1>(mB) : __shfl_up(mB, 1, LPL2);
+    if (sl == 0) x_in = T(0);
 
     T qv[kMaxQ];
-    T x = x_in;
+    {
+      T x = x_in;
 #pragma unroll
-    for (int q = 0; q < kMaxQ; ++q) {
-      qv[q] = x;
-      if (q < Q) x = beta[q] + gg * x;
+      for (int q = 0; q < kMaxQ; ++q) {
+        qv[q] = x;
+        if (q < Q) x = beta[q] + gg * x;
+      }
     }
-    // subdomain iteration on the outflow values (meaningful on end lanes)
-    const T Pseg = x;
+    // subdomain iteration on the outflow values (meaningful on end lanes,
+    // where mB is the zero-inflow outflow P_s of the subdomain)
+    const T Pseg = mB;
     T Tv = last_old;
     for (int it = 1; it < g.K; ++it) {
       const T up = __shfl(Tv, end_up, 64);
@@ -480,11 +614,7 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int r = e / R;
-    const int q = e - r * R;
-    f[rowbase + r * rowstride + q] = tile[e];
-  }
+  copy_tile<T, false>(f, tile, rowbase, rowstride, R, Na);
 }
 
 // ============================================================ launchers

@@ -29,6 +29,9 @@ CASES = {
     "cfg3_k1": (3, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=2, n_iter=1)),
     "cfg2_theta1": (2, dict(n_cells=[32, 16], sub_cells=[8, 16], steps=3, theta=1.0)),
     "cfg2_full_2steps": (2, dict(steps=2)),
+    # one subdomain of 34 cells (2 cells per lane, 17-lane scan through
+    # wavefront shuffles) and 5 cells per lane along y
+    "cfg1_odd": (1, dict(n_cells=[34, 20], sub_cells=[34, 10], steps=5)),
 }
 
 
