@@ -48,12 +48,14 @@ def workload(name):
     return wl.make_workload(cfg)
 
 
-def time_problem(spec, W0, prec, sched, steps, warmup):
+def time_problem(spec, W0, prec, sched, steps, warmup, tune=False):
     import torch
     from paper_2212_11010_amd import kds
     pb = kds.Problem(spec, precision=prec, schedule=sched)
-    info = pb.info()
     pb.set_state(torch.from_numpy(W0).cuda())
+    if tune:
+        pb.tune(3)   # autotuner (setup, outside the timed region); restores the state
+    info = pb.info()
     pb.step(warmup)
     pb.synchronize()
     torch.cuda.synchronize()
@@ -80,6 +82,51 @@ def traffic_record(kernel, wname, prec):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def _pmc_per_dispatch(csv_path, name_part, last=0):
+    """Average counter value (KiB per dispatch) of the kernels whose name
+    contains name_part, from a rocprofv3 --pmc counter_collection.csv; with
+    last > 0 only the last `last` dispatches (those after the autotuner)."""
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if name_part in r["Kernel_Name"]]
+    if last:
+        vals = vals[-last:]
+    return sum(vals) / len(vals), len(vals)
+
+
+def pmc_summary(args):
+    """Write profiles/traffic_<kernel>_<workload>_fp32.json from four rocprofv3
+    --pmc runs (FETCH_SIZE and WRITE_SIZE of the workload, and of the plain
+    1 GiB copy of --copy-probe, whose true bytes calibrate the counters)."""
+    fetch_csv, write_csv, cfetch_csv, cwrite_csv = args.pmc_summary
+    kname = KERNEL_NAMES[args.schedule if args.schedule != "auto" else "line"]
+    # the counter runs use --steps 3 --warmup 1: 1 + 3 graph + 3 timed dispatches
+    f_kib, nf = _pmc_per_dispatch(fetch_csv, kname, last=7)
+    w_kib, nw = _pmc_per_dispatch(write_csv, kname, last=7)
+    cf_kib, _ = _pmc_per_dispatch(cfetch_csv, "copyBuffer")
+    cw_kib, _ = _pmc_per_dispatch(cwrite_csv, "copyBuffer")
+    true_copy = float(1 << 30)
+    rd_scale = true_copy / (cf_kib * 1024)
+    wr_scale = true_copy / (cw_kib * 1024)
+    rd = f_kib * 1024 * rd_scale
+    wr = w_kib * 1024 * wr_scale
+    spec, _ = workload(args.workload)
+    from paper_2212_11010_amd import workloads as wl
+    U = wl.unknowns(spec)
+    rec = {"kernel": kname, "workload": args.workload, "precision": "fp32",
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+           "dispatches": [nf, nw],
+           "copy_probe_fetch_kib": cf_kib, "copy_probe_write_kib": cw_kib,
+           "read_scale": rd_scale, "write_scale": wr_scale,
+           "hbm_bytes_per_launch": rd + wr, "hbm_read_bytes": rd, "hbm_write_bytes": wr,
+           "algorithmic_bytes_per_launch": 8.0 * U,
+           "ratio_to_algorithmic": (rd + wr) / (8.0 * U)}
+    out = os.path.join(ROOT, "profiles", "traffic_%s_%s_fp32.json" % (kname, args.workload))
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(spec, W0, budget_s=12.0):
@@ -111,9 +158,15 @@ def main():
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-plan autotuner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar="CSV",
+                    help="fetch.csv write.csv copy_fetch.csv copy_write.csv -> profiles/traffic_*.json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 4
@@ -137,11 +190,14 @@ def main():
     U = wl.unknowns(spec)
     log("workload %s U=%d dt=%.5g nu=%.3f" % (spec["name"], U, spec["dt"], spec["kinetic_courant"]))
 
-    ms32, k32, info32, ok32 = time_problem(spec, W0, "fp32", args.schedule, args.steps, args.warmup)
+    ms32, k32, info32, ok32 = time_problem(spec, W0, "fp32", args.schedule, args.steps, args.warmup,
+                                           tune=not args.no_tune)
     sched = {1: "plain", 2: "line"}[info32["schedule"]]
     log("fp32 %s: %.4f ms/step (graph), kernels %s ms" % (sched, ms32, k32))
     extra = {"fp32_schedule": sched, "fp32_kernel_ms": {"sweep": k32[0], "relax": k32[1]},
-             "fp32_state_finite": ok32}
+             "fp32_state_finite": ok32, "line_plan": {"cells_per_lane": info32["line_Q"][:spec["dim"]],
+                                                      "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
+                                                      "autotuned": bool(info32["tuned"])}}
     if not args.no_fp64:
         ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", "plain", max(5, args.steps // 5), 2)
         log("fp64 plain: %.4f ms/step, kernels %s ms" % (ms64, k64))

@@ -128,6 +128,14 @@ kds_status kds_step(kds_problem* p, int32_t n_steps);
 #define KDS_N_KERNEL_KINDS 2
 kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
 
+/* Autotuner of the line schedule: times the sweep kernel for candidate
+ * launch plans (cells per lane, columns of cells per workgroup; one grid axis
+ * at a time, reps launches each) on the current state, keeps the fastest,
+ * restores the state.  Needs a state; a no-op for the plain schedule
+ * (*sweep_ms = -1).  sweep_ms (nullable): best average sweep time.  Needs
+ * one state's worth of free device memory (else KDS_E_NOMEM). */
+kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
+
 /* W = sum_k F_k (FP64, Sec. 2.2 step 3) into W_out [cell][node][c]. */
 kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device);
 
@@ -148,10 +156,12 @@ typedef struct {
   int32_t schedule;       /* schedule actually used (KDS_SCHED_PLAIN / LINE) */
   int32_t precision;
   int32_t steps_done;
-  int32_t cells_per_lane; /* line schedule: cells per lane (0 for plain) */
   double max_kinetic_courant; /* max_k |V_k| dt / h_axis */
   double min_subdomain_width; /* min over used axes of sub_cells * h */
   int32_t proposition_ok; /* 1 if |V| dt <= subdomain width (Sec. 5.1 Proposition) */
+  int32_t line_Q[3];      /* line schedule, per axis: cells per lane (0 for plain) */
+  int32_t line_bw[3];     /* line schedule, per axis: columns of cells per workgroup */
+  int32_t tuned;          /* 1 after kds_tune */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

@@ -31,6 +31,8 @@ struct kds_problem {
   std::vector<unsigned char> eq_blob;
   std::vector<unsigned char> sweep_blob;  // SweepTab<T>
   LinePlan plan{};
+  int line_Q[3] = {1, 1, 1}, line_bw[3] = {1, 1, 1};  // per-axis line-schedule choices
+  bool tuned = false;
   double max_nu = 0, min_sub_width = 0;
   bool proposition_ok = true;
   // device
@@ -134,77 +136,105 @@ kds_status validate(const kds_config* c, std::string& msg) {
   return KDS_OK;
 }
 
-// Line schedule: choose the cells per lane Q (divides the subdomain width,
-// line fits one wavefront) maximising lane utilisation, and the bundle width
-// across the line for y / z sweeps.
-bool plan_lines(kds_problem* p, std::string& why) {
-  LinePlan& pl = p->plan;
-  std::memset(&pl, 0, sizeof(pl));
-  int max_lds = 0;
-  int max_waves = 1;
-  const int lds_target = 32 * 1024 / (int)p->elem;  // bundles wider than one row stay below this
-  const int lds_cap = 64 * 1024 / (int)p->elem;     // hard limit per workgroup
-  for (int k = 0; k < p->nv; ++k) {
-    int ax = 0;
-    for (int d = 0; d < p->dim; ++d)
-      if (p->vel[k * p->dim + d] != 0.0) ax = d;
-    const int Na = p->N[ax], S = p->S[ax];
-    // prefer many cells per lane (short scans, several lines per wavefront)
-    // as long as at least 3/4 of the lanes of a line group are busy
-    int bestQ = 0;
-    double bestU = -1;
-    for (int Q = kMaxQ; Q >= 1; --Q) {
-      if (S % Q) continue;
-      const int NL = Na / Q;
-      if (NL > 64) continue;
-      int l2 = 1;
-      while (l2 < NL) l2 <<= 1;
-      const double util = (double)NL / l2;
-      if (util >= 0.74) { bestQ = Q; bestU = util; break; }
-      if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
-    }
-    if (!bestQ) {
-      why = "line schedule needs a cells-per-lane count Q <= 8 dividing the subdomain width with n_cells/Q <= 64";
-      return false;
-    }
-    const int NL = Na / bestQ;
-    int l2 = 1;
-    while (l2 < NL) l2 <<= 1;
-    pl.Q[k] = bestQ;
-    pl.lpl2[k] = l2;
-    int bw = 1;
-    if (ax != 0) {
-      // contiguous run of at least 256 bytes per row when the LDS allows
-      while (bw < p->N[0] && bw * p->nn * (int)p->elem < 256 && Na * (bw + 1) * p->nn <= lds_target) ++bw;
-    }
-    pl.bw[k] = bw;
-    const int R = (ax == 0 ? 1 : bw) * p->nn;
-    if (Na * R > lds_cap) {
-      why = "line schedule: one bundle of lines does not fit the LDS budget";
-      return false;
-    }
-    max_lds = std::max(max_lds, Na * R);
-    const int lines = (ax == 0 ? 1 : bw) * (p->nn / p->P);
-    const int lw = 64 / l2;
-    max_waves = std::max(max_waves, std::min(4, (lines + lw - 1) / lw));
+int axis_of(const kds_problem* p, int k) {
+  int ax = 0;
+  for (int d = 0; d < p->dim; ++d)
+    if (p->vel[k * p->dim + d] != 0.0) ax = d;
+  return ax;
+}
+
+int pow2_at_least(int n) {
+  int l2 = 1;
+  while (l2 < n) l2 <<= 1;
+  return l2;
+}
+
+// Is (Q cells per lane, bw columns per bundle) a valid line-schedule choice
+// for velocities along axis ax?
+bool line_choice_ok(const kds_problem* p, int ax, int Q, int bw) {
+  const int Na = p->N[ax], S = p->S[ax];
+  const int qmax = line_qmax((int)p->elem, p->nn);
+  if (Q < 1 || Q > qmax || S % Q || Na / Q > 64 || bw < 1) return false;
+  if ((int64_t)bw * Na * p->nn * (int)p->elem > 64 * 1024) return false;
+  if (ax == 0 && bw > p->ncell / Na) return false;
+  if (ax != 0 && (bw > p->N[0] || bw * p->nn > 256)) return false;
+  const int lw = 64 / pow2_at_least(Na / Q);
+  if ((bw + lw - 1) / lw > 4) return false;
+  return true;
+}
+
+// Heuristic choice: many cells per lane as long as >= 3/4 of a line group's
+// lanes work; as many columns per bundle as a 32 KB LDS tile holds.
+bool heuristic_choice(const kds_problem* p, int ax, int* Qo, int* bwo) {
+  const int Na = p->N[ax], S = p->S[ax];
+  const int qmax = line_qmax((int)p->elem, p->nn);
+  int bestQ = 0;
+  double bestU = -1;
+  for (int Q = qmax; Q >= 1; --Q) {
+    if (S % Q || Na / Q > 64) continue;
+    const double util = (double)(Na / Q) / pow2_at_least(Na / Q);
+    if (util >= 0.74) { bestQ = Q; break; }
+    if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
   }
-  pl.lds_elems = max_lds;
-  pl.threads = 64 * max_waves;
+  if (!bestQ) return false;
+  const int col = Na * p->nn * (int)p->elem;
+  int bw = std::max(1, 32 * 1024 / col);
+  while (bw > 1 && !line_choice_ok(p, ax, bestQ, bw)) --bw;
+  if (!line_choice_ok(p, ax, bestQ, bw)) return false;
+  *Qo = bestQ;
+  *bwo = bw;
+  return true;
+}
+
+// Fill the per-velocity launch plan from per-axis choices.
+bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePlan& pl) {
+  std::memset(&pl, 0, sizeof(pl));
+  int max_lds = 0, threads = 64;
   int64_t acc = 0;
   for (int k = 0; k < p->nv; ++k) {
-    int ax = 0;
-    for (int d = 0; d < p->dim; ++d)
-      if (p->vel[k * p->dim + d] != 0.0) ax = d;
+    const int ax = axis_of(p, k);
+    const int Na = p->N[ax], Q = Qax[ax], bw = bwax[ax];
+    if (!line_choice_ok(p, ax, Q, bw)) return false;
+    const int l2 = pow2_at_least(Na / Q);
+    const int lw = 64 / l2;
+    pl.Q[k] = Q;
+    pl.lpl2[k] = l2;
+    pl.bw[k] = bw;
+    max_lds = std::max(max_lds, bw * Na * p->nn);
+    threads = std::max(threads, 64 * ((bw + lw - 1) / lw));
+    if (ax != 0) threads = std::max(threads, ((bw * p->nn + 63) / 64) * 64);
     int64_t nb;
-    if (ax == 0) nb = p->ncell / p->N[0];
-    else nb = (int64_t)((p->N[0] + pl.bw[k] - 1) / pl.bw[k]) * (p->ncell / p->N[0] / p->N[ax]);
+    if (ax == 0) nb = (p->ncell / Na + bw - 1) / bw;
+    else nb = (int64_t)((p->N[0] + bw - 1) / bw) * (p->ncell / p->N[0] / Na);
     for (int c = 0; c < p->m; ++c) {
       pl.block_start[k * p->m + c] = acc;
       acc += nb;
     }
   }
   pl.block_start[p->nv * p->m] = acc;
-  if (acc > 0x7fffffffLL) { why = "line schedule: grid too large"; return false; }
+  pl.lds_elems = max_lds;
+  pl.threads = threads;
+  return threads <= 256 && acc <= 0x7fffffffLL;
+}
+
+// Line schedule plan from the heuristic choices.
+bool plan_lines(kds_problem* p, std::string& why) {
+  if (line_qmax((int)p->elem, p->nn) * p->nn * (int)p->elem > 512) {
+    why = "line schedule: the cells of one lane do not fit the register budget";
+    return false;
+  }
+  for (int ax = 0; ax < 3; ++ax) { p->line_Q[ax] = 1; p->line_bw[ax] = 1; }
+  for (int k = 0; k < p->nv; ++k) {
+    const int ax = axis_of(p, k);
+    if (!heuristic_choice(p, ax, &p->line_Q[ax], &p->line_bw[ax])) {
+      why = "line schedule: no cells-per-lane count divides the subdomain width with the line in one wavefront";
+      return false;
+    }
+  }
+  if (!finalize_plan(p, p->line_Q, p->line_bw, p->plan)) {
+    why = "line schedule: launch plan out of range";
+    return false;
+  }
   return true;
 }
 
@@ -232,19 +262,19 @@ void fill_sweep_tab(kds_problem* p, const Basis1D& basis) {
 }
 
 void free_device(kds_problem* p) {
-  if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   p->graph_exec = nullptr;
   p->graph = nullptr;
   for (auto& e : p->ev)
-    if (e) { hipEventDestroy(e); e = nullptr; }
+    if (e) { (void)hipEventDestroy(e); e = nullptr; }
   void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag};
   for (void* b : bufs)
-    if (b) hipFree(b);
+    if (b) (void)hipFree(b);
   p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
   p->stage = nullptr;
   p->flag = nullptr;
-  if (p->own_stream && p->stream) hipStreamDestroy(p->stream);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   p->stream = nullptr;
 }
 
@@ -279,7 +309,7 @@ kds_status ensure_graph(kds_problem* p) {
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(p->stream, &graph);
   if (st != KDS_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return st;
   }
   if (e != hipSuccess) return hip_fail(p, e, "hipStreamEndCapture");
@@ -304,7 +334,7 @@ kds_status check_device_ptr(kds_problem* p, const void* ptr) {
 
 kds_status ensure_stage(kds_problem* p, size_t bytes) {
   if (p->stage_bytes >= bytes) return KDS_OK;
-  if (p->stage) hipFree(p->stage);
+  if (p->stage) (void)hipFree(p->stage);
   p->stage = nullptr;
   p->stage_bytes = 0;
   hipError_t e = hipMalloc((void**)&p->stage, bytes);
@@ -401,7 +431,13 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED, why);
   }
-  p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok) ? KDS_SCHED_PLAIN : KDS_SCHED_LINE;
+  // AUTO keeps the plain schedule where a lane would hold more than 64 state
+  // values (64-node cells): the line kernel's occupancy is too low there.
+  const bool line_preferred = line_qmax((int)p->elem, p->nn) * p->nn <= 64;
+  p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok ||
+              (cfg->schedule == KDS_SCHED_AUTO && !line_preferred))
+                 ? KDS_SCHED_PLAIN
+                 : KDS_SCHED_LINE;
 
   // ---------------------------------------------------------------- device
   hipError_t e = hipGetDevice(&p->device);
@@ -520,6 +556,80 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms) {
   return KDS_OK;
 }
 
+kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_tune needs a state (kds_set_state first)");
+  if (p->sched != KDS_SCHED_LINE) {
+    if (sweep_ms) *sweep_ms = -1.0;
+    return KDS_OK;
+  }
+  reps = std::max(1, std::min(reps, 100));
+  const size_t bytes = (size_t)p->n_unknowns() * p->elem;
+  void* save = nullptr;
+  if (hipMalloc(&save, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, KDS_E_NOMEM, "kds_tune: no device memory to save the state");
+  }
+  KDS_HIP(p, hipMemcpyAsync(save, p->f, bytes, hipMemcpyDeviceToDevice, p->stream));
+  kds_status st = KDS_OK;
+  auto time_plan = [&](const LinePlan& pl, float* ms) -> bool {
+    hipError_t e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(p->ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
+    if (e != hipSuccess) {
+      st = hip_fail(p, e, "kds_tune");
+      return false;
+    }
+    *ms /= reps;
+    return true;
+  };
+  float best = 0.0f;
+  bool ok = time_plan(p->plan, &best);
+  bool used[3] = {false, false, false};
+  for (int k = 0; k < p->nv; ++k) used[axis_of(p, k)] = true;
+  const int bws[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 28, 32};
+  // coordinate search: one axis at a time, over (cells per lane, bundle width)
+  for (int ax = 0; ax < 3 && ok; ++ax) {
+    if (!used[ax]) continue;
+    for (int Q = 1; Q <= kMaxQ && ok; ++Q)
+      for (int bw : bws) {
+        if (!line_choice_ok(p, ax, Q, bw)) continue;
+        if (Q == p->line_Q[ax] && bw == p->line_bw[ax]) continue;
+        int tq[3], tb[3];
+        for (int i = 0; i < 3; ++i) { tq[i] = p->line_Q[i]; tb[i] = p->line_bw[i]; }
+        tq[ax] = Q;
+        tb[ax] = bw;
+        LinePlan pl;
+        if (!finalize_plan(p, tq, tb, pl)) continue;
+        float ms = 0.0f;
+        if (!(ok = time_plan(pl, &ms))) break;
+        if (ms < 0.97f * best) {
+          best = ms;
+          p->line_Q[ax] = Q;
+          p->line_bw[ax] = bw;
+          p->plan = pl;
+        }
+      }
+  }
+  // restore the state and drop the graph captured with the old plan
+  hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  (void)hipFree(save);
+  if (!ok) return st;
+  if (e != hipSuccess) return hip_fail(p, e, "kds_tune restore");
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  p->tuned = true;
+  if (sweep_ms) *sweep_ms = best;
+  return KDS_OK;
+}
+
 kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (!W_out) return fail(p, KDS_E_INVALID, "W_out is NULL");
@@ -604,10 +714,14 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
   info->schedule = p->sched;
   info->precision = p->prec;
   info->steps_done = p->steps_done;
-  info->cells_per_lane = p->sched == KDS_SCHED_LINE ? p->plan.Q[0] : 0;
   info->max_kinetic_courant = p->max_nu;
   info->min_subdomain_width = p->min_sub_width;
   info->proposition_ok = p->proposition_ok ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    info->line_Q[a] = p->sched == KDS_SCHED_LINE ? p->line_Q[a] : 0;
+    info->line_bw[a] = p->sched == KDS_SCHED_LINE ? p->line_bw[a] : 0;
+  }
+  info->tuned = p->tuned ? 1 : 0;
   return KDS_OK;
 }
 

@@ -16,6 +16,7 @@ constexpr int kMaxVel = 8;   // kinetic velocities
 constexpr int kMaxP = 4;     // nodes per axis (degree <= 3)
 constexpr int kMaxM = 8;     // conserved components
 constexpr int kMaxQ = 8;     // cells per lane in the line schedule
+constexpr int kXcds = 8;     // accelerator complex dies of an MI355X (own L2 each)
 
 // ---------------------------------------------------------------- host setup
 
@@ -76,11 +77,17 @@ struct EqTab {
   double gamma;       // Euler
 };
 
-// Line-schedule launch plan (per velocity axis).
+// Most cells per lane the line kernel keeps in registers (a budget of 64
+// state values per lane; nn = nodes per cell).
+__host__ __device__ constexpr int line_qmax(int elem_bytes, int nn) {
+  return (void)elem_bytes, 64 / nn >= 8 ? 8 : 64 / nn >= 4 ? 4 : 2;
+}
+
+// Line-schedule launch plan (per velocity).
 struct LinePlan {
   int Q[kMaxVel];          // cells per lane
   int lpl2[kMaxVel];       // lanes per line, power of two
-  int bw[kMaxVel];         // cells across the line per bundle (y/z axes)
+  int bw[kMaxVel];         // columns of cells per bundle
   int64_t block_start[kMaxVel * kMaxM + 1];  // prefix over (k, c) of bundles
   int lds_elems;           // max tile elements
   int threads;             // block size

@@ -336,7 +336,7 @@ template <typename T, int VW, bool LOAD>
 __device__ __forceinline__ void copy_rows(T* __restrict__ f, T* tile, int64_t rowbase,
                                           int64_t rowstride, int R, int rows) {
   using VT = typename VecT<T, VW>::type;
-  constexpr int U = 8;
+  constexpr int U = 16;
   const int RV = R / VW;  // vectors per row
   const int total = rows * RV;
   const int bs = blockDim.x;
@@ -367,10 +367,11 @@ __device__ __forceinline__ void copy_rows(T* __restrict__ f, T* tile, int64_t ro
       }
     }
     if (LOAD) {
+      // unconditional loads (slots past the end re-read element 0), so the
+      // U loads stay in flight together
       VT v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ta[u] < total) v[u] = g[ga[u]];
+      for (int u = 0; u < U; ++u) v[u] = g[ta[u] < total ? ga[u] : 0];
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ta[u] < total) t[ta[u]] = v[u];
@@ -402,27 +403,264 @@ __device__ __forceinline__ void copy_tile(T* __restrict__ f, T* tile, int64_t ro
 
 // ======================================================= line sweep
 
-// All K subdomain iterations of whole grid lines in one pass.  One workgroup
-// holds a bundle of complete lines of one (velocity, component) in LDS; one
-// wavefront (or half / quarter of one) owns a line, Q consecutive cells per
-// lane.  On a line the outflow values obey the first-order recurrence
+// All K subdomain iterations of whole grid lines in one pass.
+//
+// A workgroup holds a bundle of complete columns of cells along the velocity
+// axis (one (velocity, component) pair) in LDS, laid out [column][cell][node].
+// Each lane owns Q consecutive cells of one column and ALL the 1-D lines
+// through them (the (p+1)^(d-1) node rows parallel to the axis), so its cells
+// are read from LDS as contiguous vectors and every node offset is a
+// compile-time constant.  On a line, in downwind order, the outflow values
+// obey the first-order recurrence
 //     t_{j+1} = beta_j + g t_j,  beta_j = (C f_j^{n-1})[P-1] + e1[P-1] t_j^{n-1},
 //     g = eth[P-1],
-// reset at every subdomain start.  A segmented scan over the lanes
-// (wavefront shuffles) gives, for every cell, q_j = the inflow it would get
-// with zero inflow at its subdomain start, and per subdomain s the outflow
-// P_s with zero inflow.  With G = g^S, the outflow of subdomain s at iterate p
-// is T_s^p = P_s + G T_{s-1}^{p-1}, T^0 = outflow of f^{n-1}, and the final
-// iterate K has inflow t_in(s) = T_{s-1}^{K-1}, so t_j^n = q_j + g^{j-j_s} t_in(s).
-// This is the same linear algebra as K literal sweeps (exact reformulation,
-// different rounding order); the state is read and written once.
-template <typename T, int P>
+// restarted at every subdomain start.  A segmented scan over the lanes of a
+// subdomain (DPP row shifts) gives each cell the inflow q_j it would receive
+// with zero inflow at its subdomain start, and each subdomain s its
+// zero-inflow outflow P_s.  With G = g^S, the outflow of subdomain s at
+// iterate p is T_s^p = P_s + G T_{s-1}^{p-1} (T^0 = outflow of f^{n-1}), and the
+// final iterate K has inflow t_in(s) = T_{s-1}^{K-1}, so
+// t_j^n = q_j + g^{j - j_s} t_in(s).  This is the linear algebra of K literal
+// sweeps (eq:ibvp), evaluated in another order; the state is read and
+// written once per step.
+
+// Copy between rows of a y/z bundle (row j = cell j along the axis: ncols
+// adjacent cells, ncols*NN contiguous values at gbase + j*rowstride) and the
+// LDS tile laid out [column][cell][node] (column stride CS).  Each thread
+// owns one vector position of a row and walks the rows; U rows are in flight.
+template <typename T, int NN, int VW, bool LOAD>
+__device__ __forceinline__ void copy_cols_v(T* __restrict__ f, T* tile, int64_t gbase,
+                                            int64_t rowstride, int ncols, int Na, int CS) {
+  using VT = typename VecT<T, VW>::type;
+  constexpr int U = 32 / VW;
+  const int RWV = ncols * NN / VW;  // vectors per row
+  const int rpi = blockDim.x / RWV; // rows per pass
+  const int tid = threadIdx.x;
+  if (rpi == 0 || tid >= rpi * RWV) return;
+  const int jj = tid / RWV;
+  const int ev = tid - jj * RWV;
+  int tl[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) {
+    const int e = ev * VW + i;
+    const int c = e / NN;
+    tl[i] = c * CS + jj * NN + (e - c * NN);
+  }
+  VT* g = reinterpret_cast<VT*>(f + gbase) + ev;
+  const int64_t rs = rowstride / VW;
+  for (int j0 = 0; j0 < Na; j0 += U * rpi) {
+    if (LOAD) {
+      VT v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + jj + u * rpi;
+        v[u] = g[(j < Na ? j : 0) * rs];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + jj + u * rpi;
+        if (j < Na) {
+          const T* vp = reinterpret_cast<const T*>(&v[u]);
+#pragma unroll
+          for (int i = 0; i < VW; ++i) tile[tl[i] + (j0 + u * rpi) * NN] = vp[i];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + jj + u * rpi;
+        if (j < Na) {
+          VT v;
+          T* vp = reinterpret_cast<T*>(&v);
+#pragma unroll
+          for (int i = 0; i < VW; ++i) vp[i] = tile[tl[i] + (j0 + u * rpi) * NN];
+          g[j * rs] = v;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int NN, bool LOAD>
+__device__ __forceinline__ void copy_cols(T* __restrict__ f, T* tile, int64_t gbase,
+                                          int64_t rowstride, int ncols, int Na, int CS) {
+  const int RW = ncols * NN;
+  constexpr int VMAX = 16 / sizeof(T);
+  if (VMAX >= 4 && RW % 4 == 0 && gbase % 4 == 0 && rowstride % 4 == 0 && RW / 4 <= (int)blockDim.x)
+    copy_cols_v<T, NN, (VMAX >= 4 ? 4 : 1), LOAD>(f, tile, gbase, rowstride, ncols, Na, CS);
+  else if (RW % 2 == 0 && gbase % 2 == 0 && rowstride % 2 == 0 && RW / 2 <= (int)blockDim.x)
+    copy_cols_v<T, NN, 2, LOAD>(f, tile, gbase, rowstride, ncols, Na, CS);
+  else
+    copy_cols_v<T, NN, 1, LOAD>(f, tile, gbase, rowstride, ncols, Na, CS);
+}
+
+template <int P, int DIM>
+struct ColShape {
+  static constexpr int NN = P * (DIM > 1 ? P : 1) * (DIM > 2 ? P : 1);
+  static constexpr int PER = NN / P;  // lines through a cell along one axis
+};
+
+// offset inside a cell of the node with index b on `axis` and index `o` (a
+// mixed-radix number over the other axes, x fastest)
+template <int P, int DIM, int AXIS>
+__device__ constexpr int node_of(int o, int b) {
+  int off = 0, mul = 1;
+  for (int ax = 0; ax < DIM; ++ax) {
+    if (ax == AXIS) {
+      off += b * mul;
+    } else {
+      off += (o % P) * mul;
+      o /= P;
+    }
+    mul *= P;
+  }
+  return off;
+}
+
+struct LineLane {
+  int Q, Ls, sl, end_up, src_prev;
+  bool dpp_ok;
+};
+
+// One lane's part of the line solve.  d[q][node]: my Q cells in downwind
+// order (node indices physical); updated in place to the new state.
+// Lines O0 .. O0+PER-1 of the cells (groups keep the live registers small).
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0, int PER>
+__device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
+                                           const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
+                                           T gg, T G, int K) {
+  static_assert(NN == ColShape<P, DIM>::NN, "cell size");
+  // physical node of downwind node b along the axis, line O0 + o
+#define KDS_ND(o, b) node_of<P, DIM, AXIS>(O0 + (o), SIGN > 0 ? (b) : P - 1 - (b))
+  T last_old[PER], t_old0[PER], mB[PER];
+  T beta[PER][QMAX];
+#pragma unroll
+  for (int o = 0; o < PER; ++o) {
+    T lo = T(0);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+      if (q == ln.Q - 1) lo = d[q][KDS_ND(o, P - 1)];
+    last_old[o] = lo;
+  }
+#pragma unroll
+  for (int o = 0; o < PER; ++o) t_old0[o] = __shfl(last_old[o], ln.src_prev, 64);
+  // zero-inflow recurrence over my cells
+#pragma unroll
+  for (int o = 0; o < PER; ++o) {
+    T to = t_old0[o], x = T(0);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      if (q < ln.Q) {
+        T bq = e1[P - 1] * to;
+#pragma unroll
+        for (int c = 0; c < P; ++c) bq += C[P - 1][c] * d[q][KDS_ND(o, c)];
+        beta[o][q] = bq;
+        x = gg * x + bq;
+        to = d[q][KDS_ND(o, P - 1)];
+      } else {
+        beta[o][q] = T(0);
+      }
+    }
+    mB[o] = x;
+  }
+  // segmented inclusive scan over the lanes of each subdomain
+  {
+    T gw = powi(gg, ln.Q);
+    if (ln.dpp_ok) {
+#define KDS_SCAN_STEP(OFF)                                   \
+  if ((OFF) < ln.Ls) {                                       \
+    _Pragma("unroll") for (int o = 0; o < PER; ++o) {        \
+      const T pB = dpp_row_shr<T, (OFF)>(mB[o]);             \
+      if (ln.sl >= (OFF)) mB[o] = gw * pB + mB[o];           \
+    }                                                        \
+    gw = gw * gw;                                            \
+  }
+      KDS_SCAN_STEP(1)
+      KDS_SCAN_STEP(2)
+      KDS_SCAN_STEP(4)
+      KDS_SCAN_STEP(8)
+#undef KDS_SCAN_STEP
+    } else {
+      for (int off = 1; off < ln.Ls; off <<= 1) {
+#pragma unroll
+        for (int o = 0; o < PER; ++o) {
+          const T pB = __shfl_up(mB[o], off, 64);
+          if (ln.sl >= off) mB[o] = gw * pB + mB[o];
+        }
+        gw = gw * gw;
+      }
+    }
+  }
+  // subdomain iteration on the outflows (meaningful on subdomain-end lanes)
+  T Tv[PER];
+#pragma unroll
+  for (int o = 0; o < PER; ++o) Tv[o] = last_old[o];
+  for (int it = 1; it < K; ++it) {
+#pragma unroll
+    for (int o = 0; o < PER; ++o) {
+      const T up = __shfl(Tv[o], ln.end_up, 64);
+      Tv[o] = mB[o] + G * up;
+    }
+  }
+  const T g0 = powi(gg, ln.sl * ln.Q);
+#pragma unroll
+  for (int o = 0; o < PER; ++o) {
+    const T t_in = __shfl(Tv[o], ln.end_up, 64);
+    T x = ln.dpp_ok ? dpp_row_shr<T, 1>(mB[o]) : __shfl_up(mB[o], 1, 64);
+    if (ln.sl == 0) x = T(0);
+    T gp = g0, to = t_old0[o];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      if (q < ln.Q) {
+        const T tn = x + gp * t_in;
+        const T to_next = d[q][KDS_ND(o, P - 1)];
+        T fn[P];
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          T acc = e1[b] * to + eth[b] * tn;
+#pragma unroll
+          for (int c = 0; c < P; ++c) acc += C[b][c] * d[q][KDS_ND(o, c)];
+          fn[b] = acc;
+        }
+#pragma unroll
+        for (int b = 0; b < P; ++b) d[q][KDS_ND(o, b)] = fn[b];
+        x = beta[o][q] + gg * x;
+        to = to_next;
+        gp *= gg;
+      }
+    }
+  }
+#undef KDS_ND
+}
+
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0 = 0>
+__device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
+                                           const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
+                                           T gg, T G, int K) {
+  constexpr int ALL = ColShape<P, DIM>::PER;
+  constexpr int GS = ALL <= 4 ? ALL : (ALL % 3 == 0 ? 3 : 4);
+  if constexpr (O0 < ALL) {
+    constexpr int n = ALL - O0 < GS ? ALL - O0 : GS;
+    line_group<T, P, DIM, AXIS, SIGN, QMAX, NN, O0, n>(d, ln, C, e1, eth, gg, G, K);
+    line_lanes<T, P, DIM, AXIS, SIGN, QMAX, NN, O0 + n>(d, ln, C, e1, eth, gg, G, K);
+  }
+}
+
+template <typename T, int P, int DIM>
 __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, SweepTab<T> tab,
                                                     LinePlan pl) {
+  constexpr int NN = ColShape<P, DIM>::NN;
+  constexpr int QMAX = line_qmax((int)sizeof(T), NN);
   extern __shared__ unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
 
-  const int64_t bid = blockIdx.x;
+  // Workgroups are dealt round-robin to the XCDs; give each XCD a contiguous
+  // range of bundles so that neighbouring bundles, which share cache lines at
+  // their edges, meet in the same L2.
+  const int64_t nb = pl.block_start[g.nv * g.m];
+  const int64_t xq = nb / kXcds, xr = nb % kXcds;
+  const int64_t xcd = blockIdx.x % kXcds;
+  const int64_t bid = xcd * xq + min<int64_t>(xcd, xr) + blockIdx.x / kXcds;
   int kc = 0;
   while (bid >= pl.block_start[kc + 1]) ++kc;
   const int64_t bundle = bid - pl.block_start[kc];
@@ -435,41 +673,32 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
   const int Q = pl.Q[k];
   const int LPL2 = pl.lpl2[k];
   const int NL = Na / Q;
-  const int nn = g.nn;
-  const int per = nn / P;
+  const int bw = pl.bw[k];
+  const int CS = Na * NN;  // LDS column stride
+  const int64_t kc_base = (int64_t)kc * g.ncell * NN;
 
-  const int64_t kc_base = (int64_t)kc * g.ncell * nn;
-  int64_t rowbase, rowstride;
-  int R, n_lines;
+  // ------------------------------------------------------------ bundle
+  int ncols;
   if (a == 0) {
-    rowbase = kc_base + bundle * (int64_t)Na * nn;
-    rowstride = nn;
-    R = nn;
-    n_lines = per;
+    const int64_t nrows = g.ncell / Na;
+    const int64_t col0 = bundle * bw;
+    ncols = (int)min<int64_t>(bw, nrows - col0);
+    // consecutive rows of cells are one contiguous block
+    copy_tile<T, true>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
   } else {
-    const int B = pl.bw[k];
-    const int nbx = (g.N[0] + B - 1) / B;
+    const int nbx = (g.N[0] + bw - 1) / bw;
     const int bx = (int)(bundle % nbx);
     const int64_t other = bundle / nbx;
-    const int x0 = bx * B;
-    const int Bw = min(B, g.N[0] - x0);
-    if (a == 1) {
-      rowbase = kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)nn;
-      rowstride = (int64_t)g.N[0] * nn;
-    } else {
-      rowbase = kc_base + (other * g.N[0] + x0) * (int64_t)nn;
-      rowstride = (int64_t)g.N[0] * g.N[1] * nn;
-    }
-    R = Bw * nn;
-    n_lines = Bw * per;
+    const int x0 = bx * bw;
+    ncols = min(bw, g.N[0] - x0);
+    const int64_t gbase = a == 1 ? kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)NN
+                                 : kc_base + (other * g.N[0] + x0) * (int64_t)NN;
+    const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
+    copy_cols<T, NN, true>(f, tile, gbase, rowstride, ncols, Na, CS);
   }
-
-  copy_tile<T, true>(f, tile, rowbase, rowstride, R, Na);
   __syncthreads();
 
-  int ns = 1;
-  for (int ax = 0; ax < a; ++ax) ns *= P;
-
+  // ----------------------------------------------------------- compute
   T C[P][P], e1[P], eth[P];
 #pragma unroll
   for (int r = 0; r < P; ++r) {
@@ -488,133 +717,69 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
   const int lil = lane % LPL2;
   const int slot = lane / LPL2;
   const int lbase = slot * LPL2;
-  const int j0 = lil * Q;
-  const int Ls = S / Q;          // lanes per subdomain (Q divides S)
-  const int sl = lil % Ls;       // lane index inside its subdomain
-  const int s_me = lil / Ls;
-  const int s_up = s_me == 0 ? nseg - 1 : s_me - 1;
-  const int end_up = lbase + (s_up + 1) * Ls - 1;  // lane holding the upwind subdomain's end
-  const int src_prev = lbase + (lil == 0 ? NL - 1 : lil - 1);
-  const bool dpp_ok = Ls <= 16 && (16 % Ls) == 0;  // subdomains never straddle a 16-lane row
-  const T gQ = powi(gg, Q);
-
-  for (int lb = wave * LW; lb < n_lines; lb += nwaves * LW) {
-    const int l = lb + slot;
-    const bool act = (l < n_lines) && (lil < NL);
-    const int xl = act ? l / per : 0;
-    const int on = act ? l % per : 0;
-    const int loff = xl * nn + other_node_offset(on, a, P, g.dim);
-
-    T fo[kMaxQ][P];
-#pragma unroll
-    for (int q = 0; q < kMaxQ; ++q) {
-      const int j = j0 + q;
-      const int r = sg > 0 ? j : Na - 1 - j;
-#pragma unroll
-      for (int b = 0; b < P; ++b) {
-        const int pb = sg > 0 ? b : P - 1 - b;
-        fo[q][b] = (act && q < Q) ? tile[r * R + loff + pb * ns] : T(0);
-      }
-    }
-    T last_old = T(0);
-#pragma unroll
-    for (int q = 0; q < kMaxQ; ++q)
-      if (q == Q - 1) last_old = fo[q][P - 1];
-    // old-time inflow of my first cell: outflow node of the upwind cell
-    const T t_old0 = __shfl(last_old, src_prev, 64);
-
-    // zero-inflow recurrence over my cells: x <- beta + g x, x = 0 entering
-    // my chunk; mB = value leaving my chunk.
-    T beta[kMaxQ];
-    T mB = T(0);
-    {
-      T to = t_old0;
-#pragma unroll
-      for (int q = 0; q < kMaxQ; ++q) {
-        if (q < Q) {
-          T bq = e1[P - 1] * to;
-#pragma unroll
-          for (int c = 0; c < P; ++c) bq += C[P - 1][c] * fo[q][c];
-          beta[q] = bq;
-          mB = gg * mB + bq;
-          to = fo[q][P - 1];
-        } else {
-          beta[q] = T(0);
-        }
-      }
-    }
-    // segmented inclusive scan over the lanes of each subdomain: a window of
-    // `off` lanes that does not reach the subdomain start multiplies the
-    // incoming value by g^(Q off)
-    {
-      T gw = gQ;
-      if (dpp_ok) {
-#define KDS_SCAN_STEP(OFF)                                  \
-  if ((OFF) < Ls) {                                         \
-    const T pB = dpp_row_shr<T, (OFF)>(mB);                 \
-    if (sl >= (OFF)) mB = gw * pB + mB;                     \
-    gw = gw * gw;                                           \
+  LineLane ln;
+  ln.Q = Q;
+  ln.Ls = S / Q;
+  ln.sl = lil % ln.Ls;
+  {
+    const int s_me = lil / ln.Ls;
+    const int s_up = s_me == 0 ? nseg - 1 : s_me - 1;
+    ln.end_up = lbase + (s_up + 1) * ln.Ls - 1;
   }
-        KDS_SCAN_STEP(1)
-        KDS_SCAN_STEP(2)
-        KDS_SCAN_STEP(4)
-        KDS_SCAN_STEP(8)
-#undef KDS_SCAN_STEP
-      } else {
-        for (int off = 1; off < Ls; off <<= 1) {
-          const T pB = __shfl_up(mB, off, LPL2);
-          if (sl >= off) mB = gw * pB + mB;
-          gw = gw * gw;
-        }
-      }
-    }
-    T x_in = dpp_ok ? dpp_row_shr<T, 1>(mB) : __shfl_up(mB, 1, LPL2);
-    if (sl == 0) x_in = T(0);
+  ln.src_prev = lbase + (lil == 0 ? NL - 1 : lil - 1);
+  ln.dpp_ok = ln.Ls <= 16 && (16 % ln.Ls) == 0;
+  const int j0 = lil * Q;
 
-    T qv[kMaxQ];
-    {
-      T x = x_in;
+  for (int cb = wave * LW; cb < ncols; cb += nwaves * LW) {
+    const int c = cb + slot;
+    const bool act = (c < ncols) && (lil < NL);
+    // my cells in downwind order: physical cells j0.. (SIGN > 0) or
+    // Na-1-j0 downwards (SIGN < 0)
+    const int cbase = (act ? c : 0) * CS;
+    // (lanes without a line and cells past Q re-read cell 0 of the column;
+    // those values are never used)
+    T d[QMAX][NN];
 #pragma unroll
-      for (int q = 0; q < kMaxQ; ++q) {
-        qv[q] = x;
-        if (q < Q) x = beta[q] + gg * x;
-      }
+    for (int q = 0; q < QMAX; ++q) {
+      const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
+#pragma unroll
+      for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
     }
-    // subdomain iteration on the outflow values (meaningful on end lanes,
-    // where mB is the zero-inflow outflow P_s of the subdomain)
-    const T Pseg = mB;
-    T Tv = last_old;
-    for (int it = 1; it < g.K; ++it) {
-      const T up = __shfl(Tv, end_up, 64);
-      Tv = Pseg + G * up;
+    switch (a * 2 + (sg > 0 ? 1 : 0)) {
+      case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
     }
-    const T t_in = __shfl(Tv, end_up, 64);
-
     if (act) {
-      T gp = powi(gg, j0 % S);
-      T to = t_old0;
 #pragma unroll
-      for (int q = 0; q < kMaxQ; ++q) {
+      for (int q = 0; q < QMAX; ++q) {
         if (q < Q) {
-          const T tn = qv[q] + gp * t_in;
-          const int j = j0 + q;
-          const int r = sg > 0 ? j : Na - 1 - j;
+          const int row = sg > 0 ? j0 + q : Na - 1 - j0 - q;
 #pragma unroll
-          for (int b = 0; b < P; ++b) {
-            T s = e1[b] * to + eth[b] * tn;
-#pragma unroll
-            for (int c = 0; c < P; ++c) s += C[b][c] * fo[q][c];
-            const int pb = sg > 0 ? b : P - 1 - b;
-            tile[r * R + loff + pb * ns] = s;
-          }
-          to = fo[q][P - 1];
-          gp *= gg;
+          for (int n = 0; n < NN; ++n) tile[cbase + row * NN + n] = d[q][n];
         }
       }
     }
   }
   __syncthreads();
-  copy_tile<T, false>(f, tile, rowbase, rowstride, R, Na);
+
+  // -------------------------------------------------------- write back
+  if (a == 0) {
+    const int64_t col0 = bundle * bw;
+    copy_tile<T, false>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
+  } else {
+    const int nbx = (g.N[0] + bw - 1) / bw;
+    const int bx = (int)(bundle % nbx);
+    const int64_t other = bundle / nbx;
+    const int x0 = bx * bw;
+    const int64_t gbase = a == 1 ? kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)NN
+                                 : kc_base + (other * g.N[0] + x0) * (int64_t)NN;
+    const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
+    copy_cols<T, NN, false>(f, tile, gbase, rowstride, ncols, Na, CS);
+  }
 }
 
 // ============================================================ launchers
@@ -729,16 +894,16 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
   const SweepTab<T>& t = *(const SweepTab<T>*)tab;
   const int64_t nblocks = plan.block_start[g.nv * g.m];
   const size_t lds = (size_t)plan.lds_elems * sizeof(T);
-  switch (g.P) {
-#define KDS_LINE(PP)                                                                            \
-  case PP:                                                                                      \
-    hipLaunchKernelGGL((k_sweep_line<T, PP>), dim3((unsigned)nblocks), dim3(plan.threads), lds, s, \
-                       (T*)f, g, t, plan);                                                      \
+  const int key = g.P * 10 + g.dim;
+  switch (key) {
+#define KDS_LINE(PP, DD)                                                                        \
+  case PP * 10 + DD:                                                                            \
+    hipLaunchKernelGGL((k_sweep_line<T, PP, DD>), dim3((unsigned)nblocks), dim3(plan.threads),  \
+                       lds, s, (T*)f, g, t, plan);                                              \
     break;
-    KDS_LINE(1)
-    KDS_LINE(2)
-    KDS_LINE(3)
-    KDS_LINE(4)
+    KDS_LINE(1, 1) KDS_LINE(2, 1) KDS_LINE(3, 1) KDS_LINE(4, 1)
+    KDS_LINE(1, 2) KDS_LINE(2, 2) KDS_LINE(3, 2) KDS_LINE(4, 2)
+    KDS_LINE(1, 3) KDS_LINE(2, 3) KDS_LINE(3, 3) KDS_LINE(4, 3)
 #undef KDS_LINE
     default:
       return hipErrorInvalidValue;

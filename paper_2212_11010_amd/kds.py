@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": KDS_FP64, "fp32": KDS_FP32, "fp32_split_f16": KDS_FP32_SPL
               "fp32_split_bf16": KDS_FP32_SPLIT_BF16}
 SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED_LINE}
 N_KERNEL_KINDS = 2
-EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_moments",
+EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error"]
 
@@ -46,9 +46,10 @@ class kds_config(C.Structure):
 class kds_info_t(C.Structure):
     _fields_ = [
         ("n_unknowns", C.c_int64), ("state_bytes", C.c_int64), ("schedule", C.c_int32),
-        ("precision", C.c_int32), ("steps_done", C.c_int32), ("cells_per_lane", C.c_int32),
+        ("precision", C.c_int32), ("steps_done", C.c_int32),
         ("max_kinetic_courant", C.c_double), ("min_subdomain_width", C.c_double),
-        ("proposition_ok", C.c_int32),
+        ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
+        ("tuned", C.c_int32),
     ]
 
 
@@ -73,6 +74,7 @@ def lib():
         L.kds_set_state.argtypes = [vp, vp, C.c_int32]
         L.kds_step.argtypes = [vp, C.c_int32]
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
+        L.kds_tune.argtypes = [vp, C.c_int32, dp]
         L.kds_moments.argtypes = [vp, vp, C.c_int32]
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_set_kinetic.argtypes = [vp, vp, C.c_int32]
@@ -188,6 +190,12 @@ def kds_step_timed(h, n_steps=1):
     return list(out)
 
 
+def kds_tune(h, reps=3):
+    best = C.c_double(0.0)
+    _check(lib().kds_tune(h, int(reps), C.byref(best)), h)
+    return best.value
+
+
 def kds_moments(h, out, nbytes):
     ptr, dev = _buf(out, nbytes)
     _check(lib().kds_moments(h, ptr, dev), h)
@@ -220,7 +228,11 @@ def kds_synchronize(h):
 def kds_info(h):
     info = kds_info_t()
     _check(lib().kds_info(h, C.byref(info)), h)
-    return {name: getattr(info, name) for name, _ in kds_info_t._fields_}
+    out = {}
+    for name, _ in kds_info_t._fields_:
+        v = getattr(info, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
 
 
 def kds_destroy(h):
@@ -272,6 +284,9 @@ class Problem:
 
     def step_timed(self, n=1):
         return kds_step_timed(self.h, n)
+
+    def tune(self, reps=3):
+        return kds_tune(self.h, reps)
 
     def moments(self, out=None):
         if out is None:

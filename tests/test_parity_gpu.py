@@ -67,9 +67,18 @@ def relerr(a, b):
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec,sched", MODES)
 def test_parity_against_oracle(name, prec, sched):
+    from paper_2212_11010_amd import kds
     spec, W0, Fref, Wref = case(name)
     print("case", name, prec, sched, spec["n_cells"], spec["sub_cells"], flush=True)
-    W, F = run_gpu(spec, W0, prec, sched)
+    try:
+        W, F = run_gpu(spec, W0, prec, sched)
+    except kds.KdsError as e:
+        # FP64 cells of 64 nodes exceed the line kernel's register budget;
+        # the library refuses the schedule rather than spilling
+        if e.status == kds.KDS_E_UNSUPPORTED and prec == "fp64" and spec["degree"] == 3 \
+                and spec["dim"] == 3:
+            pytest.skip(str(e))
+        raise
     ew, ef = relerr(W, Wref), relerr(F, Fref)
     print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
     assert ew <= TOL[prec] and ef <= TOL[prec], (ew, ef)
@@ -171,3 +180,22 @@ def test_nonfinite_state_is_reported():
         F[1, 5, 2, 0] = np.nan
         pb.set_kinetic(F)
         assert not pb.check_finite()
+
+
+@pytest.mark.parametrize("name", ["cfg2_ragged", "cfg3_small", "cfg1_odd"])
+def test_autotuned_plan_restores_state_and_keeps_parity(name):
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, Fref, Wref = case(name)
+    with kds.Problem(spec, precision="fp32", schedule="line") as pb:
+        pb.set_state(torch.from_numpy(W0).cuda())
+        F0 = pb.get_kinetic()
+        ms = pb.tune(2)
+        info = pb.info()
+        assert ms > 0 and info["tuned"] == 1
+        assert np.array_equal(pb.get_kinetic(), F0)   # tuning leaves the state as it was
+        pb.step(spec["steps"])
+        W = pb.moments()
+        F = pb.get_kinetic()
+    print("tuned", name, info["line_Q"], info["line_bw"], "%.4f ms" % ms, flush=True)
+    assert relerr(W, Wref) <= TOL["fp32"] and relerr(F, Fref) <= TOL["fp32"]
