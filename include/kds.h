@@ -96,10 +96,21 @@ typedef struct {
   double omega;          /* relaxation parameter, 0 <= omega <= 2 (Sec. 2.2) */
   double dt;             /* time step, > 0 */
   double theta;          /* 1/2 = Crank-Nicolson, 1 = implicit Euler; in [1/2, 1] */
-  int32_t n_iter;        /* subdomain iterations K >= 1 (Sec. 5.1) */
+  int32_t n_iter;        /* subdomain iterations K >= 1 (Sec. 5.1); 0 = the converged
+                            limit K -> infinity (fully implicit periodic solve;
+                            line schedule only) */
   int32_t precision;     /* kds_prec */
   int32_t schedule;      /* kds_schedule */
+  const double* source_sigma; /* m damping rates sigma_c >= 0 (+inf allowed) of the
+                                 source S(W)_c = -sigma_c W_c, or NULL (no source) */
 } kds_config;
+/* Source term (Sec. 2.3): the conservative data after the transport are
+ * advanced by the Crank-Nicolson step of dW/dt = S(W) (eq:source_term_application_to_W),
+ * W+_c = mu_c W_c with mu_c = (1 - sigma_c dt/2)/(1 + sigma_c dt/2) (mu_c = -1 for
+ * sigma_c = +inf, the perfect-conductor limit); the kinetic data take the
+ * equilibrium part of that change, F_k += M_k(W+) - M_k(W), then relax towards
+ * M_k(W+).  This keeps sum_k F_k = W+ (a reading: the paper defers the
+ * kinetic details to its reference on the method). */
 /* Equilibria (eq:maxwell_def): M_k(W) = eq_a[k] W + sum_i eq_b[k*dim+i] Q^i(W).
  * With eq_a = eq_b = NULL the minimum-norm weights satisfying the moment
  * conditions for every W are used (for +-lambda e_i: M = W/(2d) +- Q^i/(2 lambda)). */
@@ -135,6 +146,13 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * (*sweep_ms = -1).  sweep_ms (nullable): best average sweep time.  Needs
  * one state's worth of free device memory (else KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
+
+/* Average duration of one launch of each kernel kind (sweep: the line kernel,
+ * or one plain subdomain iteration; relax), from HIP events around reps
+ * back-to-back launches on the problem's stream; the state is saved before
+ * and restored after (needs one state's worth of free device memory).
+ * kernel_ms[KDS_N_KERNEL_KINDS].  For measurement. */
+kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms);
 
 /* W = sum_k F_k (FP64, Sec. 2.2 step 3) into W_out [cell][node][c]. */
 kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device);

@@ -34,6 +34,7 @@
 // Layouts (all FP64):
 //   W   [cell][node][c]           cells x-fastest, nodes x-fastest
 //   F   [k][c][cell][node]        oracle-internal kinetic layout
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -63,7 +64,8 @@ typedef struct {
   double omega;
   double dt;
   double theta;
-  int32_t n_iter;        // K >= 1
+  int32_t n_iter;        // K >= 1; 0 = iterate to convergence
+  const double* source_sigma;  // m damping rates sigma_c >= 0 (may be +inf), or NULL
 } orc_config;
 
 }  // extern "C"
@@ -410,7 +412,14 @@ int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
   std::vector<double> A(nn * nn), rhs(nn), rold(nn);
   int nsub[3];
   for (int a = 0; a < 3; ++a) nsub[a] = g.N[a] / g.S[a];
-  for (int it = 1; it <= K; ++it) {
+  // K = 0: iterate until the iterates stop changing (the limit K -> infinity,
+  // the fully implicit solve): the change falls to rounding level, or stops
+  // decreasing for 20 iterates; cap 10000 iterates
+  const bool converge = K == 0;
+  const int kmax = converge ? 10000 : K;
+  double best_diff = 1e300;
+  int stalled = 0;
+  for (int it = 1; it <= kmax; ++it) {
     std::fill(done.begin(), done.end(), 0);
     for (int s2 = 0; s2 < nsub[2]; ++s2)
       for (int s1 = 0; s1 < nsub[1]; ++s1)
@@ -469,7 +478,19 @@ int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
             done[cell] = 1;
           }
         }
-    prev.swap(cur);
+    if (converge) {
+      double diff = 0.0, scale = 0.0;
+      for (long i = 0; i < total; ++i) {
+        diff = std::max(diff, std::fabs(cur[i] - prev[i]));
+        scale = std::max(scale, std::fabs(cur[i]));
+      }
+      prev.swap(cur);
+      if (diff <= 2e-16 * scale) break;
+      if (diff < best_diff) { best_diff = diff; stalled = 0; }
+      else if (++stalled >= 20 && diff <= 1e-12 * scale) break;
+    } else {
+      prev.swap(cur);
+    }
   }
   std::memcpy(f_new, prev.data(), total * sizeof(double));
   return 0;
@@ -477,7 +498,7 @@ int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
 
 int validate(const orc_config* c) {
   if (!c || c->dim < 1 || c->dim > 3 || c->degree < 0 || c->degree > 5) return 1;
-  if (c->m < 1 || c->n_vel < 1 || c->n_iter < 1 || !(c->dt > 0)) return 1;
+  if (c->m < 1 || c->n_vel < 1 || c->n_iter < 0 || !(c->dt > 0)) return 1;
   for (int a = 0; a < c->dim; ++a) {
     if (c->n_cells[a] < 1 || c->sub_cells[a] < 1) return 1;
     if (c->n_cells[a] % c->sub_cells[a]) return 1;
@@ -546,24 +567,40 @@ int orc_moments(const orc_config* c, const double* F, double* W) {
 
 // Relaxation at every node (eq:over_relaxation):
 //   W = sum_k F_k;  F_k <- omega M_k(W) + (1 - omega) F_k.
+// With a source S(W) = -sigma_c W_c (per component), step 3 of the kinetic
+// algorithm (Sec. 2.3) first replaces W by the Crank-Nicolson solution of
+// dW/dt = S(W) over dt (eq:source_term_application_to_W):
+//   W+_c = mu_c W_c,  mu_c = (1 - sigma_c dt/2) / (1 + sigma_c dt/2)
+// (mu_c = -1 for sigma_c = +inf, the perfect-conductor limit), and the kinetic
+// data follow the equilibrium part of that change, F_k += M_k(W+) - M_k(W),
+// so that sum_k F_k = W+ before the relaxation towards M_k(W+).
 int orc_relax(const orc_config* c, double* F) {
   if (validate(c)) return 1;
   long nc = ncell_of(c);
   int nn = nn_of(c), m = c->m, nv = c->n_vel;
-  std::vector<double> W(m), M(nv * m);
+  std::vector<double> W(m), Wp(m), M(nv * m), Mp(nv * m), mu(m, 1.0);
   double om = c->omega;
+  bool src = c->source_sigma != nullptr;
+  if (src)
+    for (int r = 0; r < m; ++r) {
+      double sg = c->source_sigma[r];
+      mu[r] = std::isinf(sg) ? -1.0 : (1.0 - 0.5 * sg * c->dt) / (1.0 + 0.5 * sg * c->dt);
+    }
   for (long cell = 0; cell < nc; ++cell)
     for (int i = 0; i < nn; ++i) {
       for (int r = 0; r < m; ++r) {
         double s = 0.0;
         for (int k = 0; k < nv; ++k) s += F[((long)(k * m + r) * nc + cell) * nn + i];
         W[r] = s;
+        Wp[r] = mu[r] * s;
       }
-      if (orc_equilibrium(c, W.data(), M.data())) return 1;
+      if (orc_equilibrium(c, Wp.data(), Mp.data())) return 1;
+      if (src && orc_equilibrium(c, W.data(), M.data())) return 1;
       for (int k = 0; k < nv; ++k)
         for (int r = 0; r < m; ++r) {
           double& f = F[((long)(k * m + r) * nc + cell) * nn + i];
-          f = om * M[k * m + r] + (1.0 - om) * f;
+          if (src) f += Mp[k * m + r] - M[k * m + r];
+          f = om * Mp[k * m + r] + (1.0 - om) * f;
         }
     }
   return 0;

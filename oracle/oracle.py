@@ -39,7 +39,7 @@ class _Cfg(C.Structure):
         ("n_vel", C.c_int32), ("vel", C.POINTER(C.c_double)),
         ("eq_a", C.POINTER(C.c_double)), ("eq_b", C.POINTER(C.c_double)),
         ("omega", C.c_double), ("dt", C.c_double), ("theta", C.c_double),
-        ("n_iter", C.c_int32),
+        ("n_iter", C.c_int32), ("source_sigma", C.POINTER(C.c_double)),
     ]
 
 
@@ -89,6 +89,8 @@ class Config:
         self._vel = np.ascontiguousarray(spec["vel"], dtype=np.float64)
         self._eqa = None if spec.get("eq_a") is None else np.ascontiguousarray(spec["eq_a"], dtype=np.float64)
         self._eqb = None if spec.get("eq_b") is None else np.ascontiguousarray(spec["eq_b"], dtype=np.float64)
+        self._src = None if spec.get("source_sigma") is None else np.ascontiguousarray(
+            spec["source_sigma"], dtype=np.float64)
         c = _Cfg()
         c.dim = d
         for a in range(3):
@@ -109,6 +111,7 @@ class Config:
         c.dt = spec["dt"]
         c.theta = spec.get("theta", 0.5)
         c.n_iter = spec.get("n_iter", 3)
+        c.source_sigma = _dp(self._src) if self._src is not None else C.POINTER(C.c_double)()
         self.c = c
 
     @property

@@ -117,14 +117,16 @@ kds_status validate(const kds_config* c, std::string& msg) {
   if (!(c->omega >= 0.0 && c->omega <= 2.0)) { msg = "omega must be in [0, 2]"; return KDS_E_INVALID; }
   if (!(c->dt > 0.0) || !finite(c->dt)) { msg = "dt must be > 0"; return KDS_E_INVALID; }
   if (!(c->theta >= 0.5 && c->theta <= 1.0)) { msg = "theta must be in [1/2, 1]"; return KDS_E_INVALID; }
-  if (c->n_iter < 0) { msg = "n_iter must be >= 1"; return KDS_E_INVALID; }
-  if (c->n_iter == 0) { msg = "n_iter = 0 (iterate to convergence) is not implemented"; return KDS_E_UNSUPPORTED; }
+  if (c->n_iter < 0) { msg = "n_iter must be >= 0"; return KDS_E_INVALID; }
   if (c->precision == KDS_FP32_SPLIT_F16 || c->precision == KDS_FP32_SPLIT_BF16) {
     msg = "split-precision storage is not implemented";
     return KDS_E_UNSUPPORTED;
   }
   if (c->precision != KDS_FP64 && c->precision != KDS_FP32) { msg = "unknown precision"; return KDS_E_INVALID; }
   if (c->schedule < KDS_SCHED_AUTO || c->schedule > KDS_SCHED_LINE) { msg = "unknown schedule"; return KDS_E_INVALID; }
+  if (c->source_sigma)
+    for (int r = 0; r < c->m; ++r)
+      if (!(c->source_sigma[r] >= 0.0)) { msg = "source_sigma must be >= 0 (or +inf)"; return KDS_E_INVALID; }
   for (int k = 0; k < c->n_vel; ++k) {
     int nz = 0;
     for (int a = 0; a < c->dim; ++a) nz += c->vel[k * c->dim + a] != 0.0;
@@ -390,7 +392,15 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_INVALID, msg);
   }
-  if (!build_eq_blob(p->law, p->dim, p->m, p->nv, p->law_params, a, b, p->omega, p->eq_blob)) {
+  std::vector<double> mu;
+  if (cfg->source_sigma) {
+    mu.resize(p->m);
+    for (int r = 0; r < p->m; ++r) {
+      const double sg = cfg->source_sigma[r];
+      mu[r] = std::isinf(sg) ? -1.0 : (1.0 - 0.5 * sg * p->dt) / (1.0 + 0.5 * sg * p->dt);
+    }
+  }
+  if (!build_eq_blob(p->law, p->dim, p->m, p->nv, p->law_params, a, b, p->omega, mu, p->eq_blob)) {
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED,
                 "no compiled relaxation kernel for this (law, dim, m, n_vel) combination");
@@ -435,9 +445,15 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   // values (64-node cells): the line kernel's occupancy is too low there.
   const bool line_preferred = line_qmax((int)p->elem, p->nn) * p->nn <= 64;
   p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok ||
-              (cfg->schedule == KDS_SCHED_AUTO && !line_preferred))
+              (cfg->schedule == KDS_SCHED_AUTO && !line_preferred && p->K > 0))
                  ? KDS_SCHED_PLAIN
                  : KDS_SCHED_LINE;
+  if (p->K == 0 && p->sched != KDS_SCHED_LINE) {
+    delete p;
+    return fail(nullptr, KDS_E_UNSUPPORTED,
+                "n_iter = 0 (converged subdomain iteration) needs the line schedule" +
+                    (why.empty() ? std::string() : ": " + why));
+  }
 
   // ---------------------------------------------------------------- device
   hipError_t e = hipGetDevice(&p->device);
@@ -627,6 +643,47 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   p->graph = nullptr;
   p->tuned = true;
   if (sweep_ms) *sweep_ms = best;
+  return KDS_OK;
+}
+
+kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!kernel_ms || reps < 1) return fail(p, KDS_E_INVALID, "bad arguments");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_time_kernels needs a state");
+  const size_t bytes = (size_t)p->n_unknowns() * p->elem;
+  void* save = nullptr;
+  if (hipMalloc(&save, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, KDS_E_NOMEM, "kds_time_kernels: no device memory to save the state");
+  }
+  const Geom& g = p->geom;
+  hipError_t e = hipMemcpyAsync(save, p->f, bytes, hipMemcpyDeviceToDevice, p->stream);
+  float ms[2] = {0, 0};
+  for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+    auto launch = [&]() -> hipError_t {
+      if (kind == 0) {
+        if (p->sched == KDS_SCHED_LINE)
+          return launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream);
+        // one plain subdomain iteration (the kernel a step launches n_iter times)
+        return launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, p->f_tmp, nullptr,
+                                  p->tr[0], p->stream);
+      }
+      return launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream);
+    };
+    e = launch();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(p->ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[kind], p->ev[0], p->ev[1]);
+  }
+  hipError_t e2 = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(p->stream);
+  (void)hipFree(save);
+  if (e != hipSuccess) return hip_fail(p, e, "kds_time_kernels");
+  if (e2 != hipSuccess) return hip_fail(p, e2, "kds_time_kernels restore");
+  kernel_ms[0] = ms[0] / reps;
+  kernel_ms[1] = ms[1] / reps;
   return KDS_OK;
 }
 

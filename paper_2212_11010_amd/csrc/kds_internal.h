@@ -75,6 +75,8 @@ struct EqTab {
   double b[NV][D];
   double omega;
   double gamma;       // Euler
+  double mu[M];       // Crank-Nicolson source factors W+_c = mu_c W_c
+  int has_source;
 };
 
 // Most cells per lane the line kernel keeps in registers (a budget of 64
@@ -114,6 +116,6 @@ hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const Lin
 // compiled kernel.
 bool build_eq_blob(int law, int dim, int m, int nv, const std::vector<double>& law_params,
                    const std::vector<double>& a, const std::vector<double>& b, double omega,
-                   std::vector<unsigned char>& blob);
+                   const std::vector<double>& mu, std::vector<unsigned char>& blob);
 
 }  // namespace kds

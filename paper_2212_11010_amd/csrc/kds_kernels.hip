@@ -137,7 +137,21 @@ __global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t pl
       w[r] += fv[k][r];
     }
   double Mk[NV][M];
-  equilibrium<LAW, D, M, NV>(t, w, Mk);
+  if (t.has_source) {
+    // Crank-Nicolson source step on W; the kinetic data take the equilibrium
+    // part of the change so that sum_k f_k = W+ before relaxing towards M(W+)
+    double Mm[NV][M];
+    equilibrium<LAW, D, M, NV>(t, w, Mm);
+#pragma unroll
+    for (int r = 0; r < M; ++r) w[r] *= t.mu[r];
+    equilibrium<LAW, D, M, NV>(t, w, Mk);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) fv[k][r] += Mk[k][r] - Mm[k][r];
+  } else {
+    equilibrium<LAW, D, M, NV>(t, w, Mk);
+  }
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -519,6 +533,7 @@ __device__ constexpr int node_of(int o, int b) {
 
 struct LineLane {
   int Q, Ls, sl, end_up, src_prev;
+  int nseg, s_me, lbase;
   bool dpp_ok;
 };
 
@@ -591,28 +606,49 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
       }
     }
   }
-  // subdomain iteration on the outflows (meaningful on subdomain-end lanes)
-  T Tv[PER];
+  // subdomain iteration on the outflows (meaningful on subdomain-end lanes):
+  // T_s^p = P_s + G T_{s-1}^{p-1}, inflow of iterate K = T_{s-1}^{K-1}.
+  // K = 0: the converged limit, T_s = sum_q G^q P_{s-q} / (1 - G^nseg)
+  // (the fully implicit periodic line solve).
+  T t_in[PER];
+  if (K > 0) {
+    T Tv[PER];
 #pragma unroll
-  for (int o = 0; o < PER; ++o) Tv[o] = last_old[o];
-  for (int it = 1; it < K; ++it) {
+    for (int o = 0; o < PER; ++o) Tv[o] = last_old[o];
+    for (int it = 1; it < K; ++it) {
 #pragma unroll
-    for (int o = 0; o < PER; ++o) {
-      const T up = __shfl(Tv[o], ln.end_up, 64);
-      Tv[o] = mB[o] + G * up;
+      for (int o = 0; o < PER; ++o) {
+        const T up = __shfl(Tv[o], ln.end_up, 64);
+        Tv[o] = mB[o] + G * up;
+      }
     }
+#pragma unroll
+    for (int o = 0; o < PER; ++o) t_in[o] = __shfl(Tv[o], ln.end_up, 64);
+  } else {
+#pragma unroll
+    for (int o = 0; o < PER; ++o) t_in[o] = T(0);
+    T Gq = T(1);
+    for (int q = 0; q < ln.nseg; ++q) {
+      const int s_src = ((ln.s_me - 1 - q) % ln.nseg + ln.nseg) % ln.nseg;
+      const int src = ln.lbase + (s_src + 1) * ln.Ls - 1;
+#pragma unroll
+      for (int o = 0; o < PER; ++o) t_in[o] += Gq * __shfl(mB[o], src, 64);
+      Gq *= G;
+    }
+    const T inv = T(1) / (T(1) - Gq);
+#pragma unroll
+    for (int o = 0; o < PER; ++o) t_in[o] *= inv;
   }
   const T g0 = powi(gg, ln.sl * ln.Q);
 #pragma unroll
   for (int o = 0; o < PER; ++o) {
-    const T t_in = __shfl(Tv[o], ln.end_up, 64);
     T x = ln.dpp_ok ? dpp_row_shr<T, 1>(mB[o]) : __shfl_up(mB[o], 1, 64);
     if (ln.sl == 0) x = T(0);
     T gp = g0, to = t_old0[o];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       if (q < ln.Q) {
-        const T tn = x + gp * t_in;
+        const T tn = x + gp * t_in[o];
         const T to_next = d[q][KDS_ND(o, P - 1)];
         T fn[P];
 #pragma unroll
@@ -721,9 +757,11 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
   ln.Q = Q;
   ln.Ls = S / Q;
   ln.sl = lil % ln.Ls;
+  ln.nseg = nseg;
+  ln.lbase = lbase;
+  ln.s_me = lil / ln.Ls;
   {
-    const int s_me = lil / ln.Ls;
-    const int s_up = s_me == 0 ? nseg - 1 : s_me - 1;
+    const int s_up = ln.s_me == 0 ? nseg - 1 : ln.s_me - 1;
     ln.end_up = lbase + (s_up + 1) * ln.Ls - 1;
   }
   ln.src_prev = lbase + (lil == 0 ? NL - 1 : lil - 1);
@@ -792,7 +830,8 @@ template <int LAW, int D, int M, int NV>
 struct EqCombo {
   using Tab = EqTab<D, M, NV>;
   static bool build(const std::vector<double>& lp, const std::vector<double>& a,
-                    const std::vector<double>& b, double omega, std::vector<unsigned char>& blob) {
+                    const std::vector<double>& b, double omega, const std::vector<double>& mu,
+                    std::vector<unsigned char>& blob) {
     Tab t{};
     if (LAW == KDS_LAW_LINEAR) {
       if ((int)lp.size() < D * M * M) return false;
@@ -808,6 +847,8 @@ struct EqCombo {
       for (int i = 0; i < D; ++i) t.b[k][i] = b[k * D + i];
     }
     t.omega = omega;
+    t.has_source = mu.empty() ? 0 : 1;
+    for (int r = 0; r < M; ++r) t.mu[r] = mu.empty() ? 1.0 : mu[r];
     blob.resize(sizeof(Tab));
     std::memcpy(blob.data(), &t, sizeof(Tab));
     return true;
@@ -831,7 +872,7 @@ struct EqCombo {
 struct ComboEntry {
   int law, dim, m, nv;
   bool (*build)(const std::vector<double>&, const std::vector<double>&, const std::vector<double>&,
-                double, std::vector<unsigned char>&);
+                double, const std::vector<double>&, std::vector<unsigned char>&);
   hipError_t (*init64)(const Geom&, const void*, const double*, void*, hipStream_t);
   hipError_t (*init32)(const Geom&, const void*, const double*, void*, hipStream_t);
   hipError_t (*relax64)(const Geom&, const void*, const void*, void*, hipStream_t);
@@ -915,10 +956,10 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
 
 bool build_eq_blob(int law, int dim, int m, int nv, const std::vector<double>& law_params,
                    const std::vector<double>& a, const std::vector<double>& b, double omega,
-                   std::vector<unsigned char>& blob) {
+                   const std::vector<double>& mu, std::vector<unsigned char>& blob) {
   const ComboEntry* c = find_combo(law, dim, m, nv);
   if (!c) return false;
-  return c->build(law_params, a, b, omega, blob);
+  return c->build(law_params, a, b, omega, mu, blob);
 }
 
 // The combination was validated by build_eq_blob at create time.

@@ -25,7 +25,8 @@ PRECISIONS = {"fp64": KDS_FP64, "fp32": KDS_FP32, "fp32_split_f16": KDS_FP32_SPL
               "fp32_split_bf16": KDS_FP32_SPLIT_BF16}
 SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED_LINE}
 N_KERNEL_KINDS = 2
-EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune", "kds_moments",
+EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune",
+            "kds_time_kernels", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error"]
 
@@ -40,6 +41,7 @@ class kds_config(C.Structure):
         ("eq_a", C.POINTER(C.c_double)), ("eq_b", C.POINTER(C.c_double)),
         ("omega", C.c_double), ("dt", C.c_double), ("theta", C.c_double),
         ("n_iter", C.c_int32), ("precision", C.c_int32), ("schedule", C.c_int32),
+        ("source_sigma", C.POINTER(C.c_double)),
     ]
 
 
@@ -75,6 +77,7 @@ def lib():
         L.kds_step.argtypes = [vp, C.c_int32]
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_tune.argtypes = [vp, C.c_int32, dp]
+        L.kds_time_kernels.argtypes = [vp, C.c_int32, dp]
         L.kds_moments.argtypes = [vp, vp, C.c_int32]
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_set_kinetic.argtypes = [vp, vp, C.c_int32]
@@ -111,6 +114,8 @@ def make_config(spec: dict, precision="fp32", schedule="auto"):
         "vel": np.ascontiguousarray(spec["vel"], dtype=np.float64),
         "eq_a": None if spec.get("eq_a") is None else np.ascontiguousarray(spec["eq_a"], dtype=np.float64),
         "eq_b": None if spec.get("eq_b") is None else np.ascontiguousarray(spec["eq_b"], dtype=np.float64),
+        "source_sigma": None if spec.get("source_sigma") is None else np.ascontiguousarray(
+            spec["source_sigma"], dtype=np.float64),
     }
     c = kds_config()
     c.dim = d
@@ -135,6 +140,8 @@ def make_config(spec: dict, precision="fp32", schedule="auto"):
     c.n_iter = int(spec.get("n_iter", 3))
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    c.source_sigma = (_dptr(keep["source_sigma"]) if keep["source_sigma"] is not None
+                      else C.POINTER(C.c_double)())
     return c, keep
 
 
@@ -194,6 +201,12 @@ def kds_tune(h, reps=3):
     best = C.c_double(0.0)
     _check(lib().kds_tune(h, int(reps), C.byref(best)), h)
     return best.value
+
+
+def kds_time_kernels(h, reps=10):
+    out = (C.c_double * N_KERNEL_KINDS)()
+    _check(lib().kds_time_kernels(h, int(reps), out), h)
+    return list(out)
 
 
 def kds_moments(h, out, nbytes):
@@ -287,6 +300,9 @@ class Problem:
 
     def tune(self, reps=3):
         return kds_tune(self.h, reps)
+
+    def time_kernels(self, reps=10):
+        return kds_time_kernels(self.h, reps)
 
     def moments(self, out=None):
         if out is None:

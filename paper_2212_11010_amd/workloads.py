@@ -172,7 +172,7 @@ def euler_speeds(W, d, gamma=1.4):
 
 def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=None,
                   beta=None, omega=None, n_iter=3, theta=0.5, seed=None,
-                  precision="fp32"):
+                  precision="fp32", source_sigma=None):
     """Return (spec, W0) for workload ``cfg`` (1..4), optionally resized.
 
     spec is a plain dict (problem description); W0 has shape [cell, node, m].
@@ -233,6 +233,7 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         "law": law, "law_params": params, "omega": float(omega), "theta": float(theta),
         "n_iter": int(n_iter), "steps": int(steps), "beta": float(beta), "seed": seed,
         "precision": precision,
+        "source_sigma": None if source_sigma is None else [float(v) for v in source_sigma],
     }
     X = node_coords(spec)
     if cfg == 1:

@@ -82,7 +82,7 @@ def spec():
     ("dt", float("nan"), kds.KDS_E_INVALID),
     ("theta", 0.3, kds.KDS_E_INVALID),
     ("n_iter", -1, kds.KDS_E_INVALID),
-    ("n_iter", 0, kds.KDS_E_UNSUPPORTED),
+    ("n_iter", -5, kds.KDS_E_INVALID),
     ("law", 7, kds.KDS_E_INVALID),
     ("precision", kds.KDS_FP32_SPLIT_F16, kds.KDS_E_UNSUPPORTED),
     ("precision", 9, kds.KDS_E_INVALID),

@@ -204,6 +204,23 @@ def test_converged_iteration_equals_fully_implicit_solve(orc):
     assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
 
 
+def test_converged_mode_equals_fully_implicit_solve(orc):
+    """n_iter = 0 iterates the subdomain algorithm to convergence: the fully
+    implicit periodic DG solve (dense brute force without lag)."""
+    rng = np.random.default_rng(8)
+    for vel in ([1.0, 0.6], [-0.7, 0.0]):
+        spec = {
+            "dim": 2, "n_cells": [6, 4, 1], "sub_cells": [2, 2, 1], "box_lo": [0.0] * 3,
+            "box_hi": [1.0] * 3, "degree": 2, "m": 1, "law": 0, "law_params": [0.0, 0.0],
+            "n_vel": 1, "vel": vel, "omega": 1.0, "dt": 0.3, "theta": 0.5, "n_iter": 0,
+        }
+        cfg = orc.Config(spec)
+        f0 = rng.normal(size=(cfg.ncell, cfg.nn))
+        got = orc.transport(cfg, 0, f0)
+        ref = bf.global_transport(orc, cfg, 0, f0, 1, lagged=False)
+        assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
 def test_aligned_chain_exact_after_nsub_iterations(orc):
     """For V along x, one x-row split in n_s subdomains: the Jacobi iteration
     only moves information downwind by one subdomain per iterate.  With the
@@ -462,3 +479,66 @@ def test_subdomain_iteration_stability_K1_vs_K3(orc):
     assert growth[1] > 1e6, growth
     assert growth[2] > 10.0, growth
     assert growth[3] < 1.0, growth
+
+
+# ------------------------------------------------------------- source term
+
+def _mu(sigma, dt):
+    return -1.0 if math.isinf(sigma) else (1 - sigma * dt / 2) / (1 + sigma * dt / 2)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.9, 2.0])
+def test_source_uniform_state_decays_by_crank_nicolson_factor(orc, omega):
+    """A uniform state is transported exactly, so with S(W)_c = -sigma_c W_c
+    every step multiplies W_c by the Crank-Nicolson factor
+    mu = (1 - sigma dt/2)/(1 + sigma dt/2) (eq:source_term_application_to_W)."""
+    sig = [0.0, 3.0, 0.7]
+    spec, W0 = wl.make_workload(2, n_cells=[8, 8], sub_cells=[4, 4], omega=omega,
+                                source_sigma=sig)
+    Wc = np.empty_like(W0)
+    Wc[...] = np.array([0.3, -0.2, 0.5])
+    F, W = orc.run(spec, Wc, 5)
+    expect = Wc * np.array([_mu(s, spec["dt"]) ** 5 for s in sig])
+    assert np.max(np.abs(W - expect)) < 1e-13
+
+
+def test_source_perfect_conductor_limit_flips_sign(orc):
+    """sigma -> infinity gives mu = -1: E+ = -E- (the perfect-conductor limit
+    used for the metallic wire, Sec. 6.3)."""
+    spec, W0 = wl.make_workload(2, n_cells=[8, 8], sub_cells=[4, 4], omega=1.9,
+                                source_sigma=[float("inf"), 0.0, 0.0])
+    Wc = np.empty_like(W0)
+    Wc[...] = np.array([0.8, 0.1, -0.3])
+    F, W = orc.run(spec, Wc, 1)
+    assert np.allclose(W[..., 0], -0.8, atol=1e-14)
+    assert np.allclose(W[..., 1:], [0.1, -0.3], atol=1e-14)
+
+
+def test_source_relaxation_keeps_moment_equal_to_source_updated_w(orc):
+    spec, W0 = wl.make_workload(3, n_cells=[2, 2, 2], sub_cells=[2, 2, 2],
+                                source_sigma=[0.0, 2.0, 2.0, 2.0, 0.5])
+    cfg = orc.Config(spec)
+    rng = np.random.default_rng(1)
+    F = orc.init(cfg, W0) + 0.01 * rng.normal(size=(6, 5, 8, 27))
+    W = orc.moments(cfg, F)
+    Fp = orc.relax(cfg, F)
+    mu = np.array([_mu(s, spec["dt"]) for s in spec["source_sigma"]])
+    assert np.allclose(orc.moments(cfg, Fp), W * mu, rtol=0, atol=1e-13)
+
+
+def test_source_step_is_second_order_in_time(orc):
+    """Crank-Nicolson: |mu^n - exp(-sigma T)| drops 4x when dt halves."""
+    sigma, T = 2.0, 1.0
+    errs = []
+    for n in (10, 20, 40):
+        h = 1.0 / 8
+        spec = {
+            "dim": 1, "n_cells": [8, 1, 1], "sub_cells": [4, 1, 1], "box_lo": [0.0] * 3,
+            "box_hi": [1.0] * 3, "degree": 1, "m": 1, "law": 0, "law_params": [0.3],
+            "n_vel": 2, "vel": [1.0, -1.0], "omega": 2.0, "dt": T / n, "theta": 0.5,
+            "n_iter": 3, "source_sigma": [sigma],
+        }
+        W0 = np.ones((8, 2, 1))
+        F, W = orc.run(spec, W0, n)
+        errs.append(abs(W[0, 0, 0] - math.exp(-sigma * T)))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs

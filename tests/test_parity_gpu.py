@@ -32,6 +32,16 @@ CASES = {
     # one subdomain of 34 cells (2 cells per lane, 17-lane scan through
     # wavefront shuffles) and 5 cells per lane along y
     "cfg1_odd": (1, dict(n_cells=[34, 20], sub_cells=[34, 10], steps=5)),
+    # converged subdomain iteration (n_iter = 0): line schedule only
+    "cfg2_converged": (2, dict(n_cells=[32, 24], sub_cells=[8, 6], steps=3, n_iter=0)),
+    "cfg3_converged": (3, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 2], steps=2, n_iter=0)),
+    # Crank-Nicolson damping source on the velocity / momentum components
+    "cfg2_source": (2, dict(n_cells=[32, 16], sub_cells=[8, 8], steps=4,
+                            source_sigma=[0.0, 3.0, 3.0])),
+    "cfg3_source": (3, dict(n_cells=[8, 8, 4], sub_cells=[4, 4, 2], steps=2,
+                            source_sigma=[0.0, 2.0, 2.0, 2.0, 0.0])),
+    "cfg2_pec": (2, dict(n_cells=[16, 16], sub_cells=[8, 8], steps=3,
+                         source_sigma=[float("inf"), 0.0, 0.0])),
 }
 
 
@@ -68,6 +78,8 @@ def relerr(a, b):
 @pytest.mark.parametrize("prec,sched", MODES)
 def test_parity_against_oracle(name, prec, sched):
     from paper_2212_11010_amd import kds
+    if sched == "plain" and CASES[name][1].get("n_iter") == 0:
+        pytest.skip("n_iter = 0 is a line-schedule feature (plain returns KDS_E_UNSUPPORTED)")
     spec, W0, Fref, Wref = case(name)
     print("case", name, prec, sched, spec["n_cells"], spec["sub_cells"], flush=True)
     try:
@@ -199,3 +211,11 @@ def test_autotuned_plan_restores_state_and_keeps_parity(name):
         F = pb.get_kinetic()
     print("tuned", name, info["line_Q"], info["line_bw"], "%.4f ms" % ms, flush=True)
     assert relerr(W, Wref) <= TOL["fp32"] and relerr(F, Fref) <= TOL["fp32"]
+
+
+def test_converged_mode_rejected_by_plain_schedule():
+    from paper_2212_11010_amd import kds
+    spec, _, _, _ = case("cfg2_converged")
+    with pytest.raises(kds.KdsError) as ei:
+        kds.Problem(spec, precision="fp32", schedule="plain")
+    assert ei.value.status == kds.KDS_E_UNSUPPORTED
