@@ -62,9 +62,11 @@ typedef enum {
 
 typedef enum {
   KDS_FP64 = 0,            /* transport and storage in FP64 */
-  KDS_FP32 = 1,            /* transport and storage in FP32; W and M_k in FP64 */
-  KDS_FP32_SPLIT_F16 = 2,  /* reserved (returns KDS_E_UNSUPPORTED) */
-  KDS_FP32_SPLIT_BF16 = 3  /* reserved (returns KDS_E_UNSUPPORTED) */
+  KDS_FP32 = 1,            /* transport and storage in FP32; W and M_k in FP64;
+                              the front schedule multiplies on FP32 matrix cores */
+  KDS_FP32_SPLIT_F16 = 2,  /* FP32 storage; front-schedule cell solves as three
+                              FP16 matrix-core products (hi*hi + hi*lo + lo*hi) */
+  KDS_FP32_SPLIT_BF16 = 3  /* same with BF16 halves */
 } kds_prec;
 
 typedef enum {
@@ -72,9 +74,15 @@ typedef enum {
   KDS_SCHED_PLAIN = 1, /* literal sweep: one launch per subdomain iteration,
                           one thread per (velocity, component, line, subdomain)
                           walking its cells in downwind order */
-  KDS_SCHED_LINE = 2   /* all n_iter subdomain iterations of a whole grid line
+  KDS_SCHED_LINE = 2,  /* all n_iter subdomain iterations of a whole grid line
                           resolved in one pass by one wavefront (exact
                           reformulation, see kds_step) */
+  KDS_SCHED_FRONT = 3  /* velocities in any direction: cells of a subdomain by
+                          fronts of the oriented cell graph, the solves of a
+                          front batched into one dense GEMM (matrix cores for
+                          FP32 and the split precisions); one launch per
+                          subdomain iteration.  Required (and chosen by AUTO)
+                          when a velocity is not parallel to a grid axis. */
 } kds_schedule;
 
 typedef struct {
@@ -90,7 +98,7 @@ typedef struct {
   const double* law_params;
   int32_t n_law_params;
   int32_t n_vel;         /* kinetic velocities, 1..8 */
-  const double* vel;     /* n_vel * dim; each must be parallel to an axis */
+  const double* vel;     /* n_vel * dim, nonzero; oblique velocities need the front schedule */
   const double* eq_a;    /* n_vel weights, or NULL (see below) */
   const double* eq_b;    /* n_vel * dim weights, or NULL */
   double omega;          /* relaxation parameter, 0 <= omega <= 2 (Sec. 2.2) */
@@ -171,7 +179,7 @@ kds_status kds_synchronize(kds_problem* p);
 typedef struct {
   int64_t n_unknowns;     /* cells * (p+1)^d * m * n_vel */
   int64_t state_bytes;    /* device bytes of one kinetic state */
-  int32_t schedule;       /* schedule actually used (KDS_SCHED_PLAIN / LINE) */
+  int32_t schedule;       /* schedule actually used (KDS_SCHED_PLAIN / LINE / FRONT) */
   int32_t precision;
   int32_t steps_done;
   double max_kinetic_courant; /* max_k |V_k| dt / h_axis */

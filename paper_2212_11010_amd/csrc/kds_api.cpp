@@ -32,6 +32,12 @@ struct kds_problem {
   std::vector<unsigned char> sweep_blob;  // SweepTab<T>
   LinePlan plan{};
   int line_Q[3] = {1, 1, 1}, line_bw[3] = {1, 1, 1};  // per-axis line-schedule choices
+  FrontParams front{};   // front schedule
+  int front_mode = 0;
+  void* front_W = nullptr;      // [k][nn][Kd] dense cell operators
+  int* front_lvl_start = nullptr;
+  int* front_lvl_cells = nullptr;
+  void* fit[2] = {nullptr, nullptr};  // front schedule: iterates
   bool tuned = false;
   double max_nu = 0, min_sub_width = 0;
   bool proposition_ok = true;
@@ -118,23 +124,24 @@ kds_status validate(const kds_config* c, std::string& msg) {
   if (!(c->dt > 0.0) || !finite(c->dt)) { msg = "dt must be > 0"; return KDS_E_INVALID; }
   if (!(c->theta >= 0.5 && c->theta <= 1.0)) { msg = "theta must be in [1/2, 1]"; return KDS_E_INVALID; }
   if (c->n_iter < 0) { msg = "n_iter must be >= 0"; return KDS_E_INVALID; }
-  if (c->precision == KDS_FP32_SPLIT_F16 || c->precision == KDS_FP32_SPLIT_BF16) {
-    msg = "split-precision storage is not implemented";
-    return KDS_E_UNSUPPORTED;
-  }
-  if (c->precision != KDS_FP64 && c->precision != KDS_FP32) { msg = "unknown precision"; return KDS_E_INVALID; }
-  if (c->schedule < KDS_SCHED_AUTO || c->schedule > KDS_SCHED_LINE) { msg = "unknown schedule"; return KDS_E_INVALID; }
-  if (c->source_sigma)
-    for (int r = 0; r < c->m; ++r)
-      if (!(c->source_sigma[r] >= 0.0)) { msg = "source_sigma must be >= 0 (or +inf)"; return KDS_E_INVALID; }
+  if (c->precision < KDS_FP64 || c->precision > KDS_FP32_SPLIT_BF16) { msg = "unknown precision"; return KDS_E_INVALID; }
+  if (c->schedule < KDS_SCHED_AUTO || c->schedule > KDS_SCHED_FRONT) { msg = "unknown schedule"; return KDS_E_INVALID; }
+  const bool split = c->precision == KDS_FP32_SPLIT_F16 || c->precision == KDS_FP32_SPLIT_BF16;
+  bool oblique = false;
   for (int k = 0; k < c->n_vel; ++k) {
     int nz = 0;
     for (int a = 0; a < c->dim; ++a) nz += c->vel[k * c->dim + a] != 0.0;
-    if (nz != 1) {
-      msg = "every kinetic velocity must be parallel to one grid axis (and nonzero)";
-      return KDS_E_UNSUPPORTED;
-    }
+    if (nz == 0) { msg = "kinetic velocities must be nonzero"; return KDS_E_INVALID; }
+    if (nz > 1) oblique = true;
   }
+  if ((oblique || split) && c->schedule != KDS_SCHED_AUTO && c->schedule != KDS_SCHED_FRONT) {
+    msg = oblique ? "velocities not parallel to a grid axis need the front schedule"
+                  : "split precisions are a front-schedule feature";
+    return KDS_E_UNSUPPORTED;
+  }
+  if (c->source_sigma)
+    for (int r = 0; r < c->m; ++r)
+      if (!(c->source_sigma[r] >= 0.0)) { msg = "source_sigma must be >= 0 (or +inf)"; return KDS_E_INVALID; }
   return KDS_OK;
 }
 
@@ -240,6 +247,56 @@ bool plan_lines(kds_problem* p, std::string& why) {
   return true;
 }
 
+// Front schedule tables: dense operators per velocity and, per velocity, the
+// cells of one subdomain sorted by level l = sum over axes with V^a != 0 of the
+// downwind cell index (packed lx | ly << 10 | lz << 20).
+bool build_front(kds_problem* p, const Basis1D& basis, std::vector<double>& W,
+                 std::vector<int>& lvl_start, std::vector<int>& lvl_cells, std::string& why) {
+  FrontParams& fp = p->front;
+  std::memset(&fp, 0, sizeof(fp));
+  int nn = 0, nf = 0;
+  W.clear();
+  for (int k = 0; k < p->nv; ++k) {
+    std::vector<double> Wk;
+    if (!make_dense_op(basis, p->dim, &p->vel[k * p->dim], p->h, p->dt, p->theta, Wk, nn, nf)) {
+      why = "front schedule: singular cell operator";
+      return false;
+    }
+    W.insert(W.end(), Wk.begin(), Wk.end());
+    for (int a = 0; a < 3; ++a) {
+      const double v = a < p->dim ? p->vel[k * p->dim + a] : 0.0;
+      fp.sg[k][a] = v > 0 ? 1 : (v < 0 ? -1 : 0);
+    }
+  }
+  fp.nf = nf;
+  fp.Kd = nn + 3 * nf;
+  for (int a = 0; a < 3; ++a) fp.nsub[a] = p->N[a] / p->S[a];
+  fp.theta = p->theta;
+  fp.col_chunk = 64;
+  lvl_start.clear();
+  lvl_cells.clear();
+  const int S0 = p->S[0], S1 = p->S[1], S2 = p->S[2];
+  if (S0 > 1024 || S1 > 1024 || S2 > 1024) { why = "front schedule: subdomain wider than 1024 cells"; return false; }
+  for (int k = 0; k < p->nv; ++k) {
+    int act[3];
+    for (int a = 0; a < 3; ++a) act[a] = fp.sg[k][a] != 0;
+    const int maxlev = act[0] * (S0 - 1) + act[1] * (S1 - 1) + act[2] * (S2 - 1);
+    fp.lvl_off[k] = (int)lvl_start.size();
+    fp.nlev[k] = maxlev + 1;
+    std::vector<std::vector<int>> by(maxlev + 1);
+    for (int z = 0; z < S2; ++z)
+      for (int y = 0; y < S1; ++y)
+        for (int x = 0; x < S0; ++x)
+          by[act[0] * x + act[1] * y + act[2] * z].push_back(x | (y << 10) | (z << 20));
+    for (int l = 0; l <= maxlev; ++l) {
+      lvl_start.push_back((int)lvl_cells.size());
+      lvl_cells.insert(lvl_cells.end(), by[l].begin(), by[l].end());
+    }
+    lvl_start.push_back((int)lvl_cells.size());
+  }
+  return true;
+}
+
 template <typename T>
 void fill_sweep_tab(kds_problem* p, const Basis1D& basis) {
   SweepTab<T> t;
@@ -249,7 +306,7 @@ void fill_sweep_tab(kds_problem* p, const Basis1D& basis) {
     double v = 0;
     for (int d = 0; d < p->dim; ++d)
       if (p->vel[k * p->dim + d] != 0.0) { ax = d; v = p->vel[k * p->dim + d]; }
-    const double nu = std::fabs(v) * p->dt / p->h[ax];
+    const double nu = std::fabs(v) * p->dt / p->h[ax];  // (oblique velocities: front only)
     LineOp op = make_line_op(basis, nu, p->theta);
     t.axis[k] = ax;
     t.sign[k] = v > 0 ? 1 : -1;
@@ -270,10 +327,13 @@ void free_device(kds_problem* p) {
   p->graph = nullptr;
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
-  void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag};
+  void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
+                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
+  p->front_W = p->fit[0] = p->fit[1] = nullptr;
+  p->front_lvl_start = p->front_lvl_cells = nullptr;
   p->stage = nullptr;
   p->flag = nullptr;
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
@@ -286,7 +346,16 @@ void free_device(kds_problem* p) {
 kds_status enqueue_step(kds_problem* p, bool events) {
   const Geom& g = p->geom;
   if (events) KDS_HIP(p, hipEventRecord(p->ev[0], p->stream));
-  if (p->sched == KDS_SCHED_LINE) {
+  if (p->sched == KDS_SCHED_FRONT) {
+    for (int it = 1; it <= p->K; ++it) {
+      const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
+      KDS_HIP(p, launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
+                                    p->front_lvl_start, p->front_lvl_cells, p->f, f_prev,
+                                    p->fit[it & 1], p->stream));
+    }
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->fit[p->K & 1], p->f, p->stream));
+  } else if (p->sched == KDS_SCHED_LINE) {
     KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream));
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
     KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream));
@@ -384,8 +453,12 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   p->dt = cfg->dt;
   p->theta = cfg->theta;
   p->K = cfg->n_iter;
-  p->prec = cfg->precision;
+  p->prec = cfg->precision == KDS_FP64 ? KDS_FP64 : KDS_FP32;  // storage precision
   p->elem = p->prec == KDS_FP64 ? 8 : 4;
+  p->front_mode = cfg->precision == KDS_FP32_SPLIT_F16    ? kFrontSplitF16
+                  : cfg->precision == KDS_FP32_SPLIT_BF16 ? kFrontSplitBf16
+                  : cfg->precision == KDS_FP32            ? kFrontMfma
+                                                          : kFrontFma;
 
   std::vector<double> a, b;
   if (!eq_weights(p->dim, p->nv, p->vel.data(), cfg->eq_a, cfg->eq_b, a, b, msg)) {
@@ -406,8 +479,24 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
                 "no compiled relaxation kernel for this (law, dim, m, n_vel) combination");
   }
   Basis1D basis = make_basis(p->degree);
-  if (p->prec == KDS_FP64) fill_sweep_tab<double>(p, basis);
-  else fill_sweep_tab<float>(p, basis);
+  bool oblique = false;
+  for (int k = 0; k < p->nv; ++k) {
+    int nz = 0;
+    for (int a = 0; a < p->dim; ++a) nz += p->vel[k * p->dim + a] != 0.0;
+    oblique |= nz > 1;
+  }
+  const bool want_front = oblique || cfg->schedule == KDS_SCHED_FRONT ||
+                          cfg->precision == KDS_FP32_SPLIT_F16 || cfg->precision == KDS_FP32_SPLIT_BF16;
+  if (!oblique) {
+    if (p->prec == KDS_FP64) fill_sweep_tab<double>(p, basis);
+    else fill_sweep_tab<float>(p, basis);
+  }
+  std::vector<double> frontW;
+  std::vector<int> lvl_start, lvl_cells;
+  if (want_front && !build_front(p, basis, frontW, lvl_start, lvl_cells, msg)) {
+    delete p;
+    return fail(nullptr, KDS_E_UNSUPPORTED, msg);
+  }
 
   Geom& g = p->geom;
   g.dim = p->dim;
@@ -436,7 +525,7 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   for (int ax = 0; ax < p->dim; ++ax) p->min_sub_width = std::min(p->min_sub_width, p->S[ax] * p->h[ax]);
 
   std::string why;
-  const bool line_ok = plan_lines(p, why);
+  const bool line_ok = !want_front && plan_lines(p, why);
   if (cfg->schedule == KDS_SCHED_LINE && !line_ok) {
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED, why);
@@ -448,6 +537,13 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
               (cfg->schedule == KDS_SCHED_AUTO && !line_preferred && p->K > 0))
                  ? KDS_SCHED_PLAIN
                  : KDS_SCHED_LINE;
+  if (want_front) {
+    p->sched = KDS_SCHED_FRONT;
+    if (front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) > 64 * 1024) {
+      delete p;
+      return fail(nullptr, KDS_E_UNSUPPORTED, "front schedule: cell operator too large for the LDS");
+    }
+  }
   if (p->K == 0 && p->sched != KDS_SCHED_LINE) {
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED,
@@ -464,6 +560,7 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   const size_t state_bytes = (size_t)p->n_unknowns() * p->elem;
   size_t need = state_bytes;
   if (p->sched == KDS_SCHED_PLAIN) need += state_bytes + 2 * (size_t)g.tr_stride * p->nv * p->m * p->elem;
+  if (p->sched == KDS_SCHED_FRONT) need += 2 * state_bytes;
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) {
@@ -483,6 +580,25 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   if (ok && p->sched == KDS_SCHED_PLAIN) {
     const size_t trb = std::max<size_t>(1, (size_t)g.tr_stride * p->nv * p->m * p->elem);
     ok = alloc(&p->f_tmp, state_bytes) && alloc(&p->tr[0], trb) && alloc(&p->tr[1], trb);
+  }
+  if (ok && p->sched == KDS_SCHED_FRONT) {
+    ok = alloc(&p->fit[0], state_bytes) && alloc(&p->fit[1], state_bytes) &&
+         alloc(&p->front_W, frontW.size() * p->elem) &&
+         alloc((void**)&p->front_lvl_start, lvl_start.size() * sizeof(int)) &&
+         alloc((void**)&p->front_lvl_cells, lvl_cells.size() * sizeof(int));
+    if (ok) {
+      std::vector<float> w32;
+      const void* src = frontW.data();
+      if (p->prec != KDS_FP64) {
+        w32.assign(frontW.begin(), frontW.end());
+        src = w32.data();
+      }
+      ok = hipMemcpy(p->front_W, src, frontW.size() * p->elem, hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(p->front_lvl_start, lvl_start.data(), lvl_start.size() * sizeof(int),
+                     hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(p->front_lvl_cells, lvl_cells.data(), lvl_cells.size() * sizeof(int),
+                     hipMemcpyHostToDevice) == hipSuccess;
+    }
   }
   if (!ok) {
     free_device(p);
@@ -662,6 +778,10 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
   for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
     auto launch = [&]() -> hipError_t {
       if (kind == 0) {
+        if (p->sched == KDS_SCHED_FRONT)
+          return launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
+                                    p->front_lvl_start, p->front_lvl_cells, p->f, p->f,
+                                    p->fit[1], p->stream);
         if (p->sched == KDS_SCHED_LINE)
           return launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream);
         // one plain subdomain iteration (the kernel a step launches n_iter times)

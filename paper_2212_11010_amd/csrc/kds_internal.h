@@ -40,6 +40,11 @@ struct LineOp {
 };
 LineOp make_line_op(const Basis1D& b, double nu, double theta);
 
+// Dense cell operator [C | E_0 | E_1 | E_2] (nn x (nn + 3 nf)) of the implicit
+// upwind DG cell update for a velocity in any direction.
+bool make_dense_op(const Basis1D& b, int dim, const double* V, const double* h, double dt,
+                   double theta, std::vector<double>& Wop, int& nn, int& nf);
+
 // Minimum-norm equilibrium weights (a_k, b_{k,i}) or the caller's.
 bool eq_weights(int dim, int nv, const double* vel, const double* eq_a, const double* eq_b,
                 std::vector<double>& a, std::vector<double>& b, std::string& err);
@@ -95,6 +100,20 @@ struct LinePlan {
   int threads;             // block size
 };
 
+// Front (level-ordered) sweep for velocities in any direction.
+enum FrontMode { kFrontFma = 0, kFrontMfma = 1, kFrontSplitF16 = 2, kFrontSplitBf16 = 3 };
+
+struct FrontParams {
+  int nf;                  // nodes per face, (p+1)^(d-1)
+  int Kd;                  // operator columns, nn + 3 nf
+  int sg[kMaxVel][3];      // sign of V^a, 0 where V^a = 0
+  int lvl_off[kMaxVel];    // offset of the velocity's level starts in lvl_start
+  int nlev[kMaxVel];       // number of levels (fronts) per subdomain
+  int col_chunk;           // GEMM columns per pass (multiple of 16)
+  int nsub[3];             // subdomains per axis
+  double theta;
+};
+
 // --------------------------------------------------------------- launchers
 
 
@@ -110,6 +129,13 @@ hipError_t launch_sweep_plain(int prec, const Geom& g, const void* tab, const vo
                               void* f_new, const void* tr_prev, void* tr_out, hipStream_t s);
 hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const LinePlan& plan,
                              void* f, hipStream_t s);
+// One subdomain iteration of the front sweep: reads f_old (state at t^{n-1})
+// and f_prev (iterate p-1), writes f_cur (iterate p).  mode: FrontMode; for
+// kFrontFma the element type follows prec (FP64 or FP32), the MFMA modes are FP32.
+hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontParams& fp,
+                              const void* Wop, const int* lvl_start, const int* lvl_cells,
+                              const void* f_old, const void* f_prev, void* f_cur, hipStream_t s);
+size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp);
 
 // Equilibrium tables are built into a byte blob matching EqTab<D, M, NV> for
 // the (law, dim, m, nv) combination; returns false if the combination has no

@@ -820,6 +820,213 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
   }
 }
 
+// ====================================================== front sweep
+
+// Velocities with several nonzero components (the paper's D3Q4 set): the
+// cell operator [C | E_x | E_y | E_z] is dense (nn x (nn + 3 nf)), and the
+// cells of a subdomain are visited by levels (anti-diagonal fronts) of the
+// V-oriented cell graph, l = sum over active axes of the downwind cell index:
+// the topological order of Sec. 3.2 on a box.  All cells of a level, for all
+// components, are independent, so their solves form one GEMM
+//     Y[nn x cols] = W[nn x Kd] X[Kd x cols],
+// X = [f^{n-1}(cell); theta t^n + (1-theta) t^{n-1} on the three inflow faces].
+// t^n comes from the current iterate inside the subdomain (previous level)
+// and from iterate p-1 across subdomain faces (eq:ibvp, Jacobi).  One
+// workgroup per (velocity, subdomain); one launch per subdomain iteration.
+//
+// Products: FP64/FP32 FMA (kFrontFma), FP32 matrix cores
+// (v_mfma_f32_16x16x4f32), or the split three-product forms on FP16/BF16
+// matrix cores (x = hi + lo, W X ~ Wh Xh + Wh Xl + Wl Xh, FP32 accumulation;
+// the FP16 low parts are scaled by 2^11 against underflow).
+
+typedef float kds_f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 kds_f16x4 __attribute__((ext_vector_type(4)));
+typedef short kds_i16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const unsigned int b = __float_as_uint(x);
+  return (unsigned short)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old,
+                                                     const T* __restrict__ f_prev,
+                                                     T* __restrict__ f_cur, Geom g, FrontParams fp,
+                                                     const T* __restrict__ Wop,
+                                                     const int* __restrict__ lvl_start,
+                                                     const int* __restrict__ lvl_cells) {
+  extern __shared__ unsigned char smem_raw[];
+  const int nn = g.nn, nf = fp.nf, Kd = fp.Kd, P = g.P, m = g.m;
+  const int Mpad = (nn + 15) & ~15;
+  const int Kpad = (Kd + 15) & ~15;
+  const int CH = fp.col_chunk;
+  const int XS = CH + 1;  // odd row stride: conflict-free gathers
+  T* Wt = reinterpret_cast<T*>(smem_raw);            // [Mpad][Kpad] (matrix-core modes)
+  T* X = Wt + (MODE == kFrontFma ? 0 : Mpad * Kpad);  // [Kpad][XS]
+  const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
+  const int k = blockIdx.x / nsd;
+  const int sd = blockIdx.x - k * nsd;
+  int sdc[3] = {sd % fp.nsub[0], (sd / fp.nsub[0]) % fp.nsub[1], sd / (fp.nsub[0] * fp.nsub[1])};
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const T th = (T)fp.theta;
+  const T* Wk = Wop + (int64_t)k * nn * Kd;
+  if (MODE != kFrontFma) {
+    for (int e = tid; e < Mpad * Kpad; e += bs) {
+      const int i = e / Kpad, r = e - i * Kpad;
+      Wt[e] = (i < nn && r < Kd) ? Wk[i * Kd + r] : T(0);
+    }
+  }
+  int sgn[3], outn[3];
+  for (int a = 0; a < 3; ++a) {
+    sgn[a] = a < g.dim ? fp.sg[k][a] : 0;
+    outn[a] = sgn[a] > 0 ? P - 1 : 0;  // neighbour's node index on the shared face
+  }
+  int pw[3] = {1, P, P * P};
+  const int64_t plane = g.ncell * nn;
+  const int nlev = fp.nlev[k];
+  __syncthreads();
+
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int c0 = lvl_start[fp.lvl_off[k] + lev];
+    const int c1 = lvl_start[fp.lvl_off[k] + lev + 1];
+    const int ncol = (c1 - c0) * m;
+    for (int j0 = 0; j0 < ncol; j0 += CH) {
+      const int nc = min(CH, ncol - j0);
+      // ---- gather X[r][jj]: r fastest over threads (contiguous nodes)
+      for (int e = tid; e < Kpad * CH; e += bs) {
+        const int jj = e / Kpad, r = e - jj * Kpad;
+        T v = T(0);
+        if (jj < nc && r < Kd) {
+          const int j = j0 + jj;
+          const int ci = c0 + j / m, c = j - (j / m) * m;
+          const int pk = lvl_cells[ci];
+          const int lc[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
+          int gc[3];
+          for (int a = 0; a < 3; ++a) {
+            const int pl = sgn[a] < 0 ? g.S[a] - 1 - lc[a] : lc[a];
+            gc[a] = sdc[a] * g.S[a] + pl;
+          }
+          const int64_t kc = (int64_t)(k * m + c) * plane;
+          if (r < nn) {
+            const int64_t cell = gc[0] + (int64_t)g.N[0] * (gc[1] + (int64_t)g.N[1] * gc[2]);
+            v = f_old[kc + cell * nn + r];
+          } else {
+            const int a = (r - nn) / nf, q = (r - nn) - a * nf;
+            if (a < g.dim && sgn[a] != 0) {
+              int nb[3] = {gc[0], gc[1], gc[2]};
+              nb[a] -= sgn[a];
+              if (nb[a] < 0) nb[a] += g.N[a];
+              if (nb[a] >= g.N[a]) nb[a] -= g.N[a];
+              const bool internal = lc[a] > 0;
+              // neighbour node: index outn[a] on axis a, the others from q
+              int node = 0, rem = q;
+              for (int o = 0; o < g.dim; ++o) {
+                int io;
+                if (o == a) io = outn[a];
+                else { io = rem % P; rem /= P; }
+                node += io * pw[o];
+              }
+              const int64_t nbc = nb[0] + (int64_t)g.N[0] * (nb[1] + (int64_t)g.N[1] * nb[2]);
+              const int64_t at = kc + nbc * nn + node;
+              const T tn = internal ? f_cur[at] : f_prev[at];
+              v = th * tn + (T(1) - th) * f_old[at];
+            }
+          }
+        }
+        X[r * XS + jj] = v;
+      }
+      __syncthreads();
+      // ---- Y = W X, written to the current iterate
+      auto store = [&](int i, int jj, T y) {
+        const int j = j0 + jj;
+        const int ci = c0 + j / m, c = j - (j / m) * m;
+        const int pk = lvl_cells[ci];
+        const int lc[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
+        int gc[3];
+        for (int a = 0; a < 3; ++a) {
+          const int pl = sgn[a] < 0 ? g.S[a] - 1 - lc[a] : lc[a];
+          gc[a] = sdc[a] * g.S[a] + pl;
+        }
+        const int64_t cell = gc[0] + (int64_t)g.N[0] * (gc[1] + (int64_t)g.N[1] * gc[2]);
+        f_cur[(int64_t)(k * m + c) * plane + cell * nn + i] = y;
+      };
+      if constexpr (MODE == kFrontFma) {
+        for (int e = tid; e < nn * nc; e += bs) {
+          const int jj = e / nn, i = e - jj * nn;
+          T acc = T(0);
+          for (int r = 0; r < Kd; ++r) acc += Wk[i * Kd + r] * X[r * XS + jj];
+          store(i, jj, acc);
+        }
+      } else {
+        const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+        const int li = lane & 15, lk = lane >> 4;
+        const int mt_n = Mpad / 16, nt_n = (nc + 15) / 16;
+        for (int t = wave; t < mt_n * nt_n; t += nw) {
+          const int mt = t % mt_n, nt = t / mt_n;
+          const int i0 = mt * 16, jb = nt * 16;
+          kds_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+          if constexpr (MODE == kFrontMfma) {
+            for (int kk = 0; kk < Kpad; kk += 4) {
+              const float av = (float)Wt[(i0 + li) * Kpad + kk + lk];
+              const float bv = (float)X[(kk + lk) * XS + jb + li];
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            }
+          } else {
+            kds_f32x4 cor = {0.f, 0.f, 0.f, 0.f};
+            for (int kk = 0; kk < Kpad; kk += 16) {
+              float aw[4], bw[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                aw[u] = (float)Wt[(i0 + li) * Kpad + kk + 4 * lk + u];
+                bw[u] = (float)X[(kk + 4 * lk + u) * XS + jb + li];
+              }
+              if constexpr (MODE == kFrontSplitF16) {
+                kds_f16x4 ah, al, bh, bl;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const _Float16 ha = (_Float16)aw[u], hb = (_Float16)bw[u];
+                  ah[u] = ha;
+                  bh[u] = hb;
+                  al[u] = (_Float16)((aw[u] - (float)ha) * 2048.0f);
+                  bl[u] = (_Float16)((bw[u] - (float)hb) * 2048.0f);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, cor, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, cor, 0, 0, 0);
+              } else {
+                kds_i16x4 ah, al, bh, bl;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const unsigned short ha = bf16_rne(aw[u]), hb = bf16_rne(bw[u]);
+                  ah[u] = (short)ha;
+                  bh[u] = (short)hb;
+                  al[u] = (short)bf16_rne(aw[u] - bf16_to_f32(ha));
+                  bl[u] = (short)bf16_rne(bw[u] - bf16_to_f32(hb));
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, cor, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, cor, 0, 0, 0);
+              }
+            }
+            const float sc = MODE == kFrontSplitF16 ? 1.0f / 2048.0f : 1.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += sc * cor[v];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = i0 + 4 * lk + v, jj = jb + li;
+            if (i < nn && jj < nc) store(i, jj, (T)acc[v]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ============================================================ launchers
 
 namespace {
@@ -891,7 +1098,8 @@ const ComboEntry kCombos[] = {
     KDS_COMBO(KDS_LAW_LINEAR, 1, 1, 2), KDS_COMBO(KDS_LAW_LINEAR, 1, 2, 2),
     KDS_COMBO(KDS_LAW_LINEAR, 2, 1, 4), KDS_COMBO(KDS_LAW_LINEAR, 2, 3, 4),
     KDS_COMBO(KDS_LAW_LINEAR, 3, 1, 6), KDS_COMBO(KDS_LAW_LINEAR, 3, 4, 6),
-    KDS_COMBO(KDS_LAW_LINEAR, 3, 6, 6), KDS_COMBO(KDS_LAW_EULER, 1, 3, 2),
+    KDS_COMBO(KDS_LAW_LINEAR, 3, 6, 6), KDS_COMBO(KDS_LAW_LINEAR, 3, 6, 4),
+    KDS_COMBO(KDS_LAW_EULER, 1, 3, 2),
     KDS_COMBO(KDS_LAW_EULER, 2, 4, 4),  KDS_COMBO(KDS_LAW_EULER, 3, 5, 6),
 };
 
@@ -1032,6 +1240,44 @@ hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const Lin
                              void* f, hipStream_t s) {
   return prec == KDS_FP64 ? sweep_line_t<double>(g, tab, plan, f, s)
                           : sweep_line_t<float>(g, tab, plan, f, s);
+}
+
+
+size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp) {
+  const int Mpad = (g.nn + 15) & ~15, Kpad = (fp.Kd + 15) & ~15;
+  const size_t el = prec == KDS_FP64 ? 8 : 4;
+  return ((mode == kFrontFma ? 0 : (size_t)Mpad * Kpad) + (size_t)Kpad * (fp.col_chunk + 1)) * el;
+}
+
+hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontParams& fp,
+                              const void* Wop, const int* lvl_start, const int* lvl_cells,
+                              const void* f_old, const void* f_prev, void* f_cur, hipStream_t s) {
+  const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
+  const dim3 grid((unsigned)(nsd * g.nv)), block(256);
+  const size_t lds = front_lds_bytes(prec, mode, g, fp);
+  if (prec == KDS_FP64) {
+    if (mode != kFrontFma) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sweep_front<double, kFrontFma>), grid, block, lds, s, (const double*)f_old,
+                       (const double*)f_prev, (double*)f_cur, g, fp, (const double*)Wop, lvl_start,
+                       lvl_cells);
+  } else {
+    switch (mode) {
+#define KDS_FRONT(MODE)                                                                         \
+  case MODE:                                                                                    \
+    hipLaunchKernelGGL((k_sweep_front<float, MODE>), grid, block, lds, s, (const float*)f_old,  \
+                       (const float*)f_prev, (float*)f_cur, g, fp, (const float*)Wop, lvl_start, \
+                       lvl_cells);                                                              \
+    break;
+      KDS_FRONT(kFrontFma)
+      KDS_FRONT(kFrontMfma)
+      KDS_FRONT(kFrontSplitF16)
+      KDS_FRONT(kFrontSplitBf16)
+#undef KDS_FRONT
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
 }
 
 }  // namespace kds

@@ -215,3 +215,83 @@ bool eq_weights(int dim, int nv, const double* vel, const double* eq_a, const do
 }
 
 }  // namespace kds
+
+namespace kds {
+
+// Dense cell operator for a velocity V in any direction (Sec. 3.1, eq:dg_imp
+// on a Cartesian cell with the tensor Gauss-Lobatto basis).  Per axis a with
+// V^a != 0 the residual has the 1-D part (|V^a|/h_a) (L_a f - l_a t_a), applied
+// along axis a (downwind node order along a is physical order for V^a > 0 and
+// reversed for V^a < 0).  With A = I + theta dt sum_a L_a and
+// B = I - (1 - theta) dt sum_a L_a:
+//   f^n = A^{-1} B f^{n-1} + sum_a A^{-1} lift_a (theta t_a^n + (1-theta) t_a^{n-1}),
+// lift_a mapping the P^{d-1} face values of the upwind neighbour across the
+// inflow face of axis a onto the nodes of that face.
+// Result: Wop = [C | E_0 | E_1 | E_2], nn x (nn + 3 nf), row-major, with
+// E_a = 0 for axes where V^a = 0; face node q enumerates the other axes'
+// node indices (x fastest), the neighbour's matching node has the outflow
+// index on axis a.
+bool make_dense_op(const Basis1D& b, int dim, const double* V, const double* h, double dt,
+                   double theta, std::vector<double>& Wop, int& nn, int& nf) {
+  const int P = b.P;
+  nn = 1;
+  for (int a = 0; a < dim; ++a) nn *= P;
+  nf = nn / P;
+  // 1-D operator in physical node order for a positive velocity, and its mirror
+  std::vector<double> Lp(P * P, 0.0);
+  for (int r = 0; r < P; ++r)
+    for (int c = 0; c < P; ++c) Lp[r * P + c] = -(b.w[c] / b.w[r]) * b.D[c * P + r];
+  Lp[(P - 1) * P + (P - 1)] += 1.0 / b.w[P - 1];
+  std::vector<double> Lfull(nn * nn, 0.0), A(nn * nn), B(nn * nn);
+  auto idx = [&](int i, int a) { for (int t = 0; t < a; ++t) i /= P; return i % P; };
+  for (int a = 0; a < dim; ++a) {
+    if (V[a] == 0.0) continue;
+    const double s = std::fabs(V[a]) / h[a];
+    for (int i = 0; i < nn; ++i)
+      for (int j = 0; j < nn; ++j) {
+        bool same = true;
+        for (int o = 0; o < dim; ++o)
+          if (o != a && idx(i, o) != idx(j, o)) same = false;
+        if (!same) continue;
+        int ri = idx(i, a), rj = idx(j, a);
+        if (V[a] < 0) { ri = P - 1 - ri; rj = P - 1 - rj; }  // mirror to downwind order
+        Lfull[i * nn + j] += s * Lp[ri * P + rj];
+      }
+  }
+  for (int i = 0; i < nn * nn; ++i) {
+    const double id = (i / nn == i % nn) ? 1.0 : 0.0;
+    A[i] = id + theta * dt * Lfull[i];
+    B[i] = id - (1.0 - theta) * dt * Lfull[i];
+  }
+  std::vector<double> Ai = A;
+  if (!invert(nn, Ai)) return false;
+  const int K = nn + 3 * nf;
+  Wop.assign((size_t)nn * K, 0.0);
+  for (int i = 0; i < nn; ++i)
+    for (int j = 0; j < nn; ++j) {
+      double acc = 0.0;
+      for (int t = 0; t < nn; ++t) acc += Ai[i * nn + t] * B[t * nn + j];
+      Wop[(size_t)i * K + j] = acc;
+    }
+  for (int a = 0; a < dim; ++a) {
+    if (V[a] == 0.0) continue;
+    const int in_idx = V[a] > 0 ? 0 : P - 1;        // inflow face node index on axis a
+    const double lift = dt * (std::fabs(V[a]) / h[a]) / b.w[in_idx];
+    for (int q = 0; q < nf; ++q) {
+      // cell node on the inflow face with the other-axis indices of q
+      int node = 0, mul = 1, rem = q;
+      for (int o = 0; o < dim; ++o) {
+        int io;
+        if (o == a) io = in_idx;
+        else { io = rem % P; rem /= P; }
+        node += io * mul;
+        mul *= P;
+      }
+      for (int i = 0; i < nn; ++i)
+        Wop[(size_t)i * K + nn + a * nf + q] = Ai[i * nn + node] * lift;
+    }
+  }
+  return true;
+}
+
+}  // namespace kds

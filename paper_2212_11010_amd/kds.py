@@ -20,10 +20,11 @@ KDS_OK, KDS_E_INVALID, KDS_E_NOMEM, KDS_E_DEVICE, KDS_E_STATE, KDS_E_NONFINITE, 
 STATUS_NAMES = {0: "KDS_OK", 1: "KDS_E_INVALID", 2: "KDS_E_NOMEM", 3: "KDS_E_DEVICE",
                 4: "KDS_E_STATE", 5: "KDS_E_NONFINITE", 6: "KDS_E_UNSUPPORTED"}
 KDS_FP64, KDS_FP32, KDS_FP32_SPLIT_F16, KDS_FP32_SPLIT_BF16 = range(4)
-KDS_SCHED_AUTO, KDS_SCHED_PLAIN, KDS_SCHED_LINE = range(3)
+KDS_SCHED_AUTO, KDS_SCHED_PLAIN, KDS_SCHED_LINE, KDS_SCHED_FRONT = range(4)
 PRECISIONS = {"fp64": KDS_FP64, "fp32": KDS_FP32, "fp32_split_f16": KDS_FP32_SPLIT_F16,
               "fp32_split_bf16": KDS_FP32_SPLIT_BF16}
-SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED_LINE}
+SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED_LINE,
+             "front": KDS_SCHED_FRONT}
 N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune",
             "kds_time_kernels", "kds_moments",

@@ -74,6 +74,34 @@ def d3q6(lam: float) -> list[float]:
     return v
 
 
+def d3q4(lam: float) -> list[float]:
+    """The paper's D3Q4 set (Sec. 6.1.3): lambda (1,1,1), (1,-1,-1), (-1,1,-1), (-1,-1,1)."""
+    return [lam, lam, lam, lam, -lam, -lam, -lam, lam, -lam, -lam, -lam, lam]
+
+
+def maxwell_params() -> list[float]:
+    """Q^i = A^i W for W = (E, H), Q(W, N) = (-N x H, N x E) (Sec. 6.1.1)."""
+    A = np.zeros((3, 6, 6))
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        for col in range(3):
+            u = np.zeros(3)
+            u[col] = 1.0
+            A[i, 0:3, 3 + col] = -np.cross(e, u)
+            A[i, 3:6, col] = np.cross(e, u)
+    return [float(v) for v in A.ravel()]
+
+
+def w_plane_wave(X, t, freq=1):
+    """Plane wave of Sec. 6.2: E_z = cos(2 pi nu (x - t)), H_y = -E_z."""
+    W = np.zeros(X.shape[:-1] + (6,))
+    c = np.cos(2 * np.pi * freq * (X[..., 0] - t))
+    W[..., 2] = c
+    W[..., 4] = -c
+    return W
+
+
 def _box(d):
     return [0.0] * 3, [1.0 if a < d else 1.0 for a in range(3)]
 
@@ -173,7 +201,10 @@ def euler_speeds(W, d, gamma=1.4):
 def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=None,
                   beta=None, omega=None, n_iter=3, theta=0.5, seed=None,
                   precision="fp32", source_sigma=None):
-    """Return (spec, W0) for workload ``cfg`` (1..4), optionally resized.
+    """Return (spec, W0) for workload ``cfg`` (1..4, 6), optionally resized.
+
+    6 is the paper's own setting: Maxwell's equations with the D3Q4 velocity
+    set, a plane wave along x (Sec. 6.2) in the periodic unit cube.
 
     spec is a plain dict (problem description); W0 has shape [cell, node, m].
     """
@@ -209,6 +240,19 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         law = LAW_LINEAR
         vel = d2q4(lam)
         name = "acoustics2d_q2"
+    elif cfg == 6:
+        d, p, m = 3, 2, 6
+        N = n_cells or [16, 16, 16]
+        S = sub_cells or [4, 4, 4]
+        beta = 8.0 if beta is None else beta
+        omega = (2.0 - 1e-12) if omega is None else omega
+        steps = 10 if steps is None else steps
+        params = maxwell_params()
+        lam = math.sqrt(3.0)
+        lam_max = 1.0
+        law = LAW_LINEAR
+        vel = d3q4(lam)
+        name = "maxwell3d_d3q4_q2"
     elif cfg in (3, 4):
         d, m = 3, 5
         p = 2 if cfg == 3 else 3
@@ -236,7 +280,9 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         "source_sigma": None if source_sigma is None else [float(v) for v in source_sigma],
     }
     X = node_coords(spec)
-    if cfg == 1:
+    if cfg == 6:
+        W0 = w_plane_wave(X, 0.0)
+    elif cfg == 1:
         W0 = w0_advection(X, rng)
     elif cfg == 2:
         W0 = w0_acoustics(X, rng)

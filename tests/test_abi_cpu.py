@@ -84,7 +84,7 @@ def spec():
     ("n_iter", -1, kds.KDS_E_INVALID),
     ("n_iter", -5, kds.KDS_E_INVALID),
     ("law", 7, kds.KDS_E_INVALID),
-    ("precision", kds.KDS_FP32_SPLIT_F16, kds.KDS_E_UNSUPPORTED),
+    ("schedule", kds.KDS_SCHED_LINE + 10, kds.KDS_E_INVALID),
     ("precision", 9, kds.KDS_E_INVALID),
     ("schedule", 5, kds.KDS_E_INVALID),
 ])
@@ -106,10 +106,22 @@ def test_create_rejects_non_periodic(spec):
     assert st == kds.KDS_E_UNSUPPORTED
 
 
-def test_create_rejects_oblique_velocity(spec):
+@pytest.mark.parametrize("sched", ["line", "plain"])
+def test_create_rejects_oblique_velocity_outside_front_schedule(spec, sched):
     s = dict(spec, vel=[1.0, 1.0, -1.0, 0.0, 0.0, 1.0, 0.0, -1.0])
+    st, msg = _create_status(s, schedule=sched)
+    assert st == kds.KDS_E_UNSUPPORTED and "front" in msg
+
+
+def test_create_rejects_split_precision_outside_front_schedule(spec):
+    st, msg = _create_status(spec, precision="fp32_split_f16", schedule="line")
+    assert st == kds.KDS_E_UNSUPPORTED
+
+
+def test_create_rejects_zero_velocity(spec):
+    s = dict(spec, vel=[1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, -1.0])
     st, msg = _create_status(s)
-    assert st == kds.KDS_E_UNSUPPORTED and "axis" in msg
+    assert st == kds.KDS_E_INVALID
 
 
 def test_create_rejects_missing_law_params(spec):

@@ -542,3 +542,21 @@ def test_source_step_is_second_order_in_time(orc):
         F, W = orc.run(spec, W0, n)
         errs.append(abs(W[0, 0, 0] - math.exp(-sigma * T)))
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+# ------------------------------------------------- D3Q4 Maxwell (Sec. 6)
+
+def _plane_wave_error(orc, N, beta, p=2, T=0.25):
+    spec, W0 = wl.make_workload(6, n_cells=[N] * 3, sub_cells=[N // 2] * 3, beta=beta, degree=p)
+    n = max(1, int(round(T / spec["dt"])))
+    spec["dt"] = T / n
+    F, W = orc.run(spec, W0, n, threads=8)
+    exact = wl.w_plane_wave(wl.node_coords(spec), T)
+    return float(np.max(np.abs(W - exact)))
+
+
+def test_d3q4_maxwell_plane_wave_second_order_in_time(orc):
+    """The paper's setting (D3Q4, lambda = sqrt 3, omega = 2 - 1e-12, Sec. 6.1):
+    the plane wave of Sec. 6.2 is approached at second order in dt."""
+    e = [_plane_wave_error(orc, 8, b) for b in (2.0, 1.0, 0.5)]
+    assert e[0] / e[1] > 2.4 and e[1] / e[2] > 3.0, e

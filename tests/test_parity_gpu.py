@@ -219,3 +219,56 @@ def test_converged_mode_rejected_by_plain_schedule():
     with pytest.raises(kds.KdsError) as ei:
         kds.Problem(spec, precision="fp32", schedule="plain")
     assert ei.value.status == kds.KDS_E_UNSUPPORTED
+
+
+# ------------------------------------------------------------ front schedule
+
+FRONT_CASES = {
+    # the paper's D3Q4 velocity set with Maxwell's equations (plane wave)
+    "maxwell_q2": (6, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=3)),
+    "maxwell_q1_ragged": (6, dict(n_cells=[6, 8, 4], sub_cells=[3, 4, 2], steps=2, degree=1)),
+    "maxwell_q3": (6, dict(n_cells=[4, 4, 4], sub_cells=[2, 4, 4], steps=2, degree=3)),
+    "maxwell_q2_k1_theta1": (6, dict(n_cells=[8, 4, 4], sub_cells=[4, 2, 4], steps=2,
+                                     n_iter=1, theta=1.0)),
+    # axis-aligned sets through the front kernel (cross-check of the schedules)
+    "cfg2_front": (2, dict(n_cells=[24, 16], sub_cells=[8, 8], steps=3)),
+    "cfg3_front": (3, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 4], steps=2)),
+}
+# FP16 split: three FP16 products recover ~FP32 accuracy; BF16 split keeps ~16
+# significant bits per product (measured 1e-5 .. 4e-5 over 2-3 steps)
+FRONT_TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_split_f16": 1e-5, "fp32_split_bf16": 1e-4}
+
+
+@functools.lru_cache(maxsize=None)
+def front_case(name):
+    from oracle import oracle
+    from paper_2212_11010_amd import workloads as wl
+    cfg, ov = FRONT_CASES[name]
+    spec, W0 = wl.make_workload(cfg, **ov)
+    F, W = oracle.run(spec, W0, spec["steps"], threads=0)
+    return spec, W0, np.ascontiguousarray(F.transpose(0, 2, 3, 1)), W
+
+
+@pytest.mark.parametrize("name", list(FRONT_CASES))
+@pytest.mark.parametrize("prec", list(FRONT_TOL))
+def test_front_schedule_parity(name, prec):
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, Fref, Wref = front_case(name)
+    print("front case", name, prec, flush=True)
+    with kds.Problem(spec, precision=prec, schedule="front") as pb:
+        assert pb.info()["schedule"] == kds.KDS_SCHED_FRONT
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(spec["steps"])
+        W = pb.moments()
+        F = pb.get_kinetic()
+    ew, ef = relerr(W, Wref), relerr(F, Fref)
+    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
+    assert ew <= FRONT_TOL[prec] and ef <= FRONT_TOL[prec], (ew, ef)
+
+
+def test_auto_picks_front_for_oblique_velocities():
+    from paper_2212_11010_amd import kds
+    spec, _, _, _ = front_case("maxwell_q2")
+    with kds.Problem(spec, precision="fp32") as pb:
+        assert pb.info()["schedule"] == kds.KDS_SCHED_FRONT
