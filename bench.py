@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-DOF-velocity updates/s per step, FP32-MFMA batched vs plain FP64 sweep"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {"line": "k_sweep_line", "plain": "k_sweep_plain", "relax": "k_relax"}
+KERNEL_NAMES = {"line": "k_sweep_line", "plain": "k_sweep_plain", "front": "k_sweep_front",
+                "relax": "k_relax"}
+MFMA_PEAK_TFS = {"fp32": 157.3, "fp32_split_f16": 2500.0, "fp32_split_bf16": 2500.0}
 KERNEL_SOURCES = ["paper_2212_11010_amd/csrc/kds_kernels.hip"]
 
 
@@ -42,10 +44,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def workload(name):
+def workload(name, cells=0, sub=0):
     from paper_2212_11010_amd import workloads as wl
-    cfg = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}[name]
-    return wl.make_workload(cfg)
+    cfg = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4, "maxwell": 6}[name]
+    kw = {}
+    if cells:
+        d = 2 if cfg in (1, 2) else 3
+        kw["n_cells"] = [cells] * d
+        kw["sub_cells"] = [sub or cells] * d
+    return wl.make_workload(cfg, **kw)
 
 
 def time_problem(spec, W0, prec, sched, steps, warmup, tune=False):
@@ -157,6 +164,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--schedule", default="auto")
+    ap.add_argument("--cells", type=int, default=0, help="cells per axis (default: the workload's)")
+    ap.add_argument("--sub", type=int, default=0, help="subdomain cells per axis with --cells")
+    ap.add_argument("--precision", default="fp32", help="fp32 | fp32_split_f16 | fp32_split_bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-plan autotuner")
@@ -187,20 +197,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2212_11010_amd import workloads as wl
 
-    spec, W0 = workload(args.workload)
+    spec, W0 = workload(args.workload, args.cells, args.sub)
     U = wl.unknowns(spec)
     log("workload %s U=%d dt=%.5g nu=%.3f" % (spec["name"], U, spec["dt"], spec["kinetic_courant"]))
 
-    ms32, k32, info32, ok32 = time_problem(spec, W0, "fp32", args.schedule, args.steps, args.warmup,
-                                           tune=not args.no_tune)
-    sched = {1: "plain", 2: "line"}[info32["schedule"]]
+    ms32, k32, info32, ok32 = time_problem(spec, W0, args.precision, args.schedule, args.steps,
+                                           args.warmup, tune=not args.no_tune)
+    sched = {1: "plain", 2: "line", 3: "front"}[info32["schedule"]]
     log("fp32 %s: %.4f ms/step (graph), kernels %s ms" % (sched, ms32, k32))
     extra = {"fp32_schedule": sched, "fp32_kernel_ms": {"sweep": k32[0], "relax": k32[1]},
              "fp32_state_finite": ok32, "line_plan": {"cells_per_lane": info32["line_Q"][:spec["dim"]],
                                                       "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
                                                       "autotuned": bool(info32["tuned"])}}
     if not args.no_fp64:
-        ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", "plain", max(5, args.steps // 5), 2)
+        base = "front" if sched == "front" else "plain"
+        ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2)
         log("fp64 plain: %.4f ms/step, kernels %s ms" % (ms64, k64))
         extra.update({"fp64_plain_value": U / (ms64 * 1e-3), "fp64_plain_ms_per_step": ms64,
                       "fp64_plain_kernel_ms": {"sweep": k64[0], "relax": k64[1]},
@@ -219,10 +230,24 @@ def main():
             "kernel": kname, "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": dur_s * 1e3}
 
+    if sched == "front":
+        # dense cell solves: 2 Kd flop per unknown per launch (one subdomain
+        # iteration), Kd = nn + 3 nf; the split forms execute three products
+        P = spec["degree"] + 1
+        nn = P ** spec["dim"]
+        Kd = nn + 3 * (nn // P)
+        flops = 2.0 * Kd * U * (3 if "split" in args.precision else 1)
+        sweep_s = k32[0] * 1e-3
+        extra["front_mfma"] = {"executed_tflops": flops / sweep_s / 1e12,
+                               "peak_tflops": MFMA_PEAK_TFS[args.precision],
+                               "frac": flops / sweep_s / 1e12 / MFMA_PEAK_TFS[args.precision],
+                               "hbm_gbs_algorithmic": 8.0 * U / sweep_s / 1e9}
     out = {
         "metric": METRIC, "value": U / (ms32 * 1e-3), "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp32_split_f16": "f32 (f16x3 products)",
+                  "fp32_split_bf16": "f32 (bf16x3 products)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": spec["name"], "n_cells": spec["n_cells"][:spec["dim"]],
                    "sub_cells": spec["sub_cells"][:spec["dim"]], "degree": spec["degree"],

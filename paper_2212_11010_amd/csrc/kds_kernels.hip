@@ -839,6 +839,8 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
 // matrix cores (x = hi + lo, W X ~ Wh Xh + Wh Xl + Wl Xh, FP32 accumulation;
 // the FP16 low parts are scaled by 2^11 against underflow).
 
+constexpr int kFrontMaxChunk = 64;  // GEMM columns per pass (col_chunk)
+
 typedef float kds_f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 kds_f16x4 __attribute__((ext_vector_type(4)));
 typedef short kds_i16x4 __attribute__((ext_vector_type(4)));
@@ -866,6 +868,10 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
   const int XS = CH + 1;  // odd row stride: conflict-free gathers
   T* Wt = reinterpret_cast<T*>(smem_raw);            // [Mpad][Kpad] (matrix-core modes)
   T* X = Wt + (MODE == kFrontFma ? 0 : Mpad * Kpad);  // [Kpad][XS]
+  __shared__ int64_t col_base[kFrontMaxChunk];         // per column: state offset of the cell
+  __shared__ int64_t col_nb[3][kFrontMaxChunk];        // ... of the upwind neighbour per face
+  __shared__ unsigned char col_int[3][kFrontMaxChunk]; // neighbour inside the subdomain?
+  __shared__ int face_node[3 * kMaxP * kMaxP * kMaxP]; // neighbour node of face row q
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const int k = blockIdx.x / nsd;
   const int sd = blockIdx.x - k * nsd;
@@ -884,9 +890,22 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
     sgn[a] = a < g.dim ? fp.sg[k][a] : 0;
     outn[a] = sgn[a] > 0 ? P - 1 : 0;  // neighbour's node index on the shared face
   }
-  int pw[3] = {1, P, P * P};
+  const int pw[3] = {1, P, P * P};
   const int64_t plane = g.ncell * nn;
   const int nlev = fp.nlev[k];
+  // node of the upwind neighbour matching face row (a, q): index outn[a] on
+  // axis a, the other indices from q (x fastest)
+  for (int t = tid; t < 3 * nf; t += bs) {
+    const int a = t / nf, q = t - a * nf;
+    int node = 0, rem = q;
+    for (int o = 0; o < g.dim; ++o) {
+      int io;
+      if (o == a) io = outn[a];
+      else { io = rem % P; rem /= P; }
+      node += io * pw[o];
+    }
+    face_node[t] = a < g.dim ? node : 0;
+  }
   __syncthreads();
 
   for (int lev = 0; lev < nlev; ++lev) {
@@ -895,53 +914,10 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
     const int ncol = (c1 - c0) * m;
     for (int j0 = 0; j0 < ncol; j0 += CH) {
       const int nc = min(CH, ncol - j0);
-      // ---- gather X[r][jj]: r fastest over threads (contiguous nodes)
-      for (int e = tid; e < Kpad * CH; e += bs) {
-        const int jj = e / Kpad, r = e - jj * Kpad;
-        T v = T(0);
-        if (jj < nc && r < Kd) {
-          const int j = j0 + jj;
-          const int ci = c0 + j / m, c = j - (j / m) * m;
-          const int pk = lvl_cells[ci];
-          const int lc[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
-          int gc[3];
-          for (int a = 0; a < 3; ++a) {
-            const int pl = sgn[a] < 0 ? g.S[a] - 1 - lc[a] : lc[a];
-            gc[a] = sdc[a] * g.S[a] + pl;
-          }
-          const int64_t kc = (int64_t)(k * m + c) * plane;
-          if (r < nn) {
-            const int64_t cell = gc[0] + (int64_t)g.N[0] * (gc[1] + (int64_t)g.N[1] * gc[2]);
-            v = f_old[kc + cell * nn + r];
-          } else {
-            const int a = (r - nn) / nf, q = (r - nn) - a * nf;
-            if (a < g.dim && sgn[a] != 0) {
-              int nb[3] = {gc[0], gc[1], gc[2]};
-              nb[a] -= sgn[a];
-              if (nb[a] < 0) nb[a] += g.N[a];
-              if (nb[a] >= g.N[a]) nb[a] -= g.N[a];
-              const bool internal = lc[a] > 0;
-              // neighbour node: index outn[a] on axis a, the others from q
-              int node = 0, rem = q;
-              for (int o = 0; o < g.dim; ++o) {
-                int io;
-                if (o == a) io = outn[a];
-                else { io = rem % P; rem /= P; }
-                node += io * pw[o];
-              }
-              const int64_t nbc = nb[0] + (int64_t)g.N[0] * (nb[1] + (int64_t)g.N[1] * nb[2]);
-              const int64_t at = kc + nbc * nn + node;
-              const T tn = internal ? f_cur[at] : f_prev[at];
-              v = th * tn + (T(1) - th) * f_old[at];
-            }
-          }
-        }
-        X[r * XS + jj] = v;
-      }
-      __syncthreads();
-      // ---- Y = W X, written to the current iterate
-      auto store = [&](int i, int jj, T y) {
-        const int j = j0 + jj;
+      // ---- column descriptors: state offset of the column's cell, and of the
+      // upwind neighbour across each inflow face (flagged internal / interface)
+      if (tid < nc) {
+        const int j = j0 + tid;
         const int ci = c0 + j / m, c = j - (j / m) * m;
         const int pk = lvl_cells[ci];
         const int lc[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
@@ -950,9 +926,73 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
           const int pl = sgn[a] < 0 ? g.S[a] - 1 - lc[a] : lc[a];
           gc[a] = sdc[a] * g.S[a] + pl;
         }
-        const int64_t cell = gc[0] + (int64_t)g.N[0] * (gc[1] + (int64_t)g.N[1] * gc[2]);
-        f_cur[(int64_t)(k * m + c) * plane + cell * nn + i] = y;
-      };
+        const int64_t kc = (int64_t)(k * m + c) * plane;
+        col_base[tid] = kc + (gc[0] + (int64_t)g.N[0] * (gc[1] + (int64_t)g.N[1] * gc[2])) * nn;
+        for (int a = 0; a < 3; ++a) {
+          int64_t nbo = -1;
+          if (a < g.dim && sgn[a] != 0) {
+            int nb[3] = {gc[0], gc[1], gc[2]};
+            nb[a] -= sgn[a];
+            if (nb[a] < 0) nb[a] += g.N[a];
+            if (nb[a] >= g.N[a]) nb[a] -= g.N[a];
+            nbo = kc + (nb[0] + (int64_t)g.N[0] * (nb[1] + (int64_t)g.N[1] * nb[2])) * nn;
+            col_int[a][tid] = lc[a] > 0 ? 1 : 0;
+          }
+          col_nb[a][tid] = nbo;
+        }
+      }
+      __syncthreads();
+      // ---- gather X[r][jj] (r fastest over threads: contiguous nodes); U
+      // independent loads per thread are issued before any is used
+      {
+        constexpr int U = 4;
+        const int total = Kpad * CH;
+        for (int e0 = tid; e0 < total; e0 += U * bs) {
+          T vo[U], vn[U];
+          int rr[U], jq[U];
+          int face[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bs;
+            const int jj = e / Kpad, r = e - jj * Kpad;
+            rr[u] = r;
+            jq[u] = jj;
+            int64_t at = 0;
+            int fa = -1;
+            bool live = e < total && jj < nc && r < Kd;
+            if (live) {
+              if (r < nn) {
+                at = col_base[jj] + r;
+              } else {
+                const int a = (r - nn) / nf;
+                if (col_nb[a][jj] >= 0) {
+                  fa = a;
+                  at = col_nb[a][jj] + face_node[r - nn];
+                } else {
+                  live = false;
+                }
+              }
+            }
+            face[u] = live ? fa : -2;
+            // inactive slots re-read element 0 of the state (never used)
+            vo[u] = f_old[live ? at : 0];
+            vn[u] = (fa >= 0 && col_int[fa][jj]) ? f_cur[at] : f_prev[fa >= 0 ? at : 0];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bs;
+            if (e < total) {
+              T v = T(0);
+              if (face[u] == -1) v = vo[u];
+              else if (face[u] >= 0) v = th * vn[u] + (T(1) - th) * vo[u];
+              X[rr[u] * XS + jq[u]] = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // ---- Y = W X, written to the current iterate
+      auto store = [&](int i, int jj, T y) { f_cur[col_base[jj] + i] = y; };
       if constexpr (MODE == kFrontFma) {
         for (int e = tid; e < nn * nc; e += bs) {
           const int jj = e / nn, i = e - jj * nn;
