@@ -10,6 +10,7 @@ state resident in HBM.  Prints ONE JSON line:
   extra        the plain FP64 GPU sweep (the reference GPU path) and speedup
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+       (--workload: cfg1..cfg4, maxwell, batch = 48 uneven problems together)
 """
 from __future__ import annotations
 
@@ -157,6 +158,119 @@ def cpu_baseline(spec, W0, budget_s=12.0):
                       "OpenMP over (velocity, component) transports" % n}
 
 
+def bench_batch(args):
+    """The many-problem workload: 48 seeded uneven problems advanced together
+    by kds_batch_step (grouped launches, one captured graph per step)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    specs = wl.make_batch_workload()
+    U = sum(wl.unknowns(s) for s in specs)
+    log("batch of %d problems, U=%d" % (len(specs), U))
+
+    states = {}   # host copies of the seeded initial states (sampled once)
+
+    def build(prec, sched, tune):
+        members = []
+        for s in specs:
+            if s["name"] not in states:
+                states[s["name"]] = wl.batch_member_state(s)
+                log("  sampled %s (%d unknowns)" % (s["name"], wl.unknowns(s)))
+            pb = kds.Problem(s, precision=prec, schedule=sched)
+            pb.set_state(torch.from_numpy(states[s["name"]]).cuda())
+            if tune:
+                pb.tune(3)
+            members.append(pb)
+        return members
+
+    members = build(args.precision, args.schedule, not args.no_tune)
+    scheds = [{1: "plain", 2: "line", 3: "front"}[pb.info()["schedule"]] for pb in members]
+    log("schedules: %s" % {k: scheds.count(k) for k in set(scheds)})
+    b = kds.Batch(members)
+    b.step(args.warmup)
+    b.synchronize()
+    torch.cuda.synchronize()
+    ms_total = b.step_timed(args.steps)        # HIP events on the batch stream
+    ms32 = ms_total / args.steps
+    kms = b.time_kernels(args.steps)          # grouped sweep / relax launches per step
+    # the same members stepped one problem at a time (own graphs), for the
+    # gain of grouping
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pb in members:
+        pb.step(args.steps)
+    for pb in members:
+        pb.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3 / args.steps
+    # and their own kernels' durations (line members; HIP events per problem)
+    single_k = [0.0, 0.0]
+    for pb, sc in zip(members, scheds):
+        if sc == "line":
+            k = pb.time_kernels(max(2, args.steps // 2))
+            single_k[0] += k[0]
+            single_k[1] += k[1]
+    ok = all(pb.check_finite() for pb in members)
+    log("batched %.3f ms/step (sweeps %.3f, relax %.3f), one by one %.3f ms/step"
+        % (ms32, kms[0], kms[1], ms_single))
+    b.close()
+    U_line = sum(wl.unknowns(s) for s, sc in zip(specs, scheds) if sc == "line")
+    for pb in members:
+        pb.close()
+    extra = {"schedules": {k: scheds.count(k) for k in set(scheds)},
+             "grouped_kernel_ms": {"sweep": kms[0], "relax": kms[1]},
+             "one_by_one_ms_per_step": ms_single,
+             "one_by_one_line_member_kernel_ms": {"sweep": single_k[0], "relax": single_k[1]},
+             "speedup_batched_vs_one_by_one": ms_single / ms32,
+             "state_finite": ok}
+    if not args.no_fp64:
+        m64 = build("fp64", "plain", False)
+        n64 = max(2, args.steps // 10)
+        b64 = kds.Batch(m64)
+        b64.step(1)
+        ms64 = b64.step_timed(n64) / n64
+        b64.close()
+        for pb in m64:
+            pb.close()
+        log("fp64 plain batch: %.3f ms/step" % ms64)
+        extra.update({"fp64_plain_value": U / (ms64 * 1e-3), "fp64_plain_ms_per_step": ms64,
+                      "speedup_fp32_vs_fp64_plain": ms64 / ms32})
+    alg_bytes = 8.0 * U_line
+    dur_s = kms[0] * 1e-3
+    achieved = alg_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_line_batch",
+            "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": kms[0],
+            "note": "sum over the grouped line-sweep launches of one step"}
+    out = {
+        "metric": METRIC, "value": U / (ms32 * 1e-3), "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch48_acoustics2d_euler3d_mixed", "problems": len(specs),
+                   "unknowns": U, "n_iter": specs[0]["n_iter"]},
+        "roofline": roof, "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+        u_done, t_done, names = 0, 0.0, []
+        for s in sorted(specs, key=wl.unknowns):
+            cfg = oracle.Config(s)
+            F = oracle.init(cfg, states[s["name"]])
+            t0 = time.perf_counter()
+            oracle.step(cfg, F, 1, threads)
+            t_done += time.perf_counter() - t0
+            u_done += wl.unknowns(s)
+            names.append(s["name"])
+            if t_done > 12.0:
+                break
+        out["cpu_baseline"] = {"value": u_done / t_done, "unit": "updates/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "one time step of each of the %d smallest members "
+                                         "(%d unknowns), FP64 oracle" % (len(names), u_done)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +311,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2212_11010_amd import workloads as wl
 
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     spec, W0 = workload(args.workload, args.cells, args.sub)
     U = wl.unknowns(spec)
     log("workload %s U=%d dt=%.5g nu=%.3f" % (spec["name"], U, spec["dt"], spec["kinetic_courant"]))

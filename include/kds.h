@@ -191,11 +191,58 @@ typedef struct {
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 
-/* Release device memory, graph and (own) stream.  NULL is allowed. */
+/* Release device memory, graph and (own) stream.  NULL is allowed.  A batch
+ * holding p must be destroyed first. */
 void kds_destroy(kds_problem* p);
 
 /* Last error message of p, or the thread-local kds_create message if p is NULL. */
 const char* kds_last_error(const kds_problem* p);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (any sizes, laws, degrees, schedules) advanced
+ * together by one time step each per kds_batch_step.  The members keep their
+ * own states; a batch step gives exactly the results of kds_step on every
+ * member (the same kernels' arithmetic), but the line sweeps of all members
+ * sharing (precision, degree, dimension, workgroup size) run as ONE launch
+ * whose workgroups are spread over the members, and likewise the relaxations
+ * of members sharing (precision, law, d, m, n_vel); plain- and front-schedule
+ * members add their own kernel sequences.  A whole batched step is one
+ * captured HIP graph on the batch's own stream, ordered after the work already
+ * queued on every member's stream; the members' streams are ordered after it.
+ * Members must be on one device and distinct; the batch keeps pointers to
+ * them (destroy the batch before its members).  A member re-tuned by kds_tune
+ * is picked up at the next batch step.  Not thread safe. */
+typedef struct kds_batch kds_batch; /* opaque, library-owned */
+
+/* Group the members and upload the task tables (device memory owned by the
+ * batch).  Errors: KDS_E_INVALID (NULL, duplicate, devices differ),
+ * KDS_E_UNSUPPORTED (a grouped launch would exceed a launch limit),
+ * KDS_E_NOMEM, KDS_E_DEVICE; message in kds_batch_last_error(NULL). */
+kds_status kds_batch_create(kds_problem* const* problems, int32_t n, kds_batch** out);
+
+/* n_steps time steps of every member (kds_step semantics), asynchronously.
+ * KDS_E_STATE if a member has no state.  Each member's steps_done grows. */
+kds_status kds_batch_step(kds_batch* b, int32_t n_steps);
+
+/* Same, then waits; *ms = milliseconds between HIP events recorded on the
+ * batch stream around the n_steps graph launches.  For measurement. */
+kds_status kds_batch_step_timed(kds_batch* b, int32_t n_steps, double* ms);
+
+/* Average duration of the batch's grouped kernels per step: kernel_ms[0] =
+ * sum over the grouped line-sweep launches, kernel_ms[1] = sum over the
+ * grouped relaxations (reps back-to-back launches each, HIP events on the
+ * batch stream); line-schedule member states are saved and restored (needs
+ * their size in free device memory).  For measurement. */
+kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms);
+
+/* Wait for the batch stream. */
+kds_status kds_batch_synchronize(kds_batch* b);
+
+/* Release the batch (not its members).  NULL is allowed. */
+void kds_batch_destroy(kds_batch* b);
+
+/* Last error message of b, or the thread-local kds_batch_create message if b is NULL. */
+const char* kds_batch_last_error(const kds_batch* b);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,7 @@ struct kds_problem {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   bool state_set = false;
   int steps_done = 0;
+  int plan_version = 0;  // bumped when the launch plan changes (batches rebuild)
   std::string err;
 
   int64_t plane() const { return ncell * nn; }
@@ -343,40 +344,40 @@ void free_device(kds_problem* p) {
 // Enqueue one time step (transport then relaxation) on the problem's stream.
 // With events, records ev[0] before the transport, ev[1] between transport and
 // relaxation, ev[2] after.
-kds_status enqueue_step(kds_problem* p, bool events) {
+kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
   const Geom& g = p->geom;
-  if (events) KDS_HIP(p, hipEventRecord(p->ev[0], p->stream));
+  if (events) KDS_HIP(p, hipEventRecord(p->ev[0], s));
   if (p->sched == KDS_SCHED_FRONT) {
     for (int it = 1; it <= p->K; ++it) {
       const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
       KDS_HIP(p, launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
                                     p->front_lvl_start, p->front_lvl_cells, p->f, f_prev,
-                                    p->fit[it & 1], p->stream));
+                                    p->fit[it & 1], s));
     }
-    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->fit[p->K & 1], p->f, p->stream));
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->fit[p->K & 1], p->f, s));
   } else if (p->sched == KDS_SCHED_LINE) {
-    KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream));
-    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream));
+    KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, s));
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, s));
   } else {
     for (int it = 1; it <= p->K; ++it) {
       const void* tr_prev = it == 1 ? nullptr : p->tr[(it - 1) & 1];
       void* f_new = it == p->K ? p->f_tmp : nullptr;
       KDS_HIP(p, launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, f_new, tr_prev,
-                                    p->tr[it & 1], p->stream));
+                                    p->tr[it & 1], s));
     }
-    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], p->stream));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f_tmp, p->f, p->stream));
+    if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f_tmp, p->f, s));
   }
-  if (events) KDS_HIP(p, hipEventRecord(p->ev[2], p->stream));
+  if (events) KDS_HIP(p, hipEventRecord(p->ev[2], s));
   return KDS_OK;
 }
 
 kds_status ensure_graph(kds_problem* p) {
   if (p->graph_exec) return KDS_OK;
   KDS_HIP(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  kds_status st = enqueue_step(p, false);
+  kds_status st = enqueue_step(p, false, p->stream);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(p->stream, &graph);
   if (st != KDS_OK) {
@@ -674,7 +675,7 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms) {
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step_timed before kds_set_state");
   double acc[KDS_N_KERNEL_KINDS] = {0, 0};
   for (int i = 0; i < n_steps; ++i) {
-    kds_status st = enqueue_step(p, true);
+    kds_status st = enqueue_step(p, true, p->stream);
     if (st != KDS_OK) return st;
     KDS_HIP(p, hipEventSynchronize(p->ev[2]));
     float t01 = 0, t12 = 0;
@@ -758,6 +759,7 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   p->graph_exec = nullptr;
   p->graph = nullptr;
   p->tuned = true;
+  ++p->plan_version;
   if (sweep_ms) *sweep_ms = best;
   return KDS_OK;
 }
@@ -911,6 +913,358 @@ void kds_destroy(kds_problem* p) {
 
 const char* kds_last_error(const kds_problem* p) {
   return p ? p->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"
+
+// ================================================================ batches
+// Many problems advanced together: the line sweeps of all line-schedule
+// members that share (precision, degree, dimension, workgroup size) run as one
+// launch, their relaxations as one launch per (precision, law, d, m, n_vel);
+// plain- and front-schedule members add their own kernel sequences.  The whole
+// step is one captured HIP graph on the batch's stream.
+
+struct kds_batch {
+  struct Group {
+    bool line = true;
+    int prec = 0, P = 0, dim = 0, threads = 0, law = 0, m = 0, nv = 0;
+    size_t lds_elems = 0;
+    std::vector<unsigned char> tasks;  // packed task records (host)
+    std::vector<int64_t> start{0};     // block prefix over the members
+    void* d_tasks = nullptr;
+    int64_t* d_start = nullptr;
+  };
+  std::vector<kds_problem*> probs;
+  std::vector<int> versions;
+  std::vector<Group> groups;
+  std::vector<kds_problem*> others;  // members not in a line group
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_join = nullptr, ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::string err;
+};
+
+namespace {
+
+kds_status bfail(kds_batch* b, kds_status st, const std::string& msg) {
+  if (b) b->err = msg; else g_create_error = msg;
+  return st;
+}
+
+#define KDS_BHIP(b, call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return bfail((b), KDS_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_free_groups(kds_batch* b) {
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+  for (auto& g : b->groups) {
+    if (g.d_tasks) (void)hipFree(g.d_tasks);
+    if (g.d_start) (void)hipFree(g.d_start);
+  }
+  b->groups.clear();
+  b->others.clear();
+}
+
+// Group the members and upload the task tables (blocking copies).
+kds_status batch_build(kds_batch* b) {
+  batch_free_groups(b);
+  for (kds_problem* p : b->probs) {
+    if (p->sched != KDS_SCHED_LINE) {
+      b->others.push_back(p);
+      continue;
+    }
+    const Geom& g = p->geom;
+    kds_batch::Group* lg = nullptr;
+    kds_batch::Group* rg = nullptr;
+    for (auto& gr : b->groups) {
+      if (gr.line && gr.prec == p->prec && gr.P == p->P && gr.dim == p->dim &&
+          gr.threads == p->plan.threads)
+        lg = &gr;
+      if (!gr.line && gr.prec == p->prec && gr.law == p->law && gr.dim == p->dim &&
+          gr.m == p->m && gr.nv == p->nv)
+        rg = &gr;
+    }
+    if (!lg) {
+      b->groups.emplace_back();
+      lg = &b->groups.back();
+      lg->line = true;
+      lg->prec = p->prec;
+      lg->P = p->P;
+      lg->dim = p->dim;
+      lg->threads = p->plan.threads;
+    }
+    {
+      const size_t tb = line_task_bytes(p->prec);
+      const size_t off = lg->tasks.size();
+      lg->tasks.resize(off + tb);
+      pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, lg->tasks.data() + off);
+      lg->start.push_back(lg->start.back() + p->plan.block_start[g.nv * g.m]);
+      lg->lds_elems = std::max(lg->lds_elems, (size_t)p->plan.lds_elems);
+    }
+    // (the vector may have grown: find the relax group again)
+    rg = nullptr;
+    for (auto& gr : b->groups)
+      if (!gr.line && gr.prec == p->prec && gr.law == p->law && gr.dim == p->dim &&
+          gr.m == p->m && gr.nv == p->nv)
+        rg = &gr;
+    if (!rg) {
+      b->groups.emplace_back();
+      rg = &b->groups.back();
+      rg->line = false;
+      rg->prec = p->prec;
+      rg->law = p->law;
+      rg->dim = p->dim;
+      rg->m = p->m;
+      rg->nv = p->nv;
+    }
+    {
+      const size_t tb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
+      if (tb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
+      const size_t off = rg->tasks.size();
+      rg->tasks.resize(off + tb);
+      pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->f, p->f, p->plane(),
+                      rg->tasks.data() + off);
+      rg->start.push_back(rg->start.back() + (p->plane() + 255) / 256);
+    }
+  }
+  for (auto& gr : b->groups) {
+    if (gr.start.back() > 0x7fffffffLL)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched launch exceeds the grid limit");
+    if (gr.line && gr.lds_elems * (gr.prec == KDS_FP64 ? 8 : 4) > 64 * 1024)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched line sweep needs more than 64 KiB of LDS");
+    if (hipMalloc(&gr.d_tasks, gr.tasks.size()) != hipSuccess ||
+        hipMalloc((void**)&gr.d_start, gr.start.size() * sizeof(int64_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, KDS_E_NOMEM, "batch task tables");
+    }
+    KDS_BHIP(b, hipMemcpy(gr.d_tasks, gr.tasks.data(), gr.tasks.size(), hipMemcpyHostToDevice));
+    KDS_BHIP(b, hipMemcpy(gr.d_start, gr.start.data(), gr.start.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice));
+  }
+  for (size_t i = 0; i < b->probs.size(); ++i) b->versions[i] = b->probs[i]->plan_version;
+  return KDS_OK;
+}
+
+// One batched step.  With events: ev[0] before, ev[1] after the line sweeps.
+kds_status batch_enqueue(kds_batch* b, bool events) {
+  for (auto& gr : b->groups)
+    if (gr.line)
+      KDS_BHIP(b, launch_sweep_line_batch(gr.prec, gr.P, gr.dim, gr.d_tasks, gr.d_start,
+                                          (int)(gr.start.size() - 1), gr.start.back(), gr.threads,
+                                          gr.lds_elems, b->stream));
+  if (events) KDS_BHIP(b, hipEventRecord(b->ev[1], b->stream));
+  for (auto& gr : b->groups)
+    if (!gr.line)
+      KDS_BHIP(b, launch_relax_batch(gr.prec, gr.law, gr.dim, gr.m, gr.nv, gr.d_tasks, gr.d_start,
+                                     (int)(gr.start.size() - 1), gr.start.back(), b->stream));
+  for (kds_problem* p : b->others) {
+    kds_status st = enqueue_step(p, false, b->stream);
+    if (st != KDS_OK) return bfail(b, st, "batch member: " + p->err);
+  }
+  return KDS_OK;
+}
+
+kds_status batch_prepare(kds_batch* b) {
+  for (kds_problem* p : b->probs)
+    if (!p->state_set) return bfail(b, KDS_E_STATE, "a batch member has no state");
+  bool stale = b->groups.empty() && b->others.empty();
+  for (size_t i = 0; i < b->probs.size(); ++i)
+    if (b->versions[i] != b->probs[i]->plan_version) stale = true;
+  if (stale) {
+    kds_status st = batch_build(b);
+    if (st != KDS_OK) return st;
+  }
+  if (!b->graph_exec) {
+    KDS_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    kds_status st = batch_enqueue(b, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (st != KDS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    KDS_BHIP(b, e);
+    b->graph = graph;
+    KDS_BHIP(b, hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+  }
+  return KDS_OK;
+}
+
+// Order the batch stream after every member stream (work queued there before
+// the batch step), and every member stream after the batch stream.
+kds_status batch_join_in(kds_batch* b) {
+  for (kds_problem* p : b->probs) {
+    if (p->stream == b->stream) continue;
+    KDS_BHIP(b, hipEventRecord(b->ev_join, p->stream));
+    KDS_BHIP(b, hipStreamWaitEvent(b->stream, b->ev_join, 0));
+  }
+  return KDS_OK;
+}
+
+kds_status batch_join_out(kds_batch* b, int32_t n_steps) {
+  KDS_BHIP(b, hipEventRecord(b->ev_join, b->stream));
+  for (kds_problem* p : b->probs) {
+    if (p->stream != b->stream) KDS_BHIP(b, hipStreamWaitEvent(p->stream, b->ev_join, 0));
+    p->steps_done += n_steps;
+  }
+  return KDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kds_status kds_batch_create(kds_problem* const* problems, int32_t n, kds_batch** out) {
+  if (!out) return bfail(nullptr, KDS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!problems || n < 1) return bfail(nullptr, KDS_E_INVALID, "need at least one problem");
+  for (int i = 0; i < n; ++i) {
+    if (!problems[i]) return bfail(nullptr, KDS_E_INVALID, "a problem is NULL");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i])
+        return bfail(nullptr, KDS_E_INVALID, "a problem appears twice in the batch");
+    if (problems[i]->device != problems[0]->device)
+      return bfail(nullptr, KDS_E_INVALID, "batch members must live on one device");
+  }
+  kds_batch* b = new kds_batch();
+  b->probs.assign(problems, problems + n);
+  b->versions.assign(n, -1);
+  b->device = problems[0]->device;
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess) e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipStreamCreate(&b->stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev[1]);
+  kds_status st = KDS_OK;
+  if (e != hipSuccess) st = bfail(nullptr, KDS_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+  if (st == KDS_OK) {
+    st = batch_build(b);
+    if (st != KDS_OK) g_create_error = b->err;
+  }
+  (void)hipSetDevice(cur);
+  if (st != KDS_OK) {
+    kds_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return KDS_OK;
+}
+
+kds_status kds_batch_step(kds_batch* b, int32_t n_steps) {
+  if (!b) return bfail(nullptr, KDS_E_INVALID, "batch is NULL");
+  if (n_steps < 0) return bfail(b, KDS_E_INVALID, "n_steps must be >= 0");
+  kds_status st = batch_prepare(b);
+  if (st != KDS_OK || n_steps == 0) return st;
+  if ((st = batch_join_in(b)) != KDS_OK) return st;
+  for (int i = 0; i < n_steps; ++i) KDS_BHIP(b, hipGraphLaunch(b->graph_exec, b->stream));
+  return batch_join_out(b, n_steps);
+}
+
+kds_status kds_batch_step_timed(kds_batch* b, int32_t n_steps, double* ms) {
+  if (!b) return bfail(nullptr, KDS_E_INVALID, "batch is NULL");
+  if (n_steps < 1 || !ms) return bfail(b, KDS_E_INVALID, "bad arguments");
+  kds_status st = batch_prepare(b);
+  if (st != KDS_OK) return st;
+  if ((st = batch_join_in(b)) != KDS_OK) return st;
+  KDS_BHIP(b, hipEventRecord(b->ev[0], b->stream));
+  for (int i = 0; i < n_steps; ++i) KDS_BHIP(b, hipGraphLaunch(b->graph_exec, b->stream));
+  KDS_BHIP(b, hipEventRecord(b->ev[1], b->stream));
+  KDS_BHIP(b, hipEventSynchronize(b->ev[1]));
+  float t = 0;
+  KDS_BHIP(b, hipEventElapsedTime(&t, b->ev[0], b->ev[1]));
+  *ms = t;
+  return batch_join_out(b, n_steps);
+}
+
+kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms) {
+  if (!b) return bfail(nullptr, KDS_E_INVALID, "batch is NULL");
+  if (!kernel_ms || reps < 1) return bfail(b, KDS_E_INVALID, "bad arguments");
+  kds_status st = batch_prepare(b);
+  if (st != KDS_OK) return st;
+  if ((st = batch_join_in(b)) != KDS_OK) return st;
+  // the grouped kernels update the line-schedule members in place: save them
+  size_t total = 0;
+  for (kds_problem* p : b->probs)
+    if (p->sched == KDS_SCHED_LINE) total += (size_t)p->n_unknowns() * p->elem;
+  unsigned char* save = nullptr;
+  if (total && hipMalloc((void**)&save, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, KDS_E_NOMEM, "kds_batch_time_kernels: no device memory to save the states");
+  }
+  hipError_t e = hipSuccess;
+  size_t off = 0;
+  for (kds_problem* p : b->probs)
+    if (p->sched == KDS_SCHED_LINE && e == hipSuccess) {
+      const size_t n = (size_t)p->n_unknowns() * p->elem;
+      e = hipMemcpyAsync(save + off, p->f, n, hipMemcpyDeviceToDevice, b->stream);
+      off += n;
+    }
+  float ms[2] = {0, 0};
+  for (int kind = 0; kind < 2 && e == hipSuccess; ++kind)
+    for (auto& gr : b->groups) {
+      if (gr.line != (kind == 0) || e != hipSuccess) continue;
+      auto launch = [&]() -> hipError_t {
+        const int nt = (int)(gr.start.size() - 1);
+        return gr.line ? launch_sweep_line_batch(gr.prec, gr.P, gr.dim, gr.d_tasks, gr.d_start, nt,
+                                                 gr.start.back(), gr.threads, gr.lds_elems, b->stream)
+                       : launch_relax_batch(gr.prec, gr.law, gr.dim, gr.m, gr.nv, gr.d_tasks,
+                                            gr.d_start, nt, gr.start.back(), b->stream);
+      };
+      e = launch();  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b->ev[1]);
+      float t = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, b->ev[0], b->ev[1]);
+      ms[kind] += t / reps;
+    }
+  off = 0;
+  hipError_t e2 = hipSuccess;
+  for (kds_problem* p : b->probs)
+    if (p->sched == KDS_SCHED_LINE && e2 == hipSuccess) {
+      const size_t n = (size_t)p->n_unknowns() * p->elem;
+      e2 = hipMemcpyAsync(p->f, save + off, n, hipMemcpyDeviceToDevice, b->stream);
+      off += n;
+    }
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
+  if (save) (void)hipFree(save);
+  if (e != hipSuccess) return bfail(b, KDS_E_DEVICE, std::string("kds_batch_time_kernels: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return bfail(b, KDS_E_DEVICE, std::string("kds_batch_time_kernels restore: ") + hipGetErrorString(e2));
+  kernel_ms[0] = ms[0];
+  kernel_ms[1] = ms[1];
+  return batch_join_out(b, 0);
+}
+
+kds_status kds_batch_synchronize(kds_batch* b) {
+  if (!b) return bfail(nullptr, KDS_E_INVALID, "batch is NULL");
+  KDS_BHIP(b, hipStreamSynchronize(b->stream));
+  return KDS_OK;
+}
+
+void kds_batch_destroy(kds_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_free_groups(b);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char* kds_batch_last_error(const kds_batch* b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

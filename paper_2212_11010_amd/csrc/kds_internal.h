@@ -100,6 +100,24 @@ struct LinePlan {
   int threads;             // block size
 };
 
+// One problem of a batched line-sweep launch.
+template <typename T>
+struct LineTask {
+  T* f;
+  Geom g;
+  SweepTab<T> tab;
+  LinePlan pl;
+};
+
+// One problem of a batched relaxation launch (pointwise kernel).
+template <int D, int M, int NV>
+struct RelaxTask {
+  const void* fin;
+  void* fout;
+  int64_t plane;
+  EqTab<D, M, NV> t;
+};
+
 // Front (level-ordered) sweep for velocities in any direction.
 enum FrontMode { kFrontFma = 0, kFrontMfma = 1, kFrontSplitF16 = 2, kFrontSplitBf16 = 3 };
 
@@ -136,6 +154,20 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
                               const void* Wop, const int* lvl_start, const int* lvl_cells,
                               const void* f_old, const void* f_prev, void* f_cur, hipStream_t s);
 size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp);
+
+// Batched launches (many problems per kernel): task records are packed on the
+// host, copied to device memory, and the kernels find their problem from the
+// prefix start[] over the problems' work items.
+size_t relax_task_bytes(int law, int dim, int m, int nv);
+bool pack_relax_task(int law, int dim, int m, int nv, const void* eq, const void* fin, void* fout,
+                     int64_t plane, void* out);
+hipError_t launch_relax_batch(int prec, int law, int dim, int m, int nv, const void* tasks,
+                              const int64_t* start, int ntask, int64_t nblocks, hipStream_t s);
+size_t line_task_bytes(int prec);
+void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl, void* out);
+hipError_t launch_sweep_line_batch(int prec, int P, int dim, const void* tasks, const int64_t* start,
+                                   int ntask, int64_t nblocks, int threads, size_t lds_elems,
+                                   hipStream_t s);
 
 // Equilibrium tables are built into a byte blob matching EqTab<D, M, NV> for
 // the (law, dim, m, nv) combination; returns false if the combination has no

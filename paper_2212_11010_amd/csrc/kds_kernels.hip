@@ -121,10 +121,8 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ W, T* _
 // Relaxation (eq:over_relaxation): W = sum_k f_k in FP64, M_k(W) in FP64,
 // f_k <- f_k + omega (M_k - f_k), one rounding to T.  fin may equal fout.
 template <typename T, int LAW, int D, int M, int NV>
-__global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t plane,
-                                               EqTab<D, M, NV> t) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= plane) return;
+__device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
+                                           const EqTab<D, M, NV>& t, int64_t i) {
   double fv[NV][M];
   double w[M];
 #pragma unroll
@@ -157,6 +155,28 @@ __global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t pl
 #pragma unroll
     for (int r = 0; r < M; ++r)
       fout[(int64_t)(k * M + r) * plane + i] = (T)(fv[k][r] + t.omega * (Mk[k][r] - fv[k][r]));
+}
+
+template <typename T, int LAW, int D, int M, int NV>
+__global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t plane,
+                                               EqTab<D, M, NV> t) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+  relax_node<T, LAW, D, M, NV>(fin, fout, plane, t, i);
+}
+
+// Relaxation of many problems of one (law, d, m, n_vel) in one launch; the
+// blocks of all problems are numbered consecutively (start[] prefix).
+template <typename T, int LAW, int D, int M, int NV>
+__global__ __launch_bounds__(256) void k_relax_batch(const RelaxTask<D, M, NV>* __restrict__ tasks,
+                                                     const int64_t* __restrict__ start, int ntask) {
+  const int64_t gb = blockIdx.x;
+  int pid = 0;
+  while (gb >= start[pid + 1]) ++pid;
+  const RelaxTask<D, M, NV>& t = tasks[pid];
+  const int64_t i = (gb - start[pid]) * blockDim.x + threadIdx.x;
+  if (i >= t.plane) return;
+  relax_node<T, LAW, D, M, NV>((const T*)t.fin, (T*)t.fout, t.plane, t.t, i);
 }
 
 template <typename T>
@@ -682,21 +702,23 @@ __device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
   }
 }
 
-template <typename T, int P, int DIM>
-__global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, SweepTab<T> tab,
-                                                    LinePlan pl) {
-  constexpr int NN = ColShape<P, DIM>::NN;
-  constexpr int QMAX = line_qmax((int)sizeof(T), NN);
-  extern __shared__ unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
-
-  // Workgroups are dealt round-robin to the XCDs; give each XCD a contiguous
-  // range of bundles so that neighbouring bundles, which share cache lines at
-  // their edges, meet in the same L2.
-  const int64_t nb = pl.block_start[g.nv * g.m];
+// Workgroups are dealt round-robin to the XCDs; give each XCD a contiguous
+// range of the nb work items so that neighbouring bundles, which share cache
+// lines at their edges, meet in the same L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t nb) {
   const int64_t xq = nb / kXcds, xr = nb % kXcds;
   const int64_t xcd = blockIdx.x % kXcds;
-  const int64_t bid = xcd * xq + min<int64_t>(xcd, xr) + blockIdx.x / kXcds;
+  return xcd * xq + min<int64_t>(xcd, xr) + blockIdx.x / kXcds;
+}
+
+// One bundle `bid` (numbered over all (velocity, component) pairs) of one
+// problem; the body of the single-problem and the batched line kernels.
+template <typename T, int P, int DIM>
+__device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
+                                            const SweepTab<T>& tab, const LinePlan& pl,
+                                            int64_t bid, T* tile) {
+  constexpr int NN = ColShape<P, DIM>::NN;
+  constexpr int QMAX = line_qmax((int)sizeof(T), NN);
   int kc = 0;
   while (bid >= pl.block_start[kc + 1]) ++kc;
   const int64_t bundle = bid - pl.block_start[kc];
@@ -818,6 +840,28 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
     const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
     copy_cols<T, NN, false>(f, tile, gbase, rowstride, ncols, Na, CS);
   }
+}
+
+template <typename T, int P, int DIM>
+__global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, SweepTab<T> tab,
+                                                    LinePlan pl) {
+  extern __shared__ unsigned char smem_raw[];
+  line_bundle<T, P, DIM>(f, g, tab, pl, xcd_order(pl.block_start[g.nv * g.m]),
+                         reinterpret_cast<T*>(smem_raw));
+}
+
+// Many problems of one (precision, degree, dimension) in one launch: the
+// bundles of all problems are numbered consecutively (start[] prefix).
+template <typename T, int P, int DIM>
+__global__ __launch_bounds__(256) void k_sweep_line_batch(const LineTask<T>* __restrict__ tasks,
+                                                          const int64_t* __restrict__ start,
+                                                          int ntask) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t gbid = xcd_order(start[ntask]);
+  int pid = 0;
+  while (gbid >= start[pid + 1]) ++pid;
+  const LineTask<T>& t = tasks[pid];
+  line_bundle<T, P, DIM>(t.f, t.g, t.tab, t.pl, gbid - start[pid], reinterpret_cast<T*>(smem_raw));
 }
 
 // ====================================================== front sweep
@@ -1107,6 +1151,22 @@ struct EqCombo {
                        (T*)f, plane, *(const Tab*)eq);
     return hipGetLastError();
   }
+  static size_t task_bytes() { return sizeof(RelaxTask<D, M, NV>); }
+  static void pack_task(const void* eq, const void* fin, void* fout, int64_t plane, void* out) {
+    RelaxTask<D, M, NV> t;
+    t.fin = fin;
+    t.fout = fout;
+    t.plane = plane;
+    std::memcpy(&t.t, eq, sizeof(Tab));
+    std::memcpy(out, &t, sizeof(t));
+  }
+  template <typename T>
+  static hipError_t relax_batch(const void* tasks, const int64_t* start, int ntask, int64_t nblocks,
+                                hipStream_t s) {
+    hipLaunchKernelGGL((k_relax_batch<T, LAW, D, M, NV>), dim3((unsigned)nblocks), dim3(256), 0, s,
+                       (const RelaxTask<D, M, NV>*)tasks, start, ntask);
+    return hipGetLastError();
+  }
   template <typename T>
   static hipError_t relax(const Geom& g, const void* eq, const void* fin, void* fout, hipStream_t s) {
     const int64_t plane = g.ncell * g.nn;
@@ -1124,13 +1184,19 @@ struct ComboEntry {
   hipError_t (*init32)(const Geom&, const void*, const double*, void*, hipStream_t);
   hipError_t (*relax64)(const Geom&, const void*, const void*, void*, hipStream_t);
   hipError_t (*relax32)(const Geom&, const void*, const void*, void*, hipStream_t);
+  size_t (*task_bytes)();
+  void (*pack_task)(const void*, const void*, void*, int64_t, void*);
+  hipError_t (*batch64)(const void*, const int64_t*, int, int64_t, hipStream_t);
+  hipError_t (*batch32)(const void*, const int64_t*, int, int64_t, hipStream_t);
 };
 
 #define KDS_COMBO(LAW, D, M, NV)                                                          \
   ComboEntry {                                                                            \
     LAW, D, M, NV, &EqCombo<LAW, D, M, NV>::build, &EqCombo<LAW, D, M, NV>::init<double>, \
         &EqCombo<LAW, D, M, NV>::init<float>, &EqCombo<LAW, D, M, NV>::relax<double>,     \
-        &EqCombo<LAW, D, M, NV>::relax<float>                                             \
+        &EqCombo<LAW, D, M, NV>::relax<float>, &EqCombo<LAW, D, M, NV>::task_bytes,       \
+        &EqCombo<LAW, D, M, NV>::pack_task, &EqCombo<LAW, D, M, NV>::relax_batch<double>, \
+        &EqCombo<LAW, D, M, NV>::relax_batch<float>                                       \
   }
 
 // (law, dim, m, n_vel) combinations with compiled pointwise kernels
@@ -1313,6 +1379,87 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
       KDS_FRONT(kFrontSplitF16)
       KDS_FRONT(kFrontSplitBf16)
 #undef KDS_FRONT
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+
+size_t relax_task_bytes(int law, int dim, int m, int nv) {
+  const ComboEntry* c = find_combo(law, dim, m, nv);
+  return c ? c->task_bytes() : 0;
+}
+
+bool pack_relax_task(int law, int dim, int m, int nv, const void* eq, const void* fin, void* fout,
+                     int64_t plane, void* out) {
+  const ComboEntry* c = find_combo(law, dim, m, nv);
+  if (!c) return false;
+  c->pack_task(eq, fin, fout, plane, out);
+  return true;
+}
+
+hipError_t launch_relax_batch(int prec, int law, int dim, int m, int nv, const void* tasks,
+                              const int64_t* start, int ntask, int64_t nblocks, hipStream_t s) {
+  const ComboEntry* c = find_combo(law, dim, m, nv);
+  if (!c) return hipErrorInvalidValue;
+  return prec == KDS_FP64 ? c->batch64(tasks, start, ntask, nblocks, s)
+                          : c->batch32(tasks, start, ntask, nblocks, s);
+}
+
+size_t line_task_bytes(int prec) {
+  return prec == KDS_FP64 ? sizeof(LineTask<double>) : sizeof(LineTask<float>);
+}
+
+void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl, void* out) {
+  if (prec == KDS_FP64) {
+    LineTask<double> t;
+    t.f = (double*)f;
+    t.g = g;
+    std::memcpy(&t.tab, tab, sizeof(t.tab));
+    t.pl = pl;
+    std::memcpy(out, &t, sizeof(t));
+  } else {
+    LineTask<float> t;
+    t.f = (float*)f;
+    t.g = g;
+    std::memcpy(&t.tab, tab, sizeof(t.tab));
+    t.pl = pl;
+    std::memcpy(out, &t, sizeof(t));
+  }
+}
+
+hipError_t launch_sweep_line_batch(int prec, int P, int dim, const void* tasks, const int64_t* start,
+                                   int ntask, int64_t nblocks, int threads, size_t lds_elems,
+                                   hipStream_t s) {
+  const size_t lds = lds_elems * (prec == KDS_FP64 ? 8 : 4);
+  const int key = P * 10 + dim;
+  if (prec == KDS_FP64) {
+    switch (key) {
+#define KDS_LB(PP, DD)                                                                            \
+  case PP * 10 + DD:                                                                              \
+    hipLaunchKernelGGL((k_sweep_line_batch<double, PP, DD>), dim3((unsigned)nblocks), dim3(threads), \
+                       lds, s, (const LineTask<double>*)tasks, start, ntask);                    \
+    break;
+      KDS_LB(1, 1) KDS_LB(2, 1) KDS_LB(3, 1) KDS_LB(4, 1)
+      KDS_LB(1, 2) KDS_LB(2, 2) KDS_LB(3, 2) KDS_LB(4, 2)
+      KDS_LB(1, 3) KDS_LB(2, 3) KDS_LB(3, 3) KDS_LB(4, 3)
+#undef KDS_LB
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    switch (key) {
+#define KDS_LB(PP, DD)                                                                            \
+  case PP * 10 + DD:                                                                              \
+    hipLaunchKernelGGL((k_sweep_line_batch<float, PP, DD>), dim3((unsigned)nblocks), dim3(threads), \
+                       lds, s, (const LineTask<float>*)tasks, start, ntask);                     \
+    break;
+      KDS_LB(1, 1) KDS_LB(2, 1) KDS_LB(3, 1) KDS_LB(4, 1)
+      KDS_LB(1, 2) KDS_LB(2, 2) KDS_LB(3, 2) KDS_LB(4, 2)
+      KDS_LB(1, 3) KDS_LB(2, 3) KDS_LB(3, 3) KDS_LB(4, 3)
+#undef KDS_LB
       default:
         return hipErrorInvalidValue;
     }

@@ -29,7 +29,11 @@ N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune",
             "kds_time_kernels", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
-            "kds_info", "kds_destroy", "kds_last_error"]
+            "kds_info", "kds_destroy", "kds_last_error",
+            "kds_batch_create", "kds_batch_step", "kds_batch_step_timed",
+            "kds_batch_time_kernels", "kds_batch_synchronize", "kds_batch_destroy",
+            "kds_batch_last_error"]
+_NO_STATUS = ("kds_destroy", "kds_last_error", "kds_batch_destroy", "kds_batch_last_error")
 
 
 class kds_config(C.Structure):
@@ -89,8 +93,17 @@ def lib():
         L.kds_destroy.restype = None
         L.kds_last_error.argtypes = [vp]
         L.kds_last_error.restype = C.c_char_p
+        L.kds_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+        L.kds_batch_step.argtypes = [vp, C.c_int32]
+        L.kds_batch_step_timed.argtypes = [vp, C.c_int32, dp]
+        L.kds_batch_time_kernels.argtypes = [vp, C.c_int32, dp]
+        L.kds_batch_synchronize.argtypes = [vp]
+        L.kds_batch_destroy.argtypes = [vp]
+        L.kds_batch_destroy.restype = None
+        L.kds_batch_last_error.argtypes = [vp]
+        L.kds_batch_last_error.restype = C.c_char_p
         for name in EXPORTED:
-            if name not in ("kds_destroy", "kds_last_error"):
+            if name not in _NO_STATUS:
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -258,6 +271,48 @@ def kds_last_error(h=None):
     return msg.decode() if msg else ""
 
 
+def _bcheck(status, handle=None):
+    if status != KDS_OK:
+        msg = lib().kds_batch_last_error(handle)
+        raise KdsError(status, msg.decode() if msg else "")
+
+
+def kds_batch_create(handles):
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    b = C.c_void_p()
+    _bcheck(lib().kds_batch_create(arr, len(handles), C.byref(b)))
+    return b
+
+
+def kds_batch_step(b, n_steps=1):
+    _bcheck(lib().kds_batch_step(b, int(n_steps)), b)
+
+
+def kds_batch_step_timed(b, n_steps=1):
+    ms = C.c_double(0.0)
+    _bcheck(lib().kds_batch_step_timed(b, int(n_steps), C.byref(ms)), b)
+    return ms.value
+
+
+def kds_batch_time_kernels(b, reps=10):
+    out = (C.c_double * N_KERNEL_KINDS)()
+    _bcheck(lib().kds_batch_time_kernels(b, int(reps), out), b)
+    return list(out)
+
+
+def kds_batch_synchronize(b):
+    _bcheck(lib().kds_batch_synchronize(b), b)
+
+
+def kds_batch_destroy(b):
+    lib().kds_batch_destroy(b)
+
+
+def kds_batch_last_error(b=None):
+    msg = lib().kds_batch_last_error(b)
+    return msg.decode() if msg else ""
+
+
 # ------------------------------------------------------------ convenience
 
 class Problem:
@@ -330,6 +385,43 @@ class Problem:
     def close(self):
         if self.h is not None:
             kds_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Owns one kds_batch over Problem objects (kept alive by the batch)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.h = kds_batch_create([p.h for p in self.problems])
+
+    def step(self, n=1):
+        kds_batch_step(self.h, n)
+
+    def step_timed(self, n=1):
+        return kds_batch_step_timed(self.h, n)
+
+    def time_kernels(self, reps=10):
+        return kds_batch_time_kernels(self.h, reps)
+
+    def synchronize(self):
+        kds_batch_synchronize(self.h)
+
+    def close(self):
+        if self.h is not None:
+            kds_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

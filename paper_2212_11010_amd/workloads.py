@@ -200,13 +200,16 @@ def euler_speeds(W, d, gamma=1.4):
 
 def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=None,
                   beta=None, omega=None, n_iter=3, theta=0.5, seed=None,
-                  precision="fp32", source_sigma=None):
+                  precision="fp32", source_sigma=None, speed_bound=False):
     """Return (spec, W0) for workload ``cfg`` (1..4, 6), optionally resized.
 
     6 is the paper's own setting: Maxwell's equations with the D3Q4 velocity
     set, a plane wave along x (Sec. 6.2) in the periodic unit cube.
 
     spec is a plain dict (problem description); W0 has shape [cell, node, m].
+    speed_bound (Euler): take lambda and dt from the bounds |u| <= 0.1,
+    c <= sqrt(gamma p / 0.8) that every state of the Euler recipe satisfies,
+    instead of the sampled maxima (the spec then does not depend on W0).
     """
     seed = SEED_BASE + cfg if seed is None else seed
     rng = np.random.default_rng(seed)
@@ -264,11 +267,15 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         params = [1.4]
         law = LAW_EULER
         lam = None
-        name = "euler3d_q%d" % p
+        name = "euler3d"
     else:
         raise ValueError("unknown workload %r" % cfg)
     if degree is not None:
         p = degree
+    if name in ("euler3d", "acoustics2d_q2") and degree is not None:
+        name = name.split("_q")[0] + "_q%d" % p
+    elif name == "euler3d":
+        name = "euler3d_q%d" % p
     N = list(N)
     S = list(S)
     spec = {
@@ -288,7 +295,10 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         W0 = w0_acoustics(X, rng)
     else:
         W0 = w0_euler(X, rng)
-        lam_max, lam_axis = euler_speeds(W0, d)
+        if speed_bound:
+            lam_max = lam_axis = 0.1 + math.sqrt(1.4 / 0.8)
+        else:
+            lam_max, lam_axis = euler_speeds(W0, d)
         lam = 1.1 * d * lam_axis
         vel = d3q6(lam)
     h = 1.0 / N[0]
@@ -306,3 +316,86 @@ def unknowns(spec: dict) -> int:
     d = spec["dim"]
     ncell = int(np.prod(spec["n_cells"][:d]))
     return ncell * (spec["degree"] + 1) ** d * spec["m"] * spec["n_vel"]
+
+
+# --------------------------------------------------------------------------
+# many uneven problems advanced together (batched launches)
+# --------------------------------------------------------------------------
+
+BATCH_ACOUSTICS_N = (64, 128, 256, 512)
+BATCH_EULER_N = (32, 48, 64, 96)
+
+
+def _batch_sub(N, nu, rng):
+    """A subdomain width S dividing N with nu <= S (the subdomain iteration
+    condition of Sec. 5.1 with the kinetic speed), drawn among the divisors
+    8 <= S <= N; the line schedule's cost hardly depends on S."""
+    need = max(8, math.ceil(nu))
+    cands = [s for s in range(need, N + 1) if N % s == 0]
+    return int(rng.choice(cands))
+
+
+def make_batch_workload(n_problems=48, max_unknowns=4.0e9, acoustics_n=BATCH_ACOUSTICS_N,
+                        euler_n=BATCH_EULER_N, euler_fraction=1.0 / 3.0, seed=None,
+                        steps=20):
+    """A seeded list of problem specs of uneven sizes: 2-D acoustics of degree
+    1..3 on N^2 grids and 3-D Euler of degree 1..2 on N^3 grids, N drawn from
+    the given lists, subdomain widths drawn with nu <= S, the total number of
+    kinetic unknowns kept below max_unknowns (a draw that does not fit is
+    redrawn; after 50 failed draws the smallest size is used).  The specs do
+    not depend on the initial states; batch_member_state(spec) samples W0."""
+    seed = SEED_BASE + 5 if seed is None else seed
+    rng = np.random.default_rng(seed)
+    out = []
+    total = 0
+    for i in range(n_problems):
+        euler = rng.random() < euler_fraction
+        for _ in range(50):
+            if euler:
+                p = int(rng.integers(1, 3))
+                N = int(rng.choice(euler_n))
+                u = N ** 3 * (p + 1) ** 3 * 5 * 6
+            else:
+                p = int(rng.integers(1, 4))
+                N = int(rng.choice(acoustics_n))
+                u = N ** 2 * (p + 1) ** 2 * 3 * 4
+            if total + u <= max_unknowns:
+                break
+        else:
+            p = 1
+            N = int(min(euler_n if euler else acoustics_n))
+        d = 3 if euler else 2
+        nu = (1.1 * d * 8.0 / (2 * d)) if euler else 5.0   # lambda dt / h of the recipe
+        S = _batch_sub(N, nu, rng)
+        args = {"cfg": 3 if euler else 2, "n_cells": [N] * d, "sub_cells": [S] * d,
+                "degree": p, "steps": steps, "seed": seed * 1000 + i}
+        spec = _member(args, with_state=False)
+        spec["name"] = "batch%02d_%s_%d" % (i, spec["name"], N)
+        spec["member_args"] = args
+        total += unknowns(spec)
+        out.append(spec)
+    return out
+
+
+def _member(args, with_state):
+    a = dict(args)
+    cfg = a.pop("cfg")
+    if not with_state:
+        # the spec of a member does not depend on its state: build it on a
+        # one-cell grid of the same kind and substitute the sizes
+        d = len(a["n_cells"])
+        small = dict(a, n_cells=[1] * d, sub_cells=[1] * d)
+        spec, _ = make_workload(cfg, speed_bound=(cfg == 3), **small)
+        N = a["n_cells"][0]
+        spec["n_cells"] = _pad3(a["n_cells"])
+        spec["sub_cells"] = _pad3(a["sub_cells"])
+        spec["dt"] = float(_dt(spec["beta"], 1.0 / N, d, spec["lam_max"]))
+        spec["kinetic_courant"] = float(spec["lam"] * spec["dt"] * N)
+        return spec
+    spec, W0 = make_workload(cfg, speed_bound=(cfg == 3), **a)
+    return (spec, W0) if with_state else spec
+
+
+def batch_member_state(spec):
+    """The seeded initial state W0 [cell, node, m] of a batch member."""
+    return _member(spec["member_args"], with_state=True)[1]

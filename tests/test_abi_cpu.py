@@ -158,3 +158,17 @@ def test_binding_rejects_wrong_arrays():
         kds._buf(np.zeros(4, dtype=np.float32), 16)
     with pytest.raises(ValueError):
         kds._buf(np.zeros(3), 32)
+
+
+def test_batch_calls_reject_null_and_empty():
+    L = kds.lib()
+    out = C.c_void_p()
+    assert L.kds_batch_create(None, 0, C.byref(out)) == kds.KDS_E_INVALID
+    assert "at least one" in kds.kds_batch_last_error(None)
+    assert L.kds_batch_create(None, 1, None) == kds.KDS_E_INVALID
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.kds_batch_create(arr, 2, C.byref(out)) == kds.KDS_E_INVALID
+    assert not out.value
+    assert L.kds_batch_step(None, 1) == kds.KDS_E_INVALID
+    assert L.kds_batch_synchronize(None) == kds.KDS_E_INVALID
+    L.kds_batch_destroy(None)

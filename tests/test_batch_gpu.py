@@ -1,0 +1,134 @@
+"""Batched launches (kds_batch_*): many uneven problems advanced together.
+
+A batch step runs the same arithmetic as kds_step on every member, only
+grouped into fewer launches, so every member's state after batched steps must
+equal, bit for bit, the state of an identical problem stepped on its own; the
+small members are also checked against the FP64 oracle to the usual
+tolerances (1e-12 FP64 storage, 1e-5 FP32 storage).
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def small_batch(seed=7, n=10):
+    from paper_2212_11010_amd import workloads as wl
+    return wl.make_batch_workload(n_problems=n, max_unknowns=4e6, acoustics_n=(16, 24, 32),
+                                  euler_n=(8, 12), seed=seed, steps=3)
+
+
+@functools.lru_cache(maxsize=None)
+def member_oracle(seed, i):
+    from oracle import oracle
+    from paper_2212_11010_amd import workloads as wl
+    spec = small_batch(seed)[i]
+    W0 = wl.batch_member_state(spec)
+    F, W = oracle.run(spec, W0, spec["steps"], threads=0)
+    return np.ascontiguousarray(F.transpose(0, 2, 3, 1)), W
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def make_members(specs, prec, scheds):
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    out = []
+    for spec, sched in zip(specs, scheds):
+        pb = kds.Problem(spec, precision=prec, schedule=sched)
+        pb.set_state(torch.from_numpy(wl.batch_member_state(spec)).cuda())
+        out.append(pb)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_single_problems_and_oracle(prec):
+    from paper_2212_11010_amd import kds
+    specs = small_batch()
+    # mostly automatic (line) members, two plain ones for the mixed path
+    scheds = ["auto"] * len(specs)
+    scheds[1] = "plain"
+    scheds[4] = "plain"
+    steps = specs[0]["steps"]
+    print("batch of", len(specs), prec, [s["name"] for s in specs], flush=True)
+    members = make_members(specs, prec, scheds)
+    singles = make_members(specs, prec, scheds)
+    with kds.Batch(members) as b:
+        b.step(steps)
+        b.synchronize()
+    for pb in singles:
+        pb.step(steps)
+    for i, (pm, ps) in enumerate(zip(members, singles)):
+        Fm, Fs = pm.get_kinetic(), ps.get_kinetic()
+        assert pm.info()["steps_done"] == steps
+        assert np.array_equal(Fm, Fs), (i, specs[i]["name"], relerr(Fm, Fs))
+        Fref, Wref = member_oracle(7, i)
+        ew, ef = relerr(pm.moments(), Wref), relerr(Fm, Fref)
+        print("  %s %s err W %.2e F %.2e" % (specs[i]["name"], scheds[i], ew, ef), flush=True)
+        assert ew <= TOL[prec] and ef <= TOL[prec], (specs[i]["name"], ew, ef)
+    for pb in members + singles:
+        pb.close()
+
+
+def test_batch_with_front_member_and_retune():
+    """A front-schedule member (D3Q4 Maxwell) in the batch, and a member
+    re-tuned after the batch was made (the batch rebuilds its task tables)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    specs = small_batch(seed=11, n=5)
+    mspec, mW0 = wl.make_workload(6, n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=3)
+    members = make_members(specs, "fp32", ["auto"] * len(specs))
+    singles = make_members(specs, "fp32", ["auto"] * len(specs))
+    fm = kds.Problem(mspec, precision="fp32", schedule="front")
+    fs = kds.Problem(mspec, precision="fp32", schedule="front")
+    for pb in (fm, fs):
+        pb.set_state(torch.from_numpy(mW0).cuda())
+    with kds.Batch(members + [fm]) as b:
+        b.step(1)
+        members[0].tune(reps=2)
+        singles[0].tune(reps=2)
+        b.step(2)
+        ms = b.step_timed(1)
+        assert ms > 0
+        kms = b.time_kernels(reps=2)
+        assert kms[0] > 0 and kms[1] > 0
+        b.synchronize()
+    for pb in singles + [fs]:
+        pb.step(4)
+    for i, (pm, ps) in enumerate(zip(members + [fm], singles + [fs])):
+        assert pm.info()["steps_done"] == 4
+        Fm, Fs = pm.get_kinetic(), ps.get_kinetic()
+        if i == 0:
+            # the two tuner runs may pick different launch plans (timing
+            # noise), which changes the FP32 rounding order of the line scan
+            assert relerr(Fm, Fs) <= 1e-5
+        else:
+            assert np.array_equal(Fm, Fs), (i, relerr(Fm, Fs))
+    for pb in members + singles + [fm, fs]:
+        pb.close()
+
+
+def test_batch_member_without_state_rejected():
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    specs = small_batch(n=2)
+    a = kds.Problem(specs[0], precision="fp32")
+    c = kds.Problem(specs[1], precision="fp32")
+    a.set_state(torch.from_numpy(wl.batch_member_state(specs[0])).cuda())
+    with kds.Batch([a, c]) as b:
+        with pytest.raises(kds.KdsError) as e:
+            b.step(1)
+        assert e.value.status == kds.KDS_E_STATE
+    a.close()
+    c.close()
