@@ -202,13 +202,14 @@ const char* kds_last_error(const kds_problem* p);
  * Many independent problems (any sizes, laws, degrees, schedules) advanced
  * together by one time step each per kds_batch_step.  The members keep their
  * own states; a batch step gives exactly the results of kds_step on every
- * member (the same kernels' arithmetic), but the line sweeps of all members
- * sharing (precision, degree, dimension, workgroup size) run as ONE launch
- * whose workgroups are spread over the members, and likewise the relaxations
- * of members sharing (precision, law, d, m, n_vel); plain- and front-schedule
- * members add their own kernel sequences.  A whole batched step is one
- * captured HIP graph on the batch's own stream, ordered after the work already
- * queued on every member's stream; the members' streams are ordered after it.
+ * member (the same kernels' arithmetic), but the line-schedule members that
+ * share (precision, degree, dimension, workgroup size, law, m, n_vel) are
+ * swept by ONE launch whose workgroups are spread over the members and
+ * relaxed by ONE more launch; plain- and front-schedule members add their own
+ * kernel sequences.  A whole batched step is one captured HIP graph whose
+ * groups are parallel branches (they touch disjoint memory), launched on the
+ * batch's own stream, ordered after the work already queued on every member's
+ * stream; the members' streams are ordered after it.
  * Members must be on one device and distinct; the batch keeps pointers to
  * them (destroy the batch before its members).  A member re-tuned by kds_tune
  * is picked up at the next batch step.  Not thread safe. */

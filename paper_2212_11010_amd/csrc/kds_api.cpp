@@ -918,29 +918,34 @@ const char* kds_last_error(const kds_problem* p) {
 }  // extern "C"
 
 // ================================================================ batches
-// Many problems advanced together: the line sweeps of all line-schedule
-// members that share (precision, degree, dimension, workgroup size) run as one
-// launch, their relaxations as one launch per (precision, law, d, m, n_vel);
-// plain- and front-schedule members add their own kernel sequences.  The whole
-// step is one captured HIP graph on the batch's stream.
+// Many problems advanced together.  The line-schedule members that share
+// (precision, degree, dimension, workgroup size, law, m, n_vel) form a branch:
+// ONE launch sweeps all of them (workgroups spread over the members), ONE
+// launch relaxes them.  Branches touch disjoint memory and run as parallel
+// branches of one captured HIP graph per step; the plain- and front-schedule
+// members add their own kernel sequences on one more branch.
 
 struct kds_batch {
-  struct Group {
-    bool line = true;
+  struct Branch {
     int prec = 0, P = 0, dim = 0, threads = 0, law = 0, m = 0, nv = 0;
     size_t lds_elems = 0;
-    std::vector<unsigned char> tasks;  // packed task records (host)
-    std::vector<int64_t> start{0};     // block prefix over the members
-    void* d_tasks = nullptr;
-    int64_t* d_start = nullptr;
+    std::vector<unsigned char> line_tasks, relax_tasks;  // packed records (host)
+    std::vector<int64_t> line_start{0}, relax_start{0};  // block prefixes
+    void* d_line = nullptr;
+    void* d_relax = nullptr;
+    int64_t* d_line_start = nullptr;
+    int64_t* d_relax_start = nullptr;
+    int ntask() const { return (int)line_start.size() - 1; }
   };
   std::vector<kds_problem*> probs;
   std::vector<int> versions;
-  std::vector<Group> groups;
-  std::vector<kds_problem*> others;  // members not in a line group
+  std::vector<Branch> branches;
+  std::vector<kds_problem*> others;  // members on the extra branch
   int device = 0;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev_join = nullptr, ev[2] = {nullptr, nullptr};
+  hipStream_t stream = nullptr;      // the batch's stream (branch 0 when captured)
+  std::vector<hipStream_t> sides;    // capture streams of the other branches
+  std::vector<hipEvent_t> joins;     // one per side stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::string err;
@@ -960,114 +965,132 @@ kds_status bfail(kds_batch* b, kds_status st, const std::string& msg) {
       return bfail((b), KDS_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-void batch_free_groups(kds_batch* b) {
+void batch_free_branches(kds_batch* b) {
   if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->graph_exec = nullptr;
   b->graph = nullptr;
-  for (auto& g : b->groups) {
-    if (g.d_tasks) (void)hipFree(g.d_tasks);
-    if (g.d_start) (void)hipFree(g.d_start);
+  for (auto& br : b->branches) {
+    void* bufs[] = {br.d_line, br.d_relax, br.d_line_start, br.d_relax_start};
+    for (void* x : bufs)
+      if (x) (void)hipFree(x);
   }
-  b->groups.clear();
+  b->branches.clear();
   b->others.clear();
 }
 
-// Group the members and upload the task tables (blocking copies).
+hipError_t upload(void** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+// Group the members into branches and upload the task tables (blocking copies).
 kds_status batch_build(kds_batch* b) {
-  batch_free_groups(b);
+  batch_free_branches(b);
   for (kds_problem* p : b->probs) {
     if (p->sched != KDS_SCHED_LINE) {
       b->others.push_back(p);
       continue;
     }
     const Geom& g = p->geom;
-    kds_batch::Group* lg = nullptr;
-    kds_batch::Group* rg = nullptr;
-    for (auto& gr : b->groups) {
-      if (gr.line && gr.prec == p->prec && gr.P == p->P && gr.dim == p->dim &&
-          gr.threads == p->plan.threads)
-        lg = &gr;
-      if (!gr.line && gr.prec == p->prec && gr.law == p->law && gr.dim == p->dim &&
-          gr.m == p->m && gr.nv == p->nv)
-        rg = &gr;
+    kds_batch::Branch* br = nullptr;
+    for (auto& x : b->branches)
+      if (x.prec == p->prec && x.P == p->P && x.dim == p->dim && x.threads == p->plan.threads &&
+          x.law == p->law && x.m == p->m && x.nv == p->nv)
+        br = &x;
+    if (!br) {
+      b->branches.emplace_back();
+      br = &b->branches.back();
+      br->prec = p->prec;
+      br->P = p->P;
+      br->dim = p->dim;
+      br->threads = p->plan.threads;
+      br->law = p->law;
+      br->m = p->m;
+      br->nv = p->nv;
     }
-    if (!lg) {
-      b->groups.emplace_back();
-      lg = &b->groups.back();
-      lg->line = true;
-      lg->prec = p->prec;
-      lg->P = p->P;
-      lg->dim = p->dim;
-      lg->threads = p->plan.threads;
-    }
-    {
-      const size_t tb = line_task_bytes(p->prec);
-      const size_t off = lg->tasks.size();
-      lg->tasks.resize(off + tb);
-      pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, lg->tasks.data() + off);
-      lg->start.push_back(lg->start.back() + p->plan.block_start[g.nv * g.m]);
-      lg->lds_elems = std::max(lg->lds_elems, (size_t)p->plan.lds_elems);
-    }
-    // (the vector may have grown: find the relax group again)
-    rg = nullptr;
-    for (auto& gr : b->groups)
-      if (!gr.line && gr.prec == p->prec && gr.law == p->law && gr.dim == p->dim &&
-          gr.m == p->m && gr.nv == p->nv)
-        rg = &gr;
-    if (!rg) {
-      b->groups.emplace_back();
-      rg = &b->groups.back();
-      rg->line = false;
-      rg->prec = p->prec;
-      rg->law = p->law;
-      rg->dim = p->dim;
-      rg->m = p->m;
-      rg->nv = p->nv;
-    }
-    {
-      const size_t tb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
-      if (tb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
-      const size_t off = rg->tasks.size();
-      rg->tasks.resize(off + tb);
-      pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->f, p->f, p->plane(),
-                      rg->tasks.data() + off);
-      rg->start.push_back(rg->start.back() + (p->plane() + 255) / 256);
+    const size_t lb = line_task_bytes(p->prec);
+    const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
+    if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
+    size_t off = br->line_tasks.size();
+    br->line_tasks.resize(off + lb);
+    pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, br->line_tasks.data() + off);
+    br->line_start.push_back(br->line_start.back() + p->plan.block_start[g.nv * g.m]);
+    br->lds_elems = std::max(br->lds_elems, (size_t)p->plan.lds_elems);
+    off = br->relax_tasks.size();
+    br->relax_tasks.resize(off + rb);
+    pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->f, p->f, p->plane(),
+                    br->relax_tasks.data() + off);
+    br->relax_start.push_back(br->relax_start.back() + (p->plane() + 255) / 256);
+  }
+  for (auto& br : b->branches) {
+    if (br.line_start.back() > 0x7fffffffLL || br.relax_start.back() > 0x7fffffffLL)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched launch exceeds the grid limit");
+    if (br.lds_elems * (br.prec == KDS_FP64 ? 8 : 4) > 64 * 1024)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched line sweep needs more than 64 KiB of LDS");
+    hipError_t e = upload(&br.d_line, br.line_tasks.data(), br.line_tasks.size());
+    if (e == hipSuccess) e = upload(&br.d_relax, br.relax_tasks.data(), br.relax_tasks.size());
+    if (e == hipSuccess)
+      e = upload((void**)&br.d_line_start, br.line_start.data(), br.line_start.size() * 8);
+    if (e == hipSuccess)
+      e = upload((void**)&br.d_relax_start, br.relax_start.data(), br.relax_start.size() * 8);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, e == hipErrorOutOfMemory ? KDS_E_NOMEM : KDS_E_DEVICE,
+                   std::string("batch task tables: ") + hipGetErrorString(e));
     }
   }
-  for (auto& gr : b->groups) {
-    if (gr.start.back() > 0x7fffffffLL)
-      return bfail(b, KDS_E_UNSUPPORTED, "batched launch exceeds the grid limit");
-    if (gr.line && gr.lds_elems * (gr.prec == KDS_FP64 ? 8 : 4) > 64 * 1024)
-      return bfail(b, KDS_E_UNSUPPORTED, "batched line sweep needs more than 64 KiB of LDS");
-    if (hipMalloc(&gr.d_tasks, gr.tasks.size()) != hipSuccess ||
-        hipMalloc((void**)&gr.d_start, gr.start.size() * sizeof(int64_t)) != hipSuccess) {
-      (void)hipGetLastError();
-      return bfail(b, KDS_E_NOMEM, "batch task tables");
-    }
-    KDS_BHIP(b, hipMemcpy(gr.d_tasks, gr.tasks.data(), gr.tasks.size(), hipMemcpyHostToDevice));
-    KDS_BHIP(b, hipMemcpy(gr.d_start, gr.start.data(), gr.start.size() * sizeof(int64_t),
-                          hipMemcpyHostToDevice));
+  // capture streams for the branches beyond the first
+  const size_t nside = b->branches.size() - (b->branches.empty() ? 0 : 1) + (b->others.empty() ? 0 : 1);
+  while (b->sides.size() < nside) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    KDS_BHIP(b, hipStreamCreate(&st));
+    b->sides.push_back(st);
+    KDS_BHIP(b, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->joins.push_back(ev);
   }
   for (size_t i = 0; i < b->probs.size(); ++i) b->versions[i] = b->probs[i]->plan_version;
   return KDS_OK;
 }
 
-// One batched step.  With events: ev[0] before, ev[1] after the line sweeps.
-kds_status batch_enqueue(kds_batch* b, bool events) {
-  for (auto& gr : b->groups)
-    if (gr.line)
-      KDS_BHIP(b, launch_sweep_line_batch(gr.prec, gr.P, gr.dim, gr.d_tasks, gr.d_start,
-                                          (int)(gr.start.size() - 1), gr.start.back(), gr.threads,
-                                          gr.lds_elems, b->stream));
-  if (events) KDS_BHIP(b, hipEventRecord(b->ev[1], b->stream));
-  for (auto& gr : b->groups)
-    if (!gr.line)
-      KDS_BHIP(b, launch_relax_batch(gr.prec, gr.law, gr.dim, gr.m, gr.nv, gr.d_tasks, gr.d_start,
-                                     (int)(gr.start.size() - 1), gr.start.back(), b->stream));
-  for (kds_problem* p : b->others) {
-    kds_status st = enqueue_step(p, false, b->stream);
-    if (st != KDS_OK) return bfail(b, st, "batch member: " + p->err);
+hipError_t launch_branch_line(const kds_batch::Branch& br, hipStream_t s) {
+  return launch_sweep_line_batch(br.prec, br.P, br.dim, br.d_line, br.d_line_start, br.ntask(),
+                                 br.line_start.back(), br.threads, br.lds_elems, s);
+}
+
+hipError_t launch_branch_relax(const kds_batch::Branch& br, hipStream_t s) {
+  return launch_relax_batch(br.prec, br.law, br.dim, br.m, br.nv, br.d_relax, br.d_relax_start,
+                            br.ntask(), br.relax_start.back(), s);
+}
+
+// One batched step, under stream capture: fork every side stream from the
+// batch stream, enqueue each branch on its stream, join them back.
+kds_status batch_enqueue(kds_batch* b) {
+  const size_t nb = b->branches.size();
+  std::vector<hipStream_t> bs;
+  bs.push_back(b->stream);
+  for (hipStream_t s : b->sides) bs.push_back(s);
+  const size_t nstreams = (nb ? nb : 1) + (b->others.empty() ? 0 : 1);
+  if (nstreams > 1) {
+    KDS_BHIP(b, hipEventRecord(b->ev_fork, b->stream));
+    for (size_t i = 1; i < nstreams; ++i) KDS_BHIP(b, hipStreamWaitEvent(bs[i], b->ev_fork, 0));
+  }
+  for (size_t i = 0; i < nb; ++i) {
+    KDS_BHIP(b, launch_branch_line(b->branches[i], bs[i]));
+    KDS_BHIP(b, launch_branch_relax(b->branches[i], bs[i]));
+  }
+  if (!b->others.empty()) {
+    hipStream_t s = bs[nstreams - 1];
+    for (kds_problem* p : b->others) {
+      kds_status st = enqueue_step(p, false, s);
+      if (st != KDS_OK) return bfail(b, st, "batch member: " + p->err);
+    }
+  }
+  for (size_t i = 1; i < nstreams; ++i) {
+    KDS_BHIP(b, hipEventRecord(b->joins[i - 1], bs[i]));
+    KDS_BHIP(b, hipStreamWaitEvent(b->stream, b->joins[i - 1], 0));
   }
   return KDS_OK;
 }
@@ -1075,7 +1098,7 @@ kds_status batch_enqueue(kds_batch* b, bool events) {
 kds_status batch_prepare(kds_batch* b) {
   for (kds_problem* p : b->probs)
     if (!p->state_set) return bfail(b, KDS_E_STATE, "a batch member has no state");
-  bool stale = b->groups.empty() && b->others.empty();
+  bool stale = b->branches.empty() && b->others.empty();
   for (size_t i = 0; i < b->probs.size(); ++i)
     if (b->versions[i] != b->probs[i]->plan_version) stale = true;
   if (stale) {
@@ -1084,7 +1107,7 @@ kds_status batch_prepare(kds_batch* b) {
   }
   if (!b->graph_exec) {
     KDS_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    kds_status st = batch_enqueue(b, false);
+    kds_status st = batch_enqueue(b);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &graph);
     if (st != KDS_OK) {
@@ -1142,6 +1165,7 @@ kds_status kds_batch_create(kds_problem* const* problems, int32_t n, kds_batch**
   hipError_t e = hipGetDevice(&cur);
   if (e == hipSuccess) e = hipSetDevice(b->device);
   if (e == hipSuccess) e = hipStreamCreate(&b->stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&b->ev[1]);
@@ -1211,14 +1235,10 @@ kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms)
     }
   float ms[2] = {0, 0};
   for (int kind = 0; kind < 2 && e == hipSuccess; ++kind)
-    for (auto& gr : b->groups) {
-      if (gr.line != (kind == 0) || e != hipSuccess) continue;
+    for (auto& br : b->branches) {
+      if (e != hipSuccess) break;
       auto launch = [&]() -> hipError_t {
-        const int nt = (int)(gr.start.size() - 1);
-        return gr.line ? launch_sweep_line_batch(gr.prec, gr.P, gr.dim, gr.d_tasks, gr.d_start, nt,
-                                                 gr.start.back(), gr.threads, gr.lds_elems, b->stream)
-                       : launch_relax_batch(gr.prec, gr.law, gr.dim, gr.m, gr.nv, gr.d_tasks,
-                                            gr.d_start, nt, gr.start.back(), b->stream);
+        return kind == 0 ? launch_branch_line(br, b->stream) : launch_branch_relax(br, b->stream);
       };
       e = launch();  // warm-up
       if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
@@ -1255,10 +1275,13 @@ kds_status kds_batch_synchronize(kds_batch* b) {
 void kds_batch_destroy(kds_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  batch_free_groups(b);
+  batch_free_branches(b);
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto e : b->joins) (void)hipEventDestroy(e);
+  for (auto st : b->sides) (void)hipStreamDestroy(st);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
