@@ -52,9 +52,12 @@ struct kds_problem {
   double* stage = nullptr;  // FP64 staging for W / F transfers
   size_t stage_bytes = 0;
   int* flag = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;           // one captured step
   hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph_n = nullptr;         // kGraphSteps captured steps
+  hipGraphExec_t graph_n_exec = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  int lds_cap = 64 * 1024;              // LDS bytes a workgroup may use on the device
   bool state_set = false;
   int steps_done = 0;
   int plan_version = 0;  // bumped when the launch plan changes (batches rebuild)
@@ -165,11 +168,9 @@ bool line_choice_ok(const kds_problem* p, int ax, int Q, int bw) {
   const int Na = p->N[ax], S = p->S[ax];
   const int qmax = line_qmax((int)p->elem, p->nn);
   if (Q < 1 || Q > qmax || S % Q || Na / Q > 64 || bw < 1) return false;
-  if ((int64_t)bw * Na * p->nn * (int)p->elem > 64 * 1024) return false;
+  if ((int64_t)bw * Na * p->nn * (int)p->elem > p->lds_cap) return false;
   if (ax == 0 && bw > p->ncell / Na) return false;
   if (ax != 0 && (bw > p->N[0] || bw * p->nn > 256)) return false;
-  const int lw = 64 / pow2_at_least(Na / Q);
-  if ((bw + lw - 1) / lw > 4) return false;
   return true;
 }
 
@@ -211,7 +212,7 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
     pl.lpl2[k] = l2;
     pl.bw[k] = bw;
     max_lds = std::max(max_lds, bw * Na * p->nn);
-    threads = std::max(threads, 64 * ((bw + lw - 1) / lw));
+    threads = std::max(threads, std::min(256, 64 * ((bw + lw - 1) / lw)));
     if (ax != 0) threads = std::max(threads, ((bw * p->nn + 63) / 64) * 64);
     int64_t nb;
     if (ax == 0) nb = (p->ncell / Na + bw - 1) / bw;
@@ -321,11 +322,23 @@ void fill_sweep_tab(kds_problem* p, const Basis1D& basis) {
   std::memcpy(p->sweep_blob.data(), &t, sizeof(t));
 }
 
-void free_device(kds_problem* p) {
+// Steps per captured multi-step graph: long kds_step calls launch it, so the
+// per-launch cost of a graph is paid once per kGraphSteps steps.
+constexpr int kGraphSteps = 8;
+
+void drop_graphs(kds_problem* p) {
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->graph_n_exec) (void)hipGraphExecDestroy(p->graph_n_exec);
+  if (p->graph_n) (void)hipGraphDestroy(p->graph_n);
   p->graph_exec = nullptr;
   p->graph = nullptr;
+  p->graph_n_exec = nullptr;
+  p->graph_n = nullptr;
+}
+
+void free_device(kds_problem* p) {
+  drop_graphs(p);
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
@@ -374,10 +387,12 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
   return KDS_OK;
 }
 
-kds_status ensure_graph(kds_problem* p) {
-  if (p->graph_exec) return KDS_OK;
+// Capture `steps` consecutive steps into (graph, exec) unless already there.
+kds_status ensure_graph(kds_problem* p, int steps, hipGraph_t* graph_out, hipGraphExec_t* exec) {
+  if (*exec) return KDS_OK;
   KDS_HIP(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  kds_status st = enqueue_step(p, false, p->stream);
+  kds_status st = KDS_OK;
+  for (int i = 0; i < steps && st == KDS_OK; ++i) st = enqueue_step(p, false, p->stream);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(p->stream, &graph);
   if (st != KDS_OK) {
@@ -385,8 +400,8 @@ kds_status ensure_graph(kds_problem* p) {
     return st;
   }
   if (e != hipSuccess) return hip_fail(p, e, "hipStreamEndCapture");
-  p->graph = graph;
-  KDS_HIP(p, hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  *graph_out = graph;
+  KDS_HIP(p, hipGraphInstantiate(exec, graph, nullptr, nullptr, 0));
   return KDS_OK;
 }
 
@@ -526,6 +541,16 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   for (int ax = 0; ax < p->dim; ++ax) p->min_sub_width = std::min(p->min_sub_width, p->S[ax] * p->h[ax]);
 
   std::string why;
+  {
+    // LDS a workgroup may allocate (160 KiB on gfx950): bounds the line tiles
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      p->lds_cap = std::min(v, 160 * 1024);
+    else
+      (void)hipGetLastError();
+  }
   const bool line_ok = !want_front && plan_lines(p, why);
   if (cfg->schedule == KDS_SCHED_LINE && !line_ok) {
     delete p;
@@ -627,10 +652,19 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
       return fail(nullptr, KDS_E_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
     }
   }
-  if (p->sched == KDS_SCHED_LINE && (size_t)p->plan.lds_elems * p->elem > 64 * 1024) {
-    free_device(p);
-    delete p;
-    return fail(nullptr, KDS_E_UNSUPPORTED, "line schedule LDS tile too large");
+  if (p->sched == KDS_SCHED_LINE) {
+    if ((size_t)p->plan.lds_elems * p->elem > (size_t)p->lds_cap) {
+      free_device(p);
+      delete p;
+      return fail(nullptr, KDS_E_UNSUPPORTED, "line schedule LDS tile too large");
+    }
+    // plans (also the autotuner's) may use up to lds_cap bytes of dynamic LDS
+    e = line_kernels_allow_lds((size_t)p->lds_cap);
+    if (e != hipSuccess) {
+      free_device(p);
+      delete p;
+      return fail(nullptr, KDS_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
   }
   *out = p;
   return KDS_OK;
@@ -662,9 +696,18 @@ kds_status kds_step(kds_problem* p, int32_t n_steps) {
   if (n_steps < 0) return fail(p, KDS_E_INVALID, "n_steps must be >= 0");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step before kds_set_state / kds_set_kinetic");
   if (n_steps == 0) return KDS_OK;
-  kds_status st = ensure_graph(p);
-  if (st != KDS_OK) return st;
-  for (int i = 0; i < n_steps; ++i) KDS_HIP(p, hipGraphLaunch(p->graph_exec, p->stream));
+  int left = n_steps;
+  if (left >= kGraphSteps) {
+    kds_status st = ensure_graph(p, kGraphSteps, &p->graph_n, &p->graph_n_exec);
+    if (st != KDS_OK) return st;
+    for (; left >= kGraphSteps; left -= kGraphSteps)
+      KDS_HIP(p, hipGraphLaunch(p->graph_n_exec, p->stream));
+  }
+  if (left > 0) {
+    kds_status st = ensure_graph(p, 1, &p->graph, &p->graph_exec);
+    if (st != KDS_OK) return st;
+    for (; left > 0; --left) KDS_HIP(p, hipGraphLaunch(p->graph_exec, p->stream));
+  }
   p->steps_done += n_steps;
   return KDS_OK;
 }
@@ -754,10 +797,7 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   (void)hipFree(save);
   if (!ok) return st;
   if (e != hipSuccess) return hip_fail(p, e, "kds_tune restore");
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  p->graph_exec = nullptr;
-  p->graph = nullptr;
+  drop_graphs(p);
   p->tuned = true;
   ++p->plan_version;
   if (sweep_ms) *sweep_ms = best;
@@ -1027,8 +1067,10 @@ kds_status batch_build(kds_batch* b) {
   for (auto& br : b->branches) {
     if (br.line_start.back() > 0x7fffffffLL || br.relax_start.back() > 0x7fffffffLL)
       return bfail(b, KDS_E_UNSUPPORTED, "batched launch exceeds the grid limit");
-    if (br.lds_elems * (br.prec == KDS_FP64 ? 8 : 4) > 64 * 1024)
-      return bfail(b, KDS_E_UNSUPPORTED, "batched line sweep needs more than 64 KiB of LDS");
+    int cap = 64 * 1024;
+    for (kds_problem* p : b->probs) cap = std::max(cap, p->lds_cap);
+    if (br.lds_elems * (br.prec == KDS_FP64 ? 8 : 4) > (size_t)cap)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched line sweep needs more LDS than the device has");
     hipError_t e = upload(&br.d_line, br.line_tasks.data(), br.line_tasks.size());
     if (e == hipSuccess) e = upload(&br.d_relax, br.relax_tasks.data(), br.relax_tasks.size());
     if (e == hipSuccess)

@@ -163,6 +163,7 @@ bool pack_relax_task(int law, int dim, int m, int nv, const void* eq, const void
                      int64_t plane, void* out);
 hipError_t launch_relax_batch(int prec, int law, int dim, int m, int nv, const void* tasks,
                               const int64_t* start, int ntask, int64_t nblocks, hipStream_t s);
+hipError_t line_kernels_allow_lds(size_t bytes);
 size_t line_task_bytes(int prec);
 void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl, void* out);
 hipError_t launch_sweep_line_batch(int prec, int P, int dim, const void* tasks, const int64_t* start,

@@ -1467,4 +1467,28 @@ hipError_t launch_sweep_line_batch(int prec, int P, int dim, const void* tasks, 
   return hipGetLastError();
 }
 
+
+// Allow the line kernels (single and batched) dynamic LDS up to `bytes`
+// (workgroups above 64 KiB need the attribute).  Once per size and process.
+hipError_t line_kernels_allow_lds(size_t bytes) {
+  static size_t done = 0;
+  if (bytes <= 64 * 1024 || bytes <= done) return hipSuccess;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* k) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  };
+#define KDS_ALLOW(PP, DD)                                                \
+  set(reinterpret_cast<const void*>(&k_sweep_line<float, PP, DD>));        \
+  set(reinterpret_cast<const void*>(&k_sweep_line<double, PP, DD>));       \
+  set(reinterpret_cast<const void*>(&k_sweep_line_batch<float, PP, DD>));  \
+  set(reinterpret_cast<const void*>(&k_sweep_line_batch<double, PP, DD>));
+  KDS_ALLOW(1, 1) KDS_ALLOW(2, 1) KDS_ALLOW(3, 1) KDS_ALLOW(4, 1)
+  KDS_ALLOW(1, 2) KDS_ALLOW(2, 2) KDS_ALLOW(3, 2) KDS_ALLOW(4, 2)
+  KDS_ALLOW(1, 3) KDS_ALLOW(2, 3) KDS_ALLOW(3, 3) KDS_ALLOW(4, 3)
+#undef KDS_ALLOW
+  if (e == hipSuccess) done = bytes;
+  return e;
+}
+
 }  // namespace kds
