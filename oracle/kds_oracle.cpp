@@ -21,6 +21,10 @@
 //   * the implicit system is solved by visiting the cells of each subdomain in a
 //     topological order of the velocity-oriented cell graph (Sec. 3.2,
 //     "downwind algorithm"), one dense per-cell LU solve per cell;
+//   * on an axis that is not periodic, the upwind value at an inflow face of
+//     the box is prescribed: the kinetic boundary data f_k = M_k(W_b) of a
+//     given boundary state W_b (Dirichlet conditions, Sec. 6.2), at the old
+//     and the new time of the theta-scheme;
 //   * subdomains are coupled by the iterative algorithm of Sec. 5.1 (eq:ibvp):
 //     iterate p takes its upwind interface data from the neighbours' iterate
 //     p-1; iterate 0 is the state at the previous time (eq:ibvp2); every
@@ -34,6 +38,12 @@
 // Layouts (all FP64):
 //   W   [cell][node][c]           cells x-fastest, nodes x-fastest
 //   F   [k][c][cell][node]        oracle-internal kinetic layout
+//   W_b [boundary node][c]        boundary nodes: for each non-periodic axis a
+//                                 (x, y, z order), the face at the low end,
+//                                 then at the high end; on a face, cells over
+//                                 the other axes (lower axis fastest), then
+//                                 the face nodes of the cell over the other
+//                                 axes' node indices (lower axis fastest)
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -66,6 +76,10 @@ typedef struct {
   double theta;
   int32_t n_iter;        // K >= 1; 0 = iterate to convergence
   const double* source_sigma;  // m damping rates sigma_c >= 0 (may be +inf), or NULL
+  const int32_t* periodic;     // 3 flags, or NULL (all periodic); 0 = Dirichlet ends
+  const double* bnd_W_old;     // boundary state [boundary node][c] at the step start, or NULL
+  const double* bnd_W_new;     // ... at the step end (orc_step: first step; later steps
+                               // hold it constant)
 } orc_config;
 
 }  // extern "C"
@@ -358,6 +372,7 @@ int lu_solve(int n, std::vector<double>& A, std::vector<double>& b) {
 
 struct Grid {
   int d, N[3], S[3];
+  bool per[3];
   long ncell;
   long cell_of(const int* cc) const {
     long id = 0, mul = 1;
@@ -374,17 +389,63 @@ Grid make_grid(const orc_config* c) {
   g.d = c->dim;
   for (int a = 0; a < 3; ++a) { g.N[a] = a < c->dim ? c->n_cells[a] : 1; g.S[a] = a < c->dim ? c->sub_cells[a] : 1; }
   g.ncell = ncell_of(c);
+  for (int a = 0; a < 3; ++a) g.per[a] = !(c->periodic && a < c->dim && c->periodic[a] == 0);
   return g;
+}
+
+// Boundary nodes of the face (axis ax): cells over the other axes times the
+// face nodes of a cell.
+long face_nodes(const orc_config* c, int ax) {
+  long n = 1;
+  for (int a = 0; a < c->dim; ++a)
+    if (a != ax) n *= (long)c->n_cells[a] * P_of(c);
+  return n;
+}
+
+// Offset of face (ax, side) in the boundary-node numbering, -1 if ax is periodic.
+long face_offset(const orc_config* c, int ax, int side) {
+  Grid g = make_grid(c);
+  if (g.per[ax]) return -1;
+  long off = 0;
+  for (int a = 0; a < ax; ++a)
+    if (!g.per[a]) off += 2 * face_nodes(c, a);
+  return off + side * face_nodes(c, ax);
+}
+
+long n_boundary_nodes(const orc_config* c) {
+  Grid g = make_grid(c);
+  long n = 0;
+  for (int a = 0; a < c->dim; ++a)
+    if (!g.per[a]) n += 2 * face_nodes(c, a);
+  return n;
+}
+
+// Index on face ax of the boundary node matching node i of cell cc.
+long face_index(const orc_config* c, const int* cc, int ax, int i) {
+  int P = P_of(c);
+  int ii[3];
+  node_index(i, c->dim, P, ii);
+  long cell = 0, cmul = 1, node = 0, nmul = 1;
+  for (int a = 0; a < c->dim; ++a) {
+    if (a == ax) continue;
+    cell += cc[a] * cmul;
+    cmul *= c->n_cells[a];
+    node += ii[a] * nmul;
+    nmul *= P;
+  }
+  return cell * nmul + node;
 }
 
 // Neighbour across face (ax, side): returns its cell id and whether the face is
 // interior to one subdomain (no periodic wrap, same subdomain index on ax).
+// On a non-periodic axis a face of the box has no neighbour: returns -1.
 long neighbour(const Grid& g, const int* cc, int ax, int side, bool* internal) {
   int nc[3] = {cc[0], cc[1], cc[2]};
   bool wrapped = false;
   if (side) { nc[ax] += 1; if (nc[ax] == g.N[ax]) { nc[ax] = 0; wrapped = true; } }
   else { nc[ax] -= 1; if (nc[ax] < 0) { nc[ax] = g.N[ax] - 1; wrapped = true; } }
   *internal = !wrapped && (cc[ax] / g.S[ax] == nc[ax] / g.S[ax]);
+  if (wrapped && !g.per[ax]) return -1;
   return g.cell_of(nc);
 }
 
@@ -401,8 +462,11 @@ int matching_node(int i, int dim, int P, int ax, int side) {
 
 // One transport step dt for a single scalar field f (one velocity, one
 // component): theta-scheme DG, subdomain sweeps, K Jacobi iterations.
+// fb_old / fb_new: kinetic boundary values of this field at the boundary
+// nodes (NULL: zero inflow at the faces of non-periodic axes).
 int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
-                     const double* f_old, double* f_new) {
+                     const double* f_old, double* f_new, const double* fb_old,
+                     const double* fb_new) {
   Grid g = make_grid(c);
   int d = c->dim, P = op.P, nn = op.nn, K = c->n_iter;
   double dt = c->dt, th = c->theta;
@@ -451,6 +515,19 @@ int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
               for (int side = 0; side < 2; ++side) {
                 bool internal;
                 long nb = neighbour(g, cc, ax, side, &internal);
+                if (nb < 0) {
+                  // face of the box on a Dirichlet axis: prescribed inflow
+                  const long off = face_offset(c, ax, side);
+                  for (int i = 0; i < nn; ++i) {
+                    double lc = op.lift[i * 2 * d + 2 * ax + side];
+                    if (lc == 0.0) continue;
+                    const long b = off + face_index(c, cc, ax, i);
+                    const double bo = fb_old ? fb_old[b] : 0.0;
+                    const double bn = fb_new ? fb_new[b] : 0.0;
+                    rhs[i] -= (1.0 - th) * lc * bo + th * lc * bn;
+                  }
+                  continue;
+                }
                 const double* tr_new;
                 if (internal) {
                   bool any_lift = false;
@@ -498,6 +575,9 @@ int transport_scalar(const orc_config* c, const CellOp& op, const double* V,
 
 int validate(const orc_config* c) {
   if (!c || c->dim < 1 || c->dim > 3 || c->degree < 0 || c->degree > 5) return 1;
+  if (c->periodic)
+    for (int a = 0; a < c->dim; ++a)
+      if (c->periodic[a] != 0 && c->periodic[a] != 1) return 1;
   if (c->m < 1 || c->n_vel < 1 || c->n_iter < 0 || !(c->dt > 0)) return 1;
   for (int a = 0; a < c->dim; ++a) {
     if (c->n_cells[a] < 1 || c->sub_cells[a] < 1) return 1;
@@ -527,12 +607,20 @@ int orc_cell_residual(const orc_config* c, const double* V, const double* f,
   return 0;
 }
 
-// Transport of one scalar field (velocity k) over dt; f layout [cell][node].
-int orc_transport(const orc_config* c, int k, const double* f_old, double* f_new) {
+// Transport of one scalar field (velocity k) over dt; f layout [cell][node];
+// fb_old / fb_new: its boundary values at the boundary nodes (or NULL).
+int orc_transport(const orc_config* c, int k, const double* f_old, double* f_new,
+                  const double* fb_old, const double* fb_new) {
   if (validate(c) || k < 0 || k >= c->n_vel) return 1;
   const double* V = c->vel + k * c->dim;
   CellOp op = build_cell_op(c, V);
-  return transport_scalar(c, op, V, f_old, f_new);
+  return transport_scalar(c, op, V, f_old, f_new, fb_old, fb_new);
+}
+
+// Number of boundary nodes (faces of the non-periodic axes).
+long orc_n_boundary_nodes(const orc_config* c) {
+  if (validate(c)) return -1;
+  return n_boundary_nodes(c);
 }
 
 // F[k][c][cell][node] = M_k(W)_c, W[cell][node][c]  (Sec. 2.2: F_k = M_k(W_0)).
@@ -608,7 +696,8 @@ int orc_relax(const orc_config* c, double* F) {
 
 // n_steps full time steps (Sec. 2.2): transport of every (k, c) field, then
 // relaxation.  The (k, c) transports are independent; n_threads > 1 runs them
-// concurrently (OpenMP) without changing any arithmetic.
+// concurrently (OpenMP) without changing any arithmetic.  Boundary data: the
+// first step goes from bnd_W_old to bnd_W_new, later steps hold bnd_W_new.
 int orc_step(const orc_config* c, double* F, int n_steps, int n_threads) {
   if (validate(c) || n_steps < 0) return 1;
   long nc = ncell_of(c);
@@ -616,6 +705,18 @@ int orc_step(const orc_config* c, double* F, int n_steps, int n_threads) {
   long slab = nc * nn;
   std::vector<CellOp> ops;
   for (int k = 0; k < nv; ++k) ops.push_back(build_cell_op(c, c->vel + k * c->dim));
+  // kinetic boundary data f_k = M_k(W_b) [k][c][boundary node], old and new
+  const long nb = n_boundary_nodes(c);
+  std::vector<double> fbo(nv * m * nb, 0.0), fbn(nv * m * nb, 0.0), Mb(nv * m);
+  auto kinetic = [&](const double* Wb, std::vector<double>& fb) -> int {
+    if (!Wb) return 0;
+    for (long b = 0; b < nb; ++b) {
+      if (orc_equilibrium(c, Wb + b * m, Mb.data())) return 1;
+      for (int kc = 0; kc < nv * m; ++kc) fb[kc * nb + b] = Mb[kc];
+    }
+    return 0;
+  };
+  if (nb > 0 && (kinetic(c->bnd_W_old, fbo) || kinetic(c->bnd_W_new, fbn))) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -628,10 +729,13 @@ int orc_step(const orc_config* c, double* F, int n_steps, int n_threads) {
       int k = kc / m;
       std::vector<double> out(slab);
       double* f = F + (long)kc * slab;
-      err |= transport_scalar(c, ops[k], c->vel + k * c->dim, f, out.data());
+      const double* bo = nb > 0 ? fbo.data() + kc * nb : nullptr;
+      const double* bn = nb > 0 ? fbn.data() + kc * nb : nullptr;
+      err |= transport_scalar(c, ops[k], c->vel + k * c->dim, f, out.data(), bo, bn);
       std::memcpy(f, out.data(), slab * sizeof(double));
     }
     if (err) return err;
+    fbo = fbn;  // later steps: the boundary state stays at its end value
     if (orc_relax(c, F)) return 1;
   }
   return 0;

@@ -40,6 +40,8 @@ class _Cfg(C.Structure):
         ("eq_a", C.POINTER(C.c_double)), ("eq_b", C.POINTER(C.c_double)),
         ("omega", C.c_double), ("dt", C.c_double), ("theta", C.c_double),
         ("n_iter", C.c_int32), ("source_sigma", C.POINTER(C.c_double)),
+        ("periodic", C.POINTER(C.c_int32)), ("bnd_W_old", C.POINTER(C.c_double)),
+        ("bnd_W_new", C.POINTER(C.c_double)),
     ]
 
 
@@ -60,7 +62,9 @@ def lib():
         _lib.orc_eq_weights.argtypes = [cp, dp, dp]
         _lib.orc_equilibrium.argtypes = [cp, dp, dp]
         _lib.orc_cell_residual.argtypes = [cp, dp, dp, dp, dp]
-        _lib.orc_transport.argtypes = [cp, C.c_int, dp, dp]
+        _lib.orc_transport.argtypes = [cp, C.c_int, dp, dp, dp, dp]
+        _lib.orc_n_boundary_nodes.argtypes = [cp]
+        _lib.orc_n_boundary_nodes.restype = C.c_long
         _lib.orc_init.argtypes = [cp, dp, dp]
         _lib.orc_moments.argtypes = [cp, dp, dp]
         _lib.orc_relax.argtypes = [cp, dp]
@@ -112,6 +116,10 @@ class Config:
         c.theta = spec.get("theta", 0.5)
         c.n_iter = spec.get("n_iter", 3)
         c.source_sigma = _dp(self._src) if self._src is not None else C.POINTER(C.c_double)()
+        self._per = np.ascontiguousarray(spec.get("periodic", [1, 1, 1]), dtype=np.int32)
+        c.periodic = self._per.ctypes.data_as(C.POINTER(C.c_int32))
+        c.bnd_W_old = C.POINTER(C.c_double)()
+        c.bnd_W_new = C.POINTER(C.c_double)()
         self.c = c
 
     @property
@@ -167,12 +175,26 @@ def cell_residual(cfg: Config, V, f, tr):
     return r
 
 
-def transport(cfg: Config, k: int, f_old):
-    """One transport step of a scalar field f[cell, node] for velocity k."""
+def _opt(a):
+    if a is None:
+        return None, C.POINTER(C.c_double)()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, _dp(a)
+
+
+def transport(cfg: Config, k: int, f_old, fb_old=None, fb_new=None):
+    """One transport step of a scalar field f[cell, node] for velocity k;
+    fb_old / fb_new: its values at the boundary nodes (Dirichlet axes)."""
     f_old = np.ascontiguousarray(f_old, dtype=np.float64)
     out = np.zeros_like(f_old)
-    _check(lib().orc_transport(cfg.ref, k, _dp(f_old), _dp(out)), "transport")
+    bo, po = _opt(fb_old)
+    bn, pn = _opt(fb_new)
+    _check(lib().orc_transport(cfg.ref, k, _dp(f_old), _dp(out), po, pn), "transport")
     return out
+
+
+def n_boundary_nodes(cfg: Config) -> int:
+    return int(lib().orc_n_boundary_nodes(cfg.ref))
 
 
 def init(cfg: Config, W):
@@ -195,9 +217,18 @@ def relax(cfg: Config, F):
     return F
 
 
-def step(cfg: Config, F, n_steps: int = 1, threads: int = 0):
+def step(cfg: Config, F, n_steps: int = 1, threads: int = 0, Wb_old=None, Wb_new=None):
+    """n_steps steps; Wb_old / Wb_new [boundary node, c]: boundary state at the
+    start and the end of the first step (later steps hold Wb_new)."""
     F = np.array(F, dtype=np.float64, order="C", copy=True)
-    _check(lib().orc_step(cfg.ref, _dp(F), n_steps, threads), "step")
+    bo, po = _opt(Wb_old)
+    bn, pn = _opt(Wb_new)
+    cfg.c.bnd_W_old, cfg.c.bnd_W_new = po, pn
+    try:
+        _check(lib().orc_step(cfg.ref, _dp(F), n_steps, threads), "step")
+    finally:
+        cfg.c.bnd_W_old = C.POINTER(C.c_double)()
+        cfg.c.bnd_W_new = C.POINTER(C.c_double)()
     return F
 
 

@@ -200,7 +200,7 @@ def euler_speeds(W, d, gamma=1.4):
 
 def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=None,
                   beta=None, omega=None, n_iter=3, theta=0.5, seed=None,
-                  precision="fp32", source_sigma=None, speed_bound=False):
+                  precision="fp32", source_sigma=None, speed_bound=False, periodic=None):
     """Return (spec, W0) for workload ``cfg`` (1..4, 6), optionally resized.
 
     6 is the paper's own setting: Maxwell's equations with the D3Q4 velocity
@@ -285,6 +285,7 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
         "n_iter": int(n_iter), "steps": int(steps), "beta": float(beta), "seed": seed,
         "precision": precision,
         "source_sigma": None if source_sigma is None else [float(v) for v in source_sigma],
+        "periodic": [1, 1, 1] if periodic is None else [int(v) for v in _pad3(periodic)],
     }
     X = node_coords(spec)
     if cfg == 6:
@@ -309,6 +310,85 @@ def make_workload(cfg: int, n_cells=None, sub_cells=None, degree=None, steps=Non
     spec["dt"] = float(_dt(beta, h, d, lam_max))
     spec["kinetic_courant"] = float(lam * spec["dt"] / h)
     return spec, np.ascontiguousarray(W0, dtype=np.float64)
+
+
+def boundary_faces(spec: dict):
+    """(axis, side, first boundary node, node count) of every face of the box
+    on a non-periodic axis, in the boundary-node order: axes x, y, z, low end
+    then high end."""
+    d = spec["dim"]
+    P = spec["degree"] + 1
+    N = spec["n_cells"][:d]
+    per = spec.get("periodic", [1, 1, 1])
+    out, off = [], 0
+    for a in range(d):
+        if per[a]:
+            continue
+        n = 1
+        for o in range(d):
+            if o != a:
+                n *= N[o] * P
+        for side in (0, 1):
+            out.append((a, side, off, n))
+            off += n
+    return out
+
+
+def n_boundary_nodes(spec: dict) -> int:
+    return sum(f[3] for f in boundary_faces(spec))
+
+
+def boundary_cells_nodes(spec: dict):
+    """For every boundary node: (cell index, node index inside the cell) of the
+    grid node that sits on it (the boundary cell's node on that face; degree 0:
+    the cell's single node).  Face order of boundary_faces; on a face, cells
+    over the other axes, then the cell's face nodes over the other axes' node
+    indices (lower axis fastest)."""
+    d = spec["dim"]
+    P = spec["degree"] + 1
+    N = spec["n_cells"][:d]
+    cells, nodes = [], []
+    for a, side, _, _ in boundary_faces(spec):
+        others = [o for o in range(d) if o != a]
+        for fc in np.ndindex(*[N[o] for o in reversed(others)]):
+            fc = list(reversed(fc))
+            for fn in np.ndindex(*[P for _ in others]):
+                fn = list(reversed(fn))
+                cc = [0] * d
+                ii = [0] * d
+                cc[a] = 0 if side == 0 else N[a] - 1
+                ii[a] = 0 if side == 0 else P - 1
+                for j, o in enumerate(others):
+                    cc[o] = fc[j]
+                    ii[o] = fn[j]
+                cid, mul = 0, 1
+                for o in range(d):
+                    cid += cc[o] * mul
+                    mul *= N[o]
+                nid, mul = 0, 1
+                for o in range(d):
+                    nid += ii[o] * mul
+                    mul *= P
+                cells.append(cid)
+                nodes.append(nid)
+    return np.asarray(cells, dtype=np.int64), np.asarray(nodes, dtype=np.int64)
+
+
+def boundary_coords(spec: dict) -> np.ndarray:
+    """Coordinates [boundary node, dim] of the boundary nodes."""
+    cells, nodes = boundary_cells_nodes(spec)
+    X = node_coords(spec)
+    return X[cells, nodes]
+
+
+def boundary_state(spec: dict, W0=None, t: float = 0.0) -> np.ndarray:
+    """Dirichlet data W_b [boundary node, m]: the exact plane wave at time t
+    for the Maxwell workload, else the trace of the initial state W0 on the
+    boundary (held constant in time)."""
+    if spec.get("cfg") == 6:
+        return np.ascontiguousarray(w_plane_wave(boundary_coords(spec), t), dtype=np.float64)
+    cells, nodes = boundary_cells_nodes(spec)
+    return np.ascontiguousarray(W0[cells, nodes], dtype=np.float64)
 
 
 def unknowns(spec: dict) -> int:

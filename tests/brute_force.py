@@ -62,11 +62,39 @@ def _node_id(ii, P):
     return j
 
 
-def global_transport(orc, cfg, k, f_old, K, lagged=True):
+def _boundary_index(spec, per, ax, side, cc, ii):
+    """Boundary-node number of node ii of cell cc on face (ax, side): the faces
+    of the non-periodic axes in x, y, z order, low end then high end; on a
+    face, cells over the other axes then the cell's face nodes over the other
+    axes' node indices (lower axis fastest)."""
+    d = spec["dim"]
+    N = spec["n_cells"][:d]
+    P = spec["degree"] + 1
+    def nodes_on(a):
+        n = 1
+        for o in range(d):
+            if o != a:
+                n *= N[o] * P
+        return n
+    off = sum(2 * nodes_on(a) for a in range(ax) if not per[a]) + side * nodes_on(ax)
+    cell, cmul, node, nmul = 0, 1, 0, 1
+    for o in range(d):
+        if o == ax:
+            continue
+        cell += cc[o] * cmul
+        cmul *= N[o]
+        node += ii[o] * nmul
+        nmul *= P
+    return off + cell * nmul + node
+
+
+def global_transport(orc, cfg, k, f_old, K, lagged=True, fb_old=None, fb_new=None):
     """K Jacobi iterates of the subdomain algorithm by dense global solves.
 
     lagged=False treats every face (wrap included) as implicit, i.e. the fully
-    implicit periodic DG system (the limit K -> infinity).
+    implicit periodic DG system (the limit K -> infinity).  On axes with
+    spec["periodic"][a] == 0 the faces of the box take the prescribed inflow
+    fb_old / fb_new (boundary-node numbering of _boundary_index).
     """
     spec = cfg.spec
     d, P, nn = cfg.dim, cfg.P, cfg.nn
@@ -78,7 +106,9 @@ def global_transport(orc, cfg, k, f_old, K, lagged=True):
     ncell = cfg.ncell
     n = ncell * nn
     f_old = np.asarray(f_old, dtype=np.float64).reshape(n)
-    # face structure: (cell, face, neighbour cell, interface?)
+    per = list(spec.get("periodic", [1, 1, 1]))[:d]
+    # face structure: (cell, face, neighbour cell or -1 at a Dirichlet face,
+    # interface?, cell coordinates)
     faces = []
     for cc in _cells(N, d):
         cid = _cell_id(cc, N)
@@ -89,7 +119,8 @@ def global_transport(orc, cfg, k, f_old, K, lagged=True):
                 wrapped = nc[ax] < 0 or nc[ax] >= N[ax]
                 nc[ax] %= N[ax]
                 iface = wrapped or (cc[ax] // S[ax] != nc[ax] // S[ax])
-                faces.append((cid, 2 * ax + side, _cell_id(nc, N), iface))
+                nb = -1 if (wrapped and not per[ax]) else _cell_id(nc, N)
+                faces.append((cid, 2 * ax + side, nb, iface, cc))
     prev = f_old.copy()
     iters = K if lagged else 1
     for _ in range(iters):
@@ -99,13 +130,19 @@ def global_transport(orc, cfg, k, f_old, K, lagged=True):
             sl = slice(cid * nn, (cid + 1) * nn)
             A[sl, sl] += np.eye(nn) / dt + th * L
             b[sl] += f_old[sl] / dt - (1 - th) * (L @ f_old[sl])
-        for cid, fce, nb, iface in faces:
+        for cid, fce, nb, iface, cc in faces:
             ax, side = divmod(fce, 2)
             for i in range(nn):
                 c = lift[fce, i]
                 if c == 0.0:
                     continue
                 ii = _node_idx(i, d, P)
+                if nb < 0:
+                    bi = _boundary_index(spec, per, ax, side, cc, ii)
+                    bo = 0.0 if fb_old is None else fb_old[bi]
+                    bn = 0.0 if fb_new is None else fb_new[bi]
+                    b[cid * nn + i] -= c * ((1 - th) * bo + th * bn)
+                    continue
                 ii[ax] = 0 if side else P - 1
                 j = _node_id(ii, P)
                 row = cid * nn + i
