@@ -13,10 +13,11 @@
  *   algorithm of Sec. 5.1 (eq:ibvp, n_iter iterations), and then applies the
  *   over-relaxation F_k <- F_k + omega (M_k(W) - F_k) (eq:over_relaxation).
  *
- * Discretisation: periodic Cartesian box, n_cells[a] uniform cells per axis,
- * tensor Gauss-Lobatto nodal basis of degree p ((p+1)^d nodes per cell),
- * collocated Gauss-Lobatto quadrature.  Subdomains are boxes of sub_cells[a]
- * cells.  Periodic wrap faces are always subdomain interfaces.
+ * Discretisation: Cartesian box, n_cells[a] uniform cells per axis, periodic
+ * or with Dirichlet ends per axis, tensor Gauss-Lobatto nodal basis of degree p
+ * ((p+1)^d nodes per cell), collocated Gauss-Lobatto quadrature.  Subdomains
+ * are boxes of sub_cells[a] cells.  Periodic wrap faces are always subdomain
+ * interfaces.
  *
  * Conventions for every call:
  *   - Status codes only; no exception or abort crosses the ABI.  After an
@@ -89,7 +90,7 @@ typedef struct {
   int32_t dim;           /* d = 1, 2 or 3 */
   int32_t n_cells[3];    /* cells per axis (entries beyond dim ignored) */
   int32_t sub_cells[3];  /* subdomain size in cells; must divide n_cells */
-  int32_t periodic[3];   /* must be 1 on every used axis (periodic box) */
+  int32_t periodic[3];   /* 1: periodic axis; 0: Dirichlet ends (kds_set_boundary) */
   double box_lo[3];
   double box_hi[3];
   int32_t degree;        /* p = 0..3; p = 0 is the finite-volume limit */
@@ -134,6 +135,23 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
 /* Initial kinetic state F_k = M_k(W) at every node (Sec. 2.2).
  * W: FP64 [cell][node][c].  Resets the step counter. */
 kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device);
+
+/* Dirichlet data on the faces of the axes with periodic[a] = 0 (the exact
+ * solution imposed on the boundary, Sec. 6.2).  W_b: FP64 [boundary node][c],
+ * the conservative state at the boundary nodes at the END of the next step.
+ * Boundary nodes: for each non-periodic axis a (x, y, z order), the face at
+ * the low end, then at the high end; on a face, the cells over the other axes
+ * (lower axis fastest), then the cell's face nodes over the other axes' node
+ * indices (lower axis fastest); count = sum over those axes of
+ * 2 * (cells / n_cells[a]) * (p+1)^(d-1).  The upwind value at an inflow face
+ * of the box is the kinetic equilibrium M_k(W_b) (a reading: the paper imposes
+ * W and leaves the kinetic translation open), taken at the start and at the
+ * end of the step by the theta-scheme.  A step goes from the previous call's
+ * data (the same data at the first call) to this call's; after a step the
+ * data hold their end value, so kds_step(n) with n > 1 keeps them constant.
+ * Required before kds_step when some axis is not periodic (else KDS_E_STATE);
+ * KDS_E_INVALID on a periodic box. */
+kds_status kds_set_boundary(kds_problem* p, const double* W_b, int32_t on_device);
 
 /* n_steps time steps (Sec. 2.2): transport of every F_k (K subdomain
  * iterations of the downwind sweep, eq:dg_imp / eq:ibvp) then relaxation

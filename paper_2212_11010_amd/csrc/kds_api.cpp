@@ -60,11 +60,29 @@ struct kds_problem {
   int lds_cap = 64 * 1024;              // LDS bytes a workgroup may use on the device
   bool state_set = false;
   int steps_done = 0;
+  // Dirichlet boundaries (axes with periodic = 0)
+  int per[3] = {1, 1, 1};
+  int64_t nbnd = 0;                  // boundary nodes
+  int64_t boff[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // first node of face (axis, side)
+  void* fb = nullptr;                // kinetic boundary values: old half, then new half
+  double* Wb_dev = nullptr;          // staging of W_b
+  bool bnd_set = false;
   int plan_version = 0;  // bumped when the launch plan changes (batches rebuild)
   std::string err;
 
   int64_t plane() const { return ncell * nn; }
   int64_t n_unknowns() const { return plane() * m * nv; }
+  int64_t bnd_half() const { return (int64_t)nv * m * nbnd; }  // elements per time level
+  BndArgs bnd() const {
+    BndArgs b;
+    if (nbnd == 0) return b;
+    b.old = fb;
+    b.neu = (const unsigned char*)fb + bnd_half() * elem;
+    b.nb = nbnd;
+    for (int a = 0; a < 3; ++a)
+      for (int s = 0; s < 2; ++s) b.off[a][s] = boff[a][s];
+    return b;
+  }
 };
 
 namespace {
@@ -97,7 +115,10 @@ kds_status validate(const kds_config* c, std::string& msg) {
       msg = "sub_cells must be >= 1 and divide n_cells on every axis";
       return KDS_E_INVALID;
     }
-    if (c->periodic[a] != 1) { msg = "only periodic boxes are supported (periodic[a] = 1)"; return KDS_E_UNSUPPORTED; }
+    if (c->periodic[a] != 0 && c->periodic[a] != 1) {
+      msg = "periodic[a] must be 1 (periodic) or 0 (Dirichlet ends)";
+      return KDS_E_INVALID;
+    }
     if (!finite(c->box_lo[a]) || !finite(c->box_hi[a]) || !(c->box_hi[a] > c->box_lo[a])) {
       msg = "box_hi must exceed box_lo";
       return KDS_E_INVALID;
@@ -342,12 +363,14 @@ void free_device(kds_problem* p) {
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
-                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1]};
+                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1], p->fb, p->Wb_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
   p->front_W = p->fit[0] = p->fit[1] = nullptr;
   p->front_lvl_start = p->front_lvl_cells = nullptr;
+  p->fb = nullptr;
+  p->Wb_dev = nullptr;
   p->stage = nullptr;
   p->flag = nullptr;
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
@@ -365,12 +388,12 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
       const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
       KDS_HIP(p, launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
                                     p->front_lvl_start, p->front_lvl_cells, p->f, f_prev,
-                                    p->fit[it & 1], s));
+                                    p->fit[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
     KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->fit[p->K & 1], p->f, s));
   } else if (p->sched == KDS_SCHED_LINE) {
-    KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, s));
+    KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->bnd(), s));
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
     KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, s));
   } else {
@@ -378,10 +401,15 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
       const void* tr_prev = it == 1 ? nullptr : p->tr[(it - 1) & 1];
       void* f_new = it == p->K ? p->f_tmp : nullptr;
       KDS_HIP(p, launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, f_new, tr_prev,
-                                    p->tr[it & 1], s));
+                                    p->tr[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
     KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f_tmp, p->f, s));
+  }
+  // the boundary data at the end of this step are the start data of the next
+  if (p->nbnd > 0) {
+    const BndArgs b = p->bnd();
+    KDS_HIP(p, launch_copy(p->prec, b.neu, p->fb, p->bnd_half(), s));
   }
   if (events) KDS_HIP(p, hipEventRecord(p->ev[2], s));
   return KDS_OK;
@@ -455,11 +483,20 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     p->hi[a] = a < cfg->dim ? cfg->box_hi[a] : 1.0;
     p->h[a] = (p->hi[a] - p->lo[a]) / p->N[a];
     p->ncell *= p->N[a];
+    p->per[a] = a < cfg->dim ? cfg->periodic[a] : 1;
   }
   p->degree = cfg->degree;
   p->P = cfg->degree + 1;
   p->nn = 1;
   for (int a = 0; a < p->dim; ++a) p->nn *= p->P;
+  // boundary nodes: faces of the non-periodic axes, low end then high end
+  for (int a = 0; a < p->dim; ++a) {
+    if (p->per[a]) continue;
+    const int64_t face = p->ncell / p->N[a] * (p->nn / p->P);
+    p->boff[a][0] = p->nbnd;
+    p->boff[a][1] = p->nbnd + face;
+    p->nbnd += 2 * face;
+  }
   p->m = cfg->m;
   p->law = cfg->law;
   p->nv = cfg->n_vel;
@@ -584,7 +621,7 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     return fail(nullptr, KDS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
   }
   const size_t state_bytes = (size_t)p->n_unknowns() * p->elem;
-  size_t need = state_bytes;
+  size_t need = state_bytes + 2 * (size_t)p->bnd_half() * p->elem + (size_t)p->nbnd * p->m * 8;
   if (p->sched == KDS_SCHED_PLAIN) need += state_bytes + 2 * (size_t)g.tr_stride * p->nv * p->m * p->elem;
   if (p->sched == KDS_SCHED_FRONT) need += 2 * state_bytes;
   size_t free_b = 0, total_b = 0;
@@ -603,6 +640,9 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     return true;
   };
   bool ok = alloc(&p->f, state_bytes) && alloc((void**)&p->flag, sizeof(int));
+  if (ok && p->nbnd > 0)
+    ok = alloc(&p->fb, 2 * (size_t)p->bnd_half() * p->elem) &&
+         alloc((void**)&p->Wb_dev, (size_t)p->nbnd * p->m * sizeof(double));
   if (ok && p->sched == KDS_SCHED_PLAIN) {
     const size_t trb = std::max<size_t>(1, (size_t)g.tr_stride * p->nv * p->m * p->elem);
     ok = alloc(&p->f_tmp, state_bytes) && alloc(&p->tr[0], trb) && alloc(&p->tr[1], trb);
@@ -691,10 +731,39 @@ kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device) {
   return KDS_OK;
 }
 
+kds_status kds_set_boundary(kds_problem* p, const double* Wb, int32_t on_device) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (p->nbnd == 0) return fail(p, KDS_E_INVALID, "the box is periodic on every axis");
+  if (!Wb) return fail(p, KDS_E_INVALID, "W_b is NULL");
+  const size_t bytes = (size_t)p->nbnd * p->m * sizeof(double);
+  if (on_device) {
+    kds_status st = check_device_ptr(p, Wb);
+    if (st != KDS_OK) return st;
+    KDS_HIP(p, hipMemcpyAsync(p->Wb_dev, Wb, bytes, hipMemcpyDeviceToDevice, p->stream));
+  } else {
+    KDS_HIP(p, hipMemcpyAsync(p->Wb_dev, Wb, bytes, hipMemcpyHostToDevice, p->stream));
+  }
+  // the boundary nodes as a one-node-per-cell grid: F_k = M_k(W_b) into the
+  // new half, after the new half of the previous call moved to the old half
+  Geom gb = p->geom;
+  gb.ncell = p->nbnd;
+  gb.nn = 1;
+  const BndArgs b = p->bnd();
+  void* neu = const_cast<void*>(b.neu);
+  if (p->bnd_set) KDS_HIP(p, launch_copy(p->prec, b.neu, p->fb, p->bnd_half(), p->stream));
+  KDS_HIP(p, launch_init(p->prec, p->law, gb, p->eq_blob.data(), p->Wb_dev, neu, p->stream));
+  if (!p->bnd_set) KDS_HIP(p, launch_copy(p->prec, b.neu, p->fb, p->bnd_half(), p->stream));
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
+  p->bnd_set = true;
+  return KDS_OK;
+}
+
 kds_status kds_step(kds_problem* p, int32_t n_steps) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (n_steps < 0) return fail(p, KDS_E_INVALID, "n_steps must be >= 0");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step before kds_set_state / kds_set_kinetic");
+  if (p->nbnd > 0 && !p->bnd_set)
+    return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary before kds_step");
   if (n_steps == 0) return KDS_OK;
   int left = n_steps;
   if (left >= kGraphSteps) {
@@ -716,6 +785,7 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (n_steps < 0 || !kernel_ms) return fail(p, KDS_E_INVALID, "bad arguments");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_step_timed before kds_set_state");
+  if (p->nbnd > 0 && !p->bnd_set) return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary first");
   double acc[KDS_N_KERNEL_KINDS] = {0, 0};
   for (int i = 0; i < n_steps; ++i) {
     kds_status st = enqueue_step(p, true, p->stream);
@@ -735,6 +805,7 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms) {
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_tune needs a state (kds_set_state first)");
+  if (p->nbnd > 0 && !p->bnd_set) return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary first");
   if (p->sched != KDS_SCHED_LINE) {
     if (sweep_ms) *sweep_ms = -1.0;
     return KDS_OK;
@@ -749,10 +820,11 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   KDS_HIP(p, hipMemcpyAsync(save, p->f, bytes, hipMemcpyDeviceToDevice, p->stream));
   kds_status st = KDS_OK;
   auto time_plan = [&](const LinePlan& pl, float* ms) -> bool {
-    hipError_t e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->stream);
+    hipError_t e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->bnd(),
+                                     p->stream);
     if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r)
-      e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->stream);
+      e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->bnd(), p->stream);
     if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
     if (e == hipSuccess) e = hipEventSynchronize(p->ev[1]);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
@@ -808,6 +880,7 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (!kernel_ms || reps < 1) return fail(p, KDS_E_INVALID, "bad arguments");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_time_kernels needs a state");
+  if (p->nbnd > 0 && !p->bnd_set) return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary first");
   const size_t bytes = (size_t)p->n_unknowns() * p->elem;
   void* save = nullptr;
   if (hipMalloc(&save, bytes) != hipSuccess) {
@@ -823,12 +896,13 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
         if (p->sched == KDS_SCHED_FRONT)
           return launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
                                     p->front_lvl_start, p->front_lvl_cells, p->f, p->f,
-                                    p->fit[1], p->stream);
+                                    p->fit[1], p->bnd(), p->stream);
         if (p->sched == KDS_SCHED_LINE)
-          return launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->stream);
+          return launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->bnd(),
+                                   p->stream);
         // one plain subdomain iteration (the kernel a step launches n_iter times)
         return launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, p->f_tmp, nullptr,
-                                  p->tr[0], p->stream);
+                                  p->tr[0], p->bnd(), p->stream);
       }
       return launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream);
     };
@@ -1029,7 +1103,8 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    if (p->sched != KDS_SCHED_LINE) {
+    // plain, front and Dirichlet members keep their own kernel sequences
+    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0) {
       b->others.push_back(p);
       continue;
     }
@@ -1055,7 +1130,8 @@ kds_status batch_build(kds_batch* b) {
     if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
     size_t off = br->line_tasks.size();
     br->line_tasks.resize(off + lb);
-    pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, br->line_tasks.data() + off);
+    pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, p->bnd(),
+                   br->line_tasks.data() + off);
     br->line_start.push_back(br->line_start.back() + p->plan.block_start[g.nv * g.m]);
     br->lds_elems = std::max(br->lds_elems, (size_t)p->plan.lds_elems);
     off = br->relax_tasks.size();
@@ -1138,8 +1214,11 @@ kds_status batch_enqueue(kds_batch* b) {
 }
 
 kds_status batch_prepare(kds_batch* b) {
-  for (kds_problem* p : b->probs)
+  for (kds_problem* p : b->probs) {
     if (!p->state_set) return bfail(b, KDS_E_STATE, "a batch member has no state");
+    if (p->nbnd > 0 && !p->bnd_set)
+      return bfail(b, KDS_E_STATE, "a batch member has Dirichlet axes but no boundary data");
+  }
   bool stale = b->branches.empty() && b->others.empty();
   for (size_t i = 0; i < b->probs.size(); ++i)
     if (b->versions[i] != b->probs[i]->plan_version) stale = true;

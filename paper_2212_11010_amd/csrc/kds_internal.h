@@ -100,6 +100,38 @@ struct LinePlan {
   int threads;             // block size
 };
 
+// Dirichlet inflow data of the faces of non-periodic axes: kinetic values
+// M_k(W_b) at the boundary nodes, [k][c][boundary node], at the start (old)
+// and the end (neu) of the step.  Boundary nodes: faces of the non-periodic
+// axes in x, y, z order, low end then high end; on a face, cells over the
+// other axes, then face nodes over the other axes' node indices (lower axis
+// fastest).
+struct BndArgs {
+  const void* old = nullptr;  // nullptr: periodic on every axis
+  const void* neu = nullptr;
+  int64_t nb = 0;             // boundary nodes
+  int64_t off[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // first node of face (axis, side)
+};
+
+template <typename T>
+struct BndRef {
+  const T* old;
+  const T* neu;
+  int64_t nb;
+  int64_t off[3][2];
+};
+
+template <typename T>
+inline BndRef<T> bnd_ref(const BndArgs& b) {
+  BndRef<T> r;
+  r.old = (const T*)b.old;
+  r.neu = (const T*)b.neu;
+  r.nb = b.nb;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) r.off[a][s] = b.off[a][s];
+  return r;
+}
+
 // One problem of a batched line-sweep launch.
 template <typename T>
 struct LineTask {
@@ -107,6 +139,7 @@ struct LineTask {
   Geom g;
   SweepTab<T> tab;
   LinePlan pl;
+  BndRef<T> bd;
 };
 
 // One problem of a batched relaxation launch (pointwise kernel).
@@ -144,15 +177,18 @@ hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F,
 hipError_t launch_set_kinetic(int prec, const Geom& g, const double* F, void* f, hipStream_t s);
 hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag, hipStream_t s);
 hipError_t launch_sweep_plain(int prec, const Geom& g, const void* tab, const void* f_old,
-                              void* f_new, const void* tr_prev, void* tr_out, hipStream_t s);
+                              void* f_new, const void* tr_prev, void* tr_out, const BndArgs& bnd,
+                              hipStream_t s);
 hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const LinePlan& plan,
-                             void* f, hipStream_t s);
+                             void* f, const BndArgs& bnd, hipStream_t s);
+hipError_t launch_copy(int prec, const void* src, void* dst, int64_t n, hipStream_t s);
 // One subdomain iteration of the front sweep: reads f_old (state at t^{n-1})
 // and f_prev (iterate p-1), writes f_cur (iterate p).  mode: FrontMode; for
 // kFrontFma the element type follows prec (FP64 or FP32), the MFMA modes are FP32.
 hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontParams& fp,
                               const void* Wop, const int* lvl_start, const int* lvl_cells,
-                              const void* f_old, const void* f_prev, void* f_cur, hipStream_t s);
+                              const void* f_old, const void* f_prev, void* f_cur,
+                              const BndArgs& bnd, hipStream_t s);
 size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp);
 
 // Batched launches (many problems per kernel): task records are packed on the
@@ -165,7 +201,8 @@ hipError_t launch_relax_batch(int prec, int law, int dim, int m, int nv, const v
                               const int64_t* start, int ntask, int64_t nblocks, hipStream_t s);
 hipError_t line_kernels_allow_lds(size_t bytes);
 size_t line_task_bytes(int prec);
-void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl, void* out);
+void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl,
+                    const BndArgs& bnd, void* out);
 hipError_t launch_sweep_line_batch(int prec, int P, int dim, const void* tasks, const int64_t* start,
                                    int ntask, int64_t nblocks, int threads, size_t lds_elems,
                                    hipStream_t s);

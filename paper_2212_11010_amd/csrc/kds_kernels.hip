@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_sweep_plain(const T* __restrict__ f_old
                                                      T* __restrict__ f_new,
                                                      const T* __restrict__ tr_prev,
                                                      T* __restrict__ tr_out, Geom g,
-                                                     SweepTab<T> tab) {
+                                                     SweepTab<T> tab, BndRef<T> bd) {
   const int kc = blockIdx.y;
   const int k = kc / g.m;
   const int a = tab.axis[k];
@@ -280,7 +280,14 @@ __global__ __launch_bounds__(256) void k_sweep_plain(const T* __restrict__ f_old
   }
 
   T t_old, t_new;
-  {
+  const int bside = sg > 0 ? 0 : 1;
+  if (seg == 0 && bd.old != nullptr && bd.off[a][bside] >= 0) {
+    // first subdomain on a Dirichlet axis: the prescribed inflow (the line
+    // index is the boundary node's index on the face)
+    const int64_t bi = (int64_t)kc * bd.nb + bd.off[a][bside] + line;
+    t_old = bd.old[bi];
+    t_new = bd.neu[bi];
+  } else {
     const int j = seg * S;  // downwind index of the first cell
     const int r = sg > 0 ? j : Na - 1 - j;
     const int ru = sg > 0 ? (r == 0 ? Na - 1 : r - 1) : (r == Na - 1 ? 0 : r + 1);
@@ -555,6 +562,7 @@ struct LineLane {
   int Q, Ls, sl, end_up, src_prev;
   int nseg, s_me, lbase;
   bool dpp_ok;
+  bool first;  // owns the first cells of the line in downwind order
 };
 
 // One lane's part of the line solve.  d[q][node]: my Q cells in downwind
@@ -563,8 +571,17 @@ struct LineLane {
 template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0, int PER>
 __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
                                            const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
-                                           T gg, T G, int K) {
+                                           T gg, T G, int K, const T* bo, const T* bn) {
   static_assert(NN == ColShape<P, DIM>::NN, "cell size");
+  // Dirichlet axis: bo / bn point at this line's boundary values (inflow of
+  // the first subdomain at the old / new time); nullptr on a periodic axis
+  const bool dir = bo != nullptr;
+  T bold[PER], bnew[PER];
+#pragma unroll
+  for (int o = 0; o < PER; ++o) {
+    bold[o] = dir ? bo[O0 + o] : T(0);
+    bnew[o] = dir ? bn[O0 + o] : T(0);
+  }
   // physical node of downwind node b along the axis, line O0 + o
 #define KDS_ND(o, b) node_of<P, DIM, AXIS>(O0 + (o), SIGN > 0 ? (b) : P - 1 - (b))
   T last_old[PER], t_old0[PER], mB[PER];
@@ -578,7 +595,10 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
     last_old[o] = lo;
   }
 #pragma unroll
-  for (int o = 0; o < PER; ++o) t_old0[o] = __shfl(last_old[o], ln.src_prev, 64);
+  for (int o = 0; o < PER; ++o) {
+    t_old0[o] = __shfl(last_old[o], ln.src_prev, 64);
+    if (dir && ln.first) t_old0[o] = bold[o];
+  }
   // zero-inflow recurrence over my cells
 #pragma unroll
   for (int o = 0; o < PER; ++o) {
@@ -629,7 +649,9 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
   // subdomain iteration on the outflows (meaningful on subdomain-end lanes):
   // T_s^p = P_s + G T_{s-1}^{p-1}, inflow of iterate K = T_{s-1}^{K-1}.
   // K = 0: the converged limit, T_s = sum_q G^q P_{s-q} / (1 - G^nseg)
-  // (the fully implicit periodic line solve).
+  // (the fully implicit periodic line solve).  On a Dirichlet axis the first
+  // subdomain's inflow is the boundary value b at every iterate, and the
+  // limit is T_{s-1} = sum_{q<s} G^q P_{s-1-q} + G^s b.
   T t_in[PER];
   if (K > 0) {
     T Tv[PER];
@@ -638,12 +660,16 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
     for (int it = 1; it < K; ++it) {
 #pragma unroll
       for (int o = 0; o < PER; ++o) {
-        const T up = __shfl(Tv[o], ln.end_up, 64);
+        T up = __shfl(Tv[o], ln.end_up, 64);
+        if (dir && ln.s_me == 0) up = bnew[o];
         Tv[o] = mB[o] + G * up;
       }
     }
 #pragma unroll
-    for (int o = 0; o < PER; ++o) t_in[o] = __shfl(Tv[o], ln.end_up, 64);
+    for (int o = 0; o < PER; ++o) {
+      t_in[o] = __shfl(Tv[o], ln.end_up, 64);
+      if (dir && ln.s_me == 0) t_in[o] = bnew[o];
+    }
   } else {
 #pragma unroll
     for (int o = 0; o < PER; ++o) t_in[o] = T(0);
@@ -652,12 +678,21 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
       const int s_src = ((ln.s_me - 1 - q) % ln.nseg + ln.nseg) % ln.nseg;
       const int src = ln.lbase + (s_src + 1) * ln.Ls - 1;
 #pragma unroll
-      for (int o = 0; o < PER; ++o) t_in[o] += Gq * __shfl(mB[o], src, 64);
+      for (int o = 0; o < PER; ++o) {
+        const T v = __shfl(mB[o], src, 64);
+        if (!dir || q < ln.s_me) t_in[o] += Gq * v;
+      }
       Gq *= G;
     }
-    const T inv = T(1) / (T(1) - Gq);
+    if (dir) {
+      const T Gs = powi(G, ln.s_me);
 #pragma unroll
-    for (int o = 0; o < PER; ++o) t_in[o] *= inv;
+      for (int o = 0; o < PER; ++o) t_in[o] += Gs * bnew[o];
+    } else {
+      const T inv = T(1) / (T(1) - Gq);
+#pragma unroll
+      for (int o = 0; o < PER; ++o) t_in[o] *= inv;
+    }
   }
   const T g0 = powi(gg, ln.sl * ln.Q);
 #pragma unroll
@@ -692,13 +727,13 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
 template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0 = 0>
 __device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
                                            const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
-                                           T gg, T G, int K) {
+                                           T gg, T G, int K, const T* bo, const T* bn) {
   constexpr int ALL = ColShape<P, DIM>::PER;
   constexpr int GS = ALL <= 4 ? ALL : (ALL % 3 == 0 ? 3 : 4);
   if constexpr (O0 < ALL) {
     constexpr int n = ALL - O0 < GS ? ALL - O0 : GS;
-    line_group<T, P, DIM, AXIS, SIGN, QMAX, NN, O0, n>(d, ln, C, e1, eth, gg, G, K);
-    line_lanes<T, P, DIM, AXIS, SIGN, QMAX, NN, O0 + n>(d, ln, C, e1, eth, gg, G, K);
+    line_group<T, P, DIM, AXIS, SIGN, QMAX, NN, O0, n>(d, ln, C, e1, eth, gg, G, K, bo, bn);
+    line_lanes<T, P, DIM, AXIS, SIGN, QMAX, NN, O0 + n>(d, ln, C, e1, eth, gg, G, K, bo, bn);
   }
 }
 
@@ -716,7 +751,7 @@ __device__ __forceinline__ int64_t xcd_order(int64_t nb) {
 template <typename T, int P, int DIM>
 __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
                                             const SweepTab<T>& tab, const LinePlan& pl,
-                                            int64_t bid, T* tile) {
+                                            const BndRef<T>& bd, int64_t bid, T* tile) {
   constexpr int NN = ColShape<P, DIM>::NN;
   constexpr int QMAX = line_qmax((int)sizeof(T), NN);
   int kc = 0;
@@ -788,11 +823,31 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
   }
   ln.src_prev = lbase + (lil == 0 ? NL - 1 : lil - 1);
   ln.dpp_ok = ln.Ls <= 16 && (16 % ln.Ls) == 0;
+  ln.first = lil == 0;
   const int j0 = lil * Q;
+  // Dirichlet axis: boundary values of this (k, c) on the inflow face
+  constexpr int PER = ColShape<P, DIM>::PER;
+  const int bside = sg > 0 ? 0 : 1;
+  const int64_t boff = (bd.old != nullptr && bd.off[a][bside] >= 0)
+                           ? (int64_t)kc * bd.nb + bd.off[a][bside] : -1;
 
   for (int cb = wave * LW; cb < ncols; cb += nwaves * LW) {
     const int c = cb + slot;
     const bool act = (c < ncols) && (lil < NL);
+    const T* bo = nullptr;
+    const T* bn = nullptr;
+    if (boff >= 0 && act) {
+      // the column's cell index on the face (cells over the other axes, lower fastest)
+      int64_t fcell;
+      if (a == 0) {
+        fcell = bundle * bw + c;
+      } else {
+        const int nbx = (g.N[0] + bw - 1) / bw;
+        fcell = (bundle % nbx) * bw + c + (int64_t)g.N[0] * (bundle / nbx);
+      }
+      bo = bd.old + boff + fcell * PER;
+      bn = bd.neu + boff + fcell * PER;
+    }
     // my cells in downwind order: physical cells j0.. (SIGN > 0) or
     // Na-1-j0 downwards (SIGN < 0)
     const int cbase = (act ? c : 0) * CS;
@@ -806,12 +861,12 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
       for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
     }
     switch (a * 2 + (sg > 0 ? 1 : 0)) {
-      case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
-      case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
-      case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
-      case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
-      case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
-      default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K); break;
+      case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
     }
     if (act) {
 #pragma unroll
@@ -844,9 +899,9 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
 
 template <typename T, int P, int DIM>
 __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, SweepTab<T> tab,
-                                                    LinePlan pl) {
+                                                    LinePlan pl, BndRef<T> bd) {
   extern __shared__ unsigned char smem_raw[];
-  line_bundle<T, P, DIM>(f, g, tab, pl, xcd_order(pl.block_start[g.nv * g.m]),
+  line_bundle<T, P, DIM>(f, g, tab, pl, bd, xcd_order(pl.block_start[g.nv * g.m]),
                          reinterpret_cast<T*>(smem_raw));
 }
 
@@ -861,7 +916,8 @@ __global__ __launch_bounds__(256) void k_sweep_line_batch(const LineTask<T>* __r
   int pid = 0;
   while (gbid >= start[pid + 1]) ++pid;
   const LineTask<T>& t = tasks[pid];
-  line_bundle<T, P, DIM>(t.f, t.g, t.tab, t.pl, gbid - start[pid], reinterpret_cast<T*>(smem_raw));
+  line_bundle<T, P, DIM>(t.f, t.g, t.tab, t.pl, t.bd, gbid - start[pid],
+                         reinterpret_cast<T*>(smem_raw));
 }
 
 // ====================================================== front sweep
@@ -903,7 +959,8 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
                                                      T* __restrict__ f_cur, Geom g, FrontParams fp,
                                                      const T* __restrict__ Wop,
                                                      const int* __restrict__ lvl_start,
-                                                     const int* __restrict__ lvl_cells) {
+                                                     const int* __restrict__ lvl_cells,
+                                                     BndRef<T> bd) {
   extern __shared__ unsigned char smem_raw[];
   const int nn = g.nn, nf = fp.nf, Kd = fp.Kd, P = g.P, m = g.m;
   const int Mpad = (nn + 15) & ~15;
@@ -914,7 +971,8 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
   T* X = Wt + (MODE == kFrontFma ? 0 : Mpad * Kpad);  // [Kpad][XS]
   __shared__ int64_t col_base[kFrontMaxChunk];         // per column: state offset of the cell
   __shared__ int64_t col_nb[3][kFrontMaxChunk];        // ... of the upwind neighbour per face
-  __shared__ unsigned char col_int[3][kFrontMaxChunk]; // neighbour inside the subdomain?
+  __shared__ unsigned char col_int[3][kFrontMaxChunk]; // 1: neighbour inside the subdomain,
+                                                       // 2: face of the box on a Dirichlet axis
   __shared__ int face_node[3 * kMaxP * kMaxP * kMaxP]; // neighbour node of face row q
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const int k = blockIdx.x / nsd;
@@ -977,10 +1035,24 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
           if (a < g.dim && sgn[a] != 0) {
             int nb[3] = {gc[0], gc[1], gc[2]};
             nb[a] -= sgn[a];
-            if (nb[a] < 0) nb[a] += g.N[a];
-            if (nb[a] >= g.N[a]) nb[a] -= g.N[a];
-            nbo = kc + (nb[0] + (int64_t)g.N[0] * (nb[1] + (int64_t)g.N[1] * nb[2])) * nn;
-            col_int[a][tid] = lc[a] > 0 ? 1 : 0;
+            const bool outside = nb[a] < 0 || nb[a] >= g.N[a];
+            const int bside = sgn[a] > 0 ? 0 : 1;
+            if (outside && bd.old != nullptr && bd.off[a][bside] >= 0) {
+              // boundary values of the face cell (cells over the other axes)
+              int64_t fcell = 0, mul = 1;
+              for (int o = 0; o < g.dim; ++o)
+                if (o != a) {
+                  fcell += gc[o] * mul;
+                  mul *= g.N[o];
+                }
+              nbo = (int64_t)(k * m + c) * bd.nb + bd.off[a][bside] + fcell * nf;
+              col_int[a][tid] = 2;
+            } else {
+              if (nb[a] < 0) nb[a] += g.N[a];
+              if (nb[a] >= g.N[a]) nb[a] -= g.N[a];
+              nbo = kc + (nb[0] + (int64_t)g.N[0] * (nb[1] + (int64_t)g.N[1] * nb[2])) * nn;
+              col_int[a][tid] = lc[a] > 0 ? 1 : 0;
+            }
           }
           col_nb[a][tid] = nbo;
         }
@@ -995,6 +1067,7 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
           T vo[U], vn[U];
           int rr[U], jq[U];
           int face[U];
+          bool isb[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = e0 + u * bs;
@@ -1011,16 +1084,20 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
                 const int a = (r - nn) / nf;
                 if (col_nb[a][jj] >= 0) {
                   fa = a;
-                  at = col_nb[a][jj] + face_node[r - nn];
+                  // boundary values are numbered by face node (row q of face a)
+                  at = col_nb[a][jj] +
+                       (col_int[a][jj] == 2 ? (r - nn - a * nf) : face_node[r - nn]);
                 } else {
                   live = false;
                 }
               }
             }
             face[u] = live ? fa : -2;
+            isb[u] = live && fa >= 0 && col_int[fa][jj] == 2;
             // inactive slots re-read element 0 of the state (never used)
-            vo[u] = f_old[live ? at : 0];
-            vn[u] = (fa >= 0 && col_int[fa][jj]) ? f_cur[at] : f_prev[fa >= 0 ? at : 0];
+            vo[u] = isb[u] ? bd.old[at] : f_old[live ? at : 0];
+            vn[u] = isb[u] ? bd.neu[at]
+                           : ((fa >= 0 && col_int[fa][jj]) ? f_cur[at] : f_prev[fa >= 0 ? at : 0]);
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
@@ -1217,7 +1294,7 @@ const ComboEntry* find_combo(int law, int dim, int m, int nv) {
 
 template <typename T>
 hipError_t sweep_plain_t(const Geom& g, const void* tab, const void* f_old, void* f_new,
-                         const void* tr_prev, void* tr_out, hipStream_t s) {
+                         const void* tr_prev, void* tr_out, const BndArgs& bnd, hipStream_t s) {
   const SweepTab<T>& t = *(const SweepTab<T>*)tab;
   int64_t maxthreads = 0;
   for (int k = 0; k < g.nv; ++k) {
@@ -1230,7 +1307,7 @@ hipError_t sweep_plain_t(const Geom& g, const void* tab, const void* f_old, void
 #define KDS_PLAIN(PP)                                                                          \
   case PP:                                                                                     \
     hipLaunchKernelGGL((k_sweep_plain<T, PP>), grid, dim3(256), 0, s, (const T*)f_old, (T*)f_new, \
-                       (const T*)tr_prev, (T*)tr_out, g, t);                                   \
+                       (const T*)tr_prev, (T*)tr_out, g, t, bnd_ref<T>(bnd));                  \
     break;
     KDS_PLAIN(1)
     KDS_PLAIN(2)
@@ -1245,7 +1322,8 @@ hipError_t sweep_plain_t(const Geom& g, const void* tab, const void* f_old, void
 
 template <typename T>
 hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, void* f,
-                        hipStream_t s) {
+                        const BndArgs& bnd, hipStream_t s) {
+  const BndRef<T> bd = bnd_ref<T>(bnd);
   const SweepTab<T>& t = *(const SweepTab<T>*)tab;
   const int64_t nblocks = plan.block_start[g.nv * g.m];
   const size_t lds = (size_t)plan.lds_elems * sizeof(T);
@@ -1254,7 +1332,7 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
 #define KDS_LINE(PP, DD)                                                                        \
   case PP * 10 + DD:                                                                            \
     hipLaunchKernelGGL((k_sweep_line<T, PP, DD>), dim3((unsigned)nblocks), dim3(plan.threads),  \
-                       lds, s, (T*)f, g, t, plan);                                              \
+                       lds, s, (T*)f, g, t, plan, bd);                                          \
     break;
     KDS_LINE(1, 1) KDS_LINE(2, 1) KDS_LINE(3, 1) KDS_LINE(4, 1)
     KDS_LINE(1, 2) KDS_LINE(2, 2) KDS_LINE(3, 2) KDS_LINE(4, 2)
@@ -1337,15 +1415,34 @@ hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag
 }
 
 hipError_t launch_sweep_plain(int prec, const Geom& g, const void* tab, const void* f_old,
-                              void* f_new, const void* tr_prev, void* tr_out, hipStream_t s) {
-  return prec == KDS_FP64 ? sweep_plain_t<double>(g, tab, f_old, f_new, tr_prev, tr_out, s)
-                          : sweep_plain_t<float>(g, tab, f_old, f_new, tr_prev, tr_out, s);
+                              void* f_new, const void* tr_prev, void* tr_out, const BndArgs& bnd,
+                              hipStream_t s) {
+  return prec == KDS_FP64 ? sweep_plain_t<double>(g, tab, f_old, f_new, tr_prev, tr_out, bnd, s)
+                          : sweep_plain_t<float>(g, tab, f_old, f_new, tr_prev, tr_out, bnd, s);
 }
 
 hipError_t launch_sweep_line(int prec, const Geom& g, const void* tab, const LinePlan& plan,
-                             void* f, hipStream_t s) {
-  return prec == KDS_FP64 ? sweep_line_t<double>(g, tab, plan, f, s)
-                          : sweep_line_t<float>(g, tab, plan, f, s);
+                             void* f, const BndArgs& bnd, hipStream_t s) {
+  return prec == KDS_FP64 ? sweep_line_t<double>(g, tab, plan, f, bnd, s)
+                          : sweep_line_t<float>(g, tab, plan, f, bnd, s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, T* __restrict__ dst,
+                                              int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy(int prec, const void* src, void* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (prec == KDS_FP64)
+    hipLaunchKernelGGL(k_copy<double>, dim3(blocks_for(n)), dim3(256), 0, s, (const double*)src,
+                       (double*)dst, n);
+  else
+    hipLaunchKernelGGL(k_copy<float>, dim3(blocks_for(n)), dim3(256), 0, s, (const float*)src,
+                       (float*)dst, n);
+  return hipGetLastError();
 }
 
 
@@ -1357,7 +1454,8 @@ size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp)
 
 hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontParams& fp,
                               const void* Wop, const int* lvl_start, const int* lvl_cells,
-                              const void* f_old, const void* f_prev, void* f_cur, hipStream_t s) {
+                              const void* f_old, const void* f_prev, void* f_cur,
+                              const BndArgs& bnd, hipStream_t s) {
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const dim3 grid((unsigned)(nsd * g.nv)), block(256);
   const size_t lds = front_lds_bytes(prec, mode, g, fp);
@@ -1365,14 +1463,14 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
     if (mode != kFrontFma) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_sweep_front<double, kFrontFma>), grid, block, lds, s, (const double*)f_old,
                        (const double*)f_prev, (double*)f_cur, g, fp, (const double*)Wop, lvl_start,
-                       lvl_cells);
+                       lvl_cells, bnd_ref<double>(bnd));
   } else {
     switch (mode) {
 #define KDS_FRONT(MODE)                                                                         \
   case MODE:                                                                                    \
     hipLaunchKernelGGL((k_sweep_front<float, MODE>), grid, block, lds, s, (const float*)f_old,  \
                        (const float*)f_prev, (float*)f_cur, g, fp, (const float*)Wop, lvl_start, \
-                       lvl_cells);                                                              \
+                       lvl_cells, bnd_ref<float>(bnd));                                         \
     break;
       KDS_FRONT(kFrontFma)
       KDS_FRONT(kFrontMfma)
@@ -1412,13 +1510,15 @@ size_t line_task_bytes(int prec) {
   return prec == KDS_FP64 ? sizeof(LineTask<double>) : sizeof(LineTask<float>);
 }
 
-void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl, void* out) {
+void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl,
+                    const BndArgs& bnd, void* out) {
   if (prec == KDS_FP64) {
     LineTask<double> t;
     t.f = (double*)f;
     t.g = g;
     std::memcpy(&t.tab, tab, sizeof(t.tab));
     t.pl = pl;
+    t.bd = bnd_ref<double>(bnd);
     std::memcpy(out, &t, sizeof(t));
   } else {
     LineTask<float> t;
@@ -1426,6 +1526,7 @@ void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const Lin
     t.g = g;
     std::memcpy(&t.tab, tab, sizeof(t.tab));
     t.pl = pl;
+    t.bd = bnd_ref<float>(bnd);
     std::memcpy(out, &t, sizeof(t));
   }
 }

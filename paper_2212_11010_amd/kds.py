@@ -26,7 +26,8 @@ PRECISIONS = {"fp64": KDS_FP64, "fp32": KDS_FP32, "fp32_split_f16": KDS_FP32_SPL
 SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED_LINE,
              "front": KDS_SCHED_FRONT}
 N_KERNEL_KINDS = 2
-EXPORTED = ["kds_create", "kds_set_state", "kds_step", "kds_step_timed", "kds_tune",
+EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_step_timed",
+            "kds_tune",
             "kds_time_kernels", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
@@ -79,6 +80,7 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.kds_create.argtypes = [C.POINTER(kds_config), vp, C.POINTER(vp)]
         L.kds_set_state.argtypes = [vp, vp, C.c_int32]
+        L.kds_set_boundary.argtypes = [vp, vp, C.c_int32]
         L.kds_step.argtypes = [vp, C.c_int32]
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_tune.argtypes = [vp, C.c_int32, dp]
@@ -199,6 +201,11 @@ def kds_create(spec, precision="fp32", schedule="auto", stream=None):
 def kds_set_state(h, W, nbytes):
     ptr, dev = _buf(W, nbytes)
     _check(lib().kds_set_state(h, ptr, dev), h)
+
+
+def kds_set_boundary(h, Wb, nbytes):
+    ptr, dev = _buf(Wb, nbytes)
+    _check(lib().kds_set_boundary(h, ptr, dev), h)
 
 
 def kds_step(h, n_steps=1):
@@ -326,6 +333,10 @@ class Problem:
         self.nn = (spec["degree"] + 1) ** d
         self.m = spec["m"]
         self.n_vel = spec["n_vel"]
+        per = list(spec.get("periodic", [1, 1, 1]))
+        P = spec["degree"] + 1
+        self.n_boundary = sum(2 * (self.ncell // spec["n_cells"][a]) * (self.nn // P)
+                              for a in range(d) if not per[a])
         if stream == "torch":
             stream = None
             try:
@@ -347,6 +358,10 @@ class Problem:
 
     def set_state(self, W):
         kds_set_state(self.h, W, self.ncell * self.nn * self.m * 8)
+
+    def set_boundary(self, Wb):
+        """Dirichlet data W_b [boundary node, m] for the end of the next step."""
+        kds_set_boundary(self.h, Wb, self.n_boundary * self.m * 8)
 
     def step(self, n=1):
         kds_step(self.h, n)

@@ -100,10 +100,14 @@ def test_create_rejects_subdomains_not_dividing(spec):
     assert st == kds.KDS_E_INVALID and "divide" in msg
 
 
-def test_create_rejects_non_periodic(spec):
-    s = dict(spec, periodic=[1, 0, 1])
+def test_create_rejects_bad_periodic_flag(spec):
+    s = dict(spec, periodic=[1, 2, 1])
     st, msg = _create_status(s)
-    assert st == kds.KDS_E_UNSUPPORTED
+    assert st == kds.KDS_E_INVALID and "periodic" in msg
+
+
+def test_set_boundary_rejects_null_problem():
+    assert kds.lib().kds_set_boundary(None, None, 0) == kds.KDS_E_INVALID
 
 
 @pytest.mark.parametrize("sched", ["line", "plain"])

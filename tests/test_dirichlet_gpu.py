@@ -1,0 +1,130 @@
+"""GPU parity with Dirichlet boundaries (axes with periodic = 0): the HIP path
+through the C ABI against the FP64 oracle, element by element, with boundary
+data that change every step (the start-of-step data are the previous call's,
+kds_set_boundary semantics), for the plain, line and front schedules.
+
+Tolerances as in the periodic parity tests: FP64 1e-12, FP32 1e-5 (front
+split precisions: FP16 1e-5, BF16 1e-4) relative to max |oracle|."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_split_f16": 1e-5, "fp32_split_bf16": 1e-4}
+
+CASES = {
+    # name: (cfg, overrides, schedules)
+    "cfg2_dir_x": (2, dict(n_cells=[32, 16], sub_cells=[8, 8], steps=4, periodic=[0, 1]),
+                   ("plain", "line")),
+    "cfg2_dir_xy": (2, dict(n_cells=[24, 32], sub_cells=[8, 8], steps=3, periodic=[0, 0]),
+                    ("plain", "line")),
+    "cfg2_dir_converged": (2, dict(n_cells=[32, 24], sub_cells=[8, 6], steps=3, n_iter=0,
+                                   periodic=[0, 0]), ("line",)),
+    "cfg1_dir_q1": (1, dict(n_cells=[34, 20], sub_cells=[34, 10], steps=4, periodic=[0, 0]),
+                    ("plain", "line")),
+    "cfg3_dir_xz": (3, dict(n_cells=[8, 6, 8], sub_cells=[4, 3, 4], steps=2, periodic=[0, 1, 0]),
+                    ("plain", "line")),
+    "maxwell_dir_x": (6, dict(n_cells=[8, 4, 4], sub_cells=[4, 4, 2], steps=3,
+                              periodic=[0, 1, 1]), ("front",)),
+    "maxwell_dir_all": (6, dict(n_cells=[6, 4, 4], sub_cells=[3, 2, 4], steps=2, degree=1,
+                                periodic=[0, 0, 0]), ("front",)),
+}
+
+
+def boundary_series(spec, W0, n):
+    """Boundary states B_0 .. B_n: the plane wave's exact values at t = s dt
+    for the Maxwell workload, else the initial trace scaled by (1 + 0.05 s)."""
+    from paper_2212_11010_amd import workloads as wl
+    if spec["cfg"] == 6:
+        return [wl.boundary_state(spec, t=s * spec["dt"]) for s in range(n + 1)]
+    B = wl.boundary_state(spec, W0)
+    return [B * (1.0 + 0.05 * s) for s in range(n + 1)]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    from oracle import oracle
+    from paper_2212_11010_amd import workloads as wl
+    cfg, ov, _ = CASES[name]
+    spec, W0 = wl.make_workload(cfg, **ov)
+    n = spec["steps"]
+    B = boundary_series(spec, W0, n)
+    c = oracle.Config(spec)
+    F = oracle.init(c, W0)
+    for s in range(n):
+        F = oracle.step(c, F, 1, threads=0, Wb_old=B[s], Wb_new=B[s + 1])
+    W = oracle.moments(c, F)
+    return spec, W0, B, np.ascontiguousarray(F.transpose(0, 2, 3, 1)), W
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+PARAMS = [(name, sched, prec) for name, (_, _, scheds) in CASES.items() for sched in scheds
+          for prec in (("fp64", "fp32", "fp32_split_f16", "fp32_split_bf16") if sched == "front"
+                       else ("fp64", "fp32"))]
+
+
+@pytest.mark.parametrize("name,sched,prec", PARAMS)
+def test_dirichlet_parity_against_oracle(name, sched, prec):
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, B, Fref, Wref = case(name)
+    print("case", name, sched, prec, spec["n_cells"], spec["periodic"], flush=True)
+    with kds.Problem(spec, precision=prec, schedule=sched) as pb:
+        assert pb.info()["schedule"] == {"plain": 1, "line": 2, "front": 3}[sched]
+        pb.set_state(torch.from_numpy(W0).cuda())
+        with pytest.raises(kds.KdsError) as e:
+            pb.step(1)   # boundary data missing
+        assert e.value.status == kds.KDS_E_STATE
+        pb.set_boundary(B[0])
+        for s in range(spec["steps"]):
+            # host data for even steps, device data for odd ones
+            pb.set_boundary(B[s + 1] if s % 2 == 0 else torch.from_numpy(B[s + 1]).cuda())
+            pb.step(1)
+        W, F = pb.moments(), pb.get_kinetic()
+    ew, ef = relerr(W, Wref), relerr(F, Fref)
+    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
+    assert ew <= TOL[prec] and ef <= TOL[prec], (ew, ef)
+
+
+def test_constant_boundary_multi_step_graph_matches_single_steps():
+    """kds_step(n) with constant data (captured multi-step graph) equals n
+    single steps, and the autotuner keeps the boundary data."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    spec, W0 = wl.make_workload(2, n_cells=[32, 32], sub_cells=[8, 8], periodic=[0, 0])
+    Wb = wl.boundary_state(spec, W0)
+    outs = []
+    for mode in ("graph", "single", "tuned"):
+        with kds.Problem(spec, precision="fp32", schedule="line") as pb:
+            pb.set_state(torch.from_numpy(W0).cuda())
+            pb.set_boundary(Wb)
+            if mode == "tuned":
+                pb.tune(2)
+            if mode == "single":
+                for _ in range(10):
+                    pb.step(1)
+            else:
+                pb.step(10)
+            outs.append(pb.get_kinetic())
+    assert np.array_equal(outs[0], outs[1])
+    assert relerr(outs[2], outs[0]) < 1e-5
+
+
+def test_set_boundary_rejected_on_periodic_box():
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    spec, W0 = wl.make_workload(2, n_cells=[16, 16], sub_cells=[8, 8])
+    with kds.Problem(spec, precision="fp32") as pb:
+        pb.set_state(torch.from_numpy(W0).cuda())
+        with pytest.raises(kds.KdsError) as e:
+            kds.kds_set_boundary(pb.h, np.zeros(3), 24)
+        assert e.value.status == kds.KDS_E_INVALID
