@@ -31,7 +31,9 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {"line": "k_sweep_line", "plain": "k_sweep_plain", "front": "k_sweep_front",
                 "relax": "k_relax"}
 MFMA_PEAK_TFS = {"fp32": 157.3, "fp32_split_f16": 2500.0, "fp32_split_bf16": 2500.0}
-KERNEL_SOURCES = ["paper_2212_11010_amd/csrc/kds_kernels.hip"]
+KERNEL_SOURCES = ["paper_2212_11010_amd/csrc/" + f for f in (
+    "kds_internal.h", "kds_device.h", "kds_line.h", "kds_line_f32.hip", "kds_line_f64.hip",
+    "kds_kernels.hip", "kds_front.hip")]
 
 
 def log(*a):

@@ -1,33 +1,54 @@
-"""Build libkds.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libkds.so (HIP, gfx950) in-tree with hipcc: every source compiled to
+an object in parallel (a temporary directory), then linked."""
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libkds.so")
-SOURCES = ["csrc/kds_setup.cpp", "csrc/kds_api.cpp", "csrc/kds_kernels.hip"]
+SOURCES = ["csrc/kds_setup.cpp", "csrc/kds_api.cpp", "csrc/kds_kernels.hip",
+           "csrc/kds_front.hip", "csrc/kds_line_f32.hip", "csrc/kds_line_f64.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp,
-           *[os.path.join(PKG, s) for s in SOURCES]]
+def _run(cmd, verbose):
     if verbose:
-        print(" ".join(cmd))
+        print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    tmpdir = tempfile.mkdtemp(prefix="kds_build_")
+    try:
+        objs, cmds = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append(["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", "-o", obj,
+                         os.path.join(PKG, src)])
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

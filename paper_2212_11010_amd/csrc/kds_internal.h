@@ -200,6 +200,23 @@ bool pack_relax_task(int law, int dim, int m, int nv, const void* eq, const void
 hipError_t launch_relax_batch(int prec, int law, int dim, int m, int nv, const void* tasks,
                               const int64_t* start, int ntask, int64_t nblocks, hipStream_t s);
 hipError_t line_kernels_allow_lds(size_t bytes);
+// per element type (kds_line_f32.hip, kds_line_f64.hip)
+hipError_t sweep_line_f32(const Geom& g, const void* tab, const LinePlan& plan, void* f,
+                          const BndArgs& bnd, hipStream_t s);
+hipError_t sweep_line_f64(const Geom& g, const void* tab, const LinePlan& plan, void* f,
+                          const BndArgs& bnd, hipStream_t s);
+hipError_t sweep_line_batch_f32(int P, int dim, const void* tasks, const int64_t* start, int ntask,
+                                int64_t nblocks, int threads, size_t lds_elems, hipStream_t s);
+hipError_t sweep_line_batch_f64(int P, int dim, const void* tasks, const int64_t* start, int ntask,
+                                int64_t nblocks, int threads, size_t lds_elems, hipStream_t s);
+hipError_t line_allow_lds_f32(size_t bytes);
+hipError_t line_allow_lds_f64(size_t bytes);
+size_t line_task_bytes_f32();
+size_t line_task_bytes_f64();
+void pack_line_task_f32(void* f, const Geom& g, const void* tab, const LinePlan& pl,
+                        const BndArgs& bnd, void* out);
+void pack_line_task_f64(void* f, const Geom& g, const void* tab, const LinePlan& pl,
+                        const BndArgs& bnd, void* out);
 size_t line_task_bytes(int prec);
 void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl,
                     const BndArgs& bnd, void* out);
