@@ -206,6 +206,7 @@ typedef struct {
   int32_t line_Q[3];      /* line schedule, per axis: cells per lane (0 for plain) */
   int32_t line_bw[3];     /* line schedule, per axis: columns of cells per workgroup */
   int32_t tuned;          /* 1 after kds_tune */
+  int32_t line_xdirect;   /* line schedule: x lines read / written straight to registers */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

@@ -246,6 +246,7 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
   pl.block_start[p->nv * p->m] = acc;
   pl.lds_elems = max_lds;
   pl.threads = threads;
+  pl.xdirect = 1;
   return threads <= 256 && acc <= 0x7fffffffLL;
 }
 
@@ -863,6 +864,16 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
         }
       }
   }
+  // x lines: the direct register path or the LDS tile, whichever is faster
+  if (ok && used[0]) {
+    LinePlan pl = p->plan;
+    pl.xdirect = 1 - pl.xdirect;
+    float ms = 0.0f;
+    if ((ok = time_plan(pl, &ms)) && ms < 0.97f * best) {
+      best = ms;
+      p->plan = pl;
+    }
+  }
   // restore the state and drop the graph captured with the old plan
   hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -1015,6 +1026,7 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
     info->line_bw[a] = p->sched == KDS_SCHED_LINE ? p->line_bw[a] : 0;
   }
   info->tuned = p->tuned ? 1 : 0;
+  info->line_xdirect = p->sched == KDS_SCHED_LINE ? p->plan.xdirect : 0;
   return KDS_OK;
 }
 

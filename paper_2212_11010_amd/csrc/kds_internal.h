@@ -98,6 +98,7 @@ struct LinePlan {
   int64_t block_start[kMaxVel * kMaxM + 1];  // prefix over (k, c) of bundles
   int lds_elems;           // max tile elements
   int threads;             // block size
+  int xdirect;             // x lines may bypass the LDS tile (cells per lane = QMAX)
 };
 
 // Dirichlet inflow data of the faces of non-periodic axes: kinetic values

@@ -219,6 +219,13 @@ __device__ __forceinline__ void copy_cols(T* __restrict__ f, T* tile, int64_t gb
     copy_cols_v<T, NN, 1, LOAD>(f, tile, gbase, rowstride, ncols, Na, CS);
 }
 
+// Widest vector (16 B at most) whose width divides n elements.
+template <typename T, int n>
+struct LineVec {
+  static constexpr int V16 = 16 / (int)sizeof(T);
+  static constexpr int VW = n % V16 == 0 ? V16 : (n % 2 == 0 ? 2 : 1);
+};
+
 template <int P, int DIM>
 struct ColShape {
   static constexpr int NN = P * (DIM > 1 ? P : 1) * (DIM > 2 ? P : 1);
@@ -258,6 +265,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
                                            const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
                                            T gg, T G, int K, const T* bo, const T* bn) {
   static_assert(NN == ColShape<P, DIM>::NN, "cell size");
+  const int Qn = ln.Q;  // cells per lane
   // Dirichlet axis: bo / bn point at this line's boundary values (inflow of
   // the first subdomain at the old / new time); nullptr on a periodic axis
   // (loaded where used: short live ranges; DIR = false compiles them out)
@@ -271,7 +279,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
     T lo = T(0);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q)
-      if (q == ln.Q - 1) lo = d[q][KDS_ND(o, P - 1)];
+      if (q == Qn - 1) lo = d[q][KDS_ND(o, P - 1)];
     last_old[o] = lo;
   }
 #pragma unroll
@@ -285,7 +293,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
     T to = t_old0[o], x = T(0);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      if (q < ln.Q) {
+      if (q < Qn) {
         T bq = e1[P - 1] * to;
 #pragma unroll
         for (int c = 0; c < P; ++c) bq += C[P - 1][c] * d[q][KDS_ND(o, c)];
@@ -300,7 +308,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
   }
   // segmented inclusive scan over the lanes of each subdomain
   {
-    T gw = powi(gg, ln.Q);
+    T gw = powi(gg, Qn);
     if (ln.dpp_ok) {
 #define KDS_SCAN_STEP(OFF)                                   \
   if ((OFF) < ln.Ls) {                                       \
@@ -377,7 +385,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
       for (int o = 0; o < PER; ++o) t_in[o] *= inv;
     }
   }
-  const T g0 = powi(gg, ln.sl * ln.Q);
+  const T g0 = powi(gg, ln.sl * Qn);
 #pragma unroll
   for (int o = 0; o < PER; ++o) {
     T x = ln.dpp_ok ? dpp_row_shr<T, 1>(mB[o]) : __shfl_up(mB[o], 1, 64);
@@ -385,7 +393,7 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
     T gp = g0, to = t_old0[o];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      if (q < ln.Q) {
+      if (q < Qn) {
         const T tn = x + gp * t_in[o];
         const T to_next = d[q][KDS_ND(o, P - 1)];
         T fn[P];
@@ -453,14 +461,21 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
   const int CS = Na * NN;  // LDS column stride
   const int64_t kc_base = (int64_t)kc * g.ncell * NN;
 
+  // x lines with QMAX cells per lane: each lane's cells are one contiguous,
+  // aligned block of QMAX * NN values, read and written straight from / to
+  // registers (no LDS tile, no barriers)
+  using LVT = typename VecT<T, LineVec<T, QMAX * NN>::VW>::type;
+  constexpr int LV = LineVec<T, QMAX * NN>::VW;
+  const bool direct = pl.xdirect && a == 0 && Q == QMAX && kc_base % LV == 0 && CS % LV == 0;
+  const int64_t col0 = a == 0 ? bundle * bw : 0;
+
   // ------------------------------------------------------------ bundle
   int ncols;
   if (a == 0) {
     const int64_t nrows = g.ncell / Na;
-    const int64_t col0 = bundle * bw;
     ncols = (int)min<int64_t>(bw, nrows - col0);
     // consecutive rows of cells are one contiguous block
-    copy_tile<T, true>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
+    if (!direct) copy_tile<T, true>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
   } else {
     const int nbx = (g.N[0] + bw - 1) / bw;
     const int bx = (int)(bundle % nbx);
@@ -472,7 +487,7 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
     const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
     copy_cols<T, NN, true>(f, tile, gbase, rowstride, ncols, Na, CS);
   }
-  __syncthreads();
+  if (!direct) __syncthreads();
 
   // ----------------------------------------------------------- compute
   T C[P][P], e1[P], eth[P];
@@ -537,11 +552,27 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
     // (lanes without a line and cells past Q re-read cell 0 of the column;
     // those values are never used)
     T d[QMAX][NN];
+    // direct: my block starts at cell j0 (downwind = physical order) or at
+    // Na - j0 - QMAX (reversed); lanes without a line read column 0
+    const int64_t dbase = kc_base + (col0 + (act ? c : 0)) * CS +
+                          (int64_t)(act ? (sg > 0 ? j0 : Na - j0 - QMAX) : 0) * NN;
+    if (direct) {
+      LVT v[QMAX * NN / LV];
+      const LVT* src = reinterpret_cast<const LVT*>(f + dbase);
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
+      for (int i = 0; i < QMAX * NN / LV; ++i) v[i] = src[i];
+      const T* vs = reinterpret_cast<const T*>(v);
 #pragma unroll
-      for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+      for (int q = 0; q < QMAX; ++q)
+#pragma unroll
+        for (int n = 0; n < NN; ++n) d[q][n] = vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n];
+    } else {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
+#pragma unroll
+        for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+      }
     }
     switch (a * 2 + (sg > 0 ? 1 : 0)) {
       case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
@@ -551,7 +582,17 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
       case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
       default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
     }
-    if (act) {
+    if (act && direct) {
+      LVT v[QMAX * NN / LV];
+      T* vs = reinterpret_cast<T*>(v);
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q)
+#pragma unroll
+        for (int n = 0; n < NN; ++n) vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n] = d[q][n];
+      LVT* dst = reinterpret_cast<LVT*>(f + dbase);
+#pragma unroll
+      for (int i = 0; i < QMAX * NN / LV; ++i) dst[i] = v[i];
+    } else if (act) {
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
         if (q < Q) {
@@ -562,11 +603,11 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
       }
     }
   }
+  if (direct) return;
   __syncthreads();
 
   // -------------------------------------------------------- write back
   if (a == 0) {
-    const int64_t col0 = bundle * bw;
     copy_tile<T, false>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
   } else {
     const int nbx = (g.N[0] + bw - 1) / bw;
