@@ -246,7 +246,7 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
   pl.block_start[p->nv * p->m] = acc;
   pl.lds_elems = max_lds;
   pl.threads = threads;
-  pl.xdirect = 1;
+  pl.xdirect = 0;  // the autotuner switches it on where it is faster
   return threads <= 256 && acc <= 0x7fffffffLL;
 }
 
@@ -864,13 +864,15 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
         }
       }
   }
-  // x lines: the direct register path or the LDS tile, whichever is faster
+  // x lines: the direct register path where it is clearly faster than the
+  // LDS tile (both timed again, back to back)
   if (ok && used[0]) {
     LinePlan pl = p->plan;
-    pl.xdirect = 1 - pl.xdirect;
-    float ms = 0.0f;
-    if ((ok = time_plan(pl, &ms)) && ms < 0.97f * best) {
-      best = ms;
+    pl.xdirect = 1;
+    float ms_tile = 0.0f, ms_direct = 0.0f;
+    ok = time_plan(p->plan, &ms_tile) && time_plan(pl, &ms_direct);
+    if (ok && ms_direct < 0.97f * ms_tile) {
+      best = ms_direct;
       p->plan = pl;
     }
   }
