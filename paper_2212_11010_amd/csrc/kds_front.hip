@@ -24,6 +24,7 @@ namespace kds {
 // the FP16 low parts are scaled by 2^11 against underflow).
 
 constexpr int kFrontMaxChunk = 64;  // GEMM columns per pass (col_chunk)
+constexpr int kFrontMaxKpad = 112;  // operator columns nn + 3 nf (p = 3, d = 3), padded to 16
 
 typedef float kds_f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 kds_f16x4 __attribute__((ext_vector_type(4)));
@@ -37,7 +38,9 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __uint_as_float(((unsigned int)h) << 16);
 }
 
-template <typename T, int MODE>
+// KP: upper bound of the padded operator width Kpad (64 covers p <= 2 in 3-D,
+// kFrontMaxKpad the rest), sizing the register-resident operator slice.
+template <typename T, int MODE, int KP>
 __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old,
                                                      const T* __restrict__ f_prev,
                                                      T* __restrict__ f_cur, Geom g, FrontParams fp,
@@ -51,8 +54,7 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
   const int Kpad = (Kd + 15) & ~15;
   const int CH = fp.col_chunk;
   const int XS = CH + 1;  // odd row stride: conflict-free gathers
-  T* Wt = reinterpret_cast<T*>(smem_raw);            // [Mpad][Kpad] (matrix-core modes)
-  T* X = Wt + (MODE == kFrontFma ? 0 : Mpad * Kpad);  // [Kpad][XS]
+  T* X = reinterpret_cast<T*>(smem_raw);  // [Kpad][XS]
   __shared__ int64_t col_base[kFrontMaxChunk];         // per column: state offset of the cell
   __shared__ int64_t col_nb[3][kFrontMaxChunk];        // ... of the upwind neighbour per face
   __shared__ unsigned char col_int[3][kFrontMaxChunk]; // 1: neighbour inside the subdomain,
@@ -65,11 +67,48 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
   const int tid = threadIdx.x, bs = blockDim.x;
   const T th = (T)fp.theta;
   const T* Wk = Wop + (int64_t)k * nn * Kd;
-  if (MODE != kFrontFma) {
-    for (int e = tid; e < Mpad * Kpad; e += bs) {
-      const int i = e / Kpad, r = e - i * Kpad;
-      Wt[e] = (i < nn && r < Kd) ? Wk[i * Kd + r] : T(0);
-    }
+  // rows Kd..Kpad-1 of X stay zero (padding of the K dimension)
+  for (int e = tid; e < Kpad * XS; e += bs) X[e] = T(0);
+
+  // Matrix-core modes: a wave always computes the same 16-row tile of Y
+  // (4 waves, Mpad / 16 in {1, 2, 4} row tiles), so its slice of the
+  // operator W stays in registers for the whole kernel: per K step of the
+  // 16x16x4 FP32 product one value, per step of the 16x16x16 split products
+  // four values as hi / lo halves.
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt_n = Mpad / 16;
+  const int i0 = (wave % mt_n) * 16;
+  constexpr int KS4 = KP / 4, KS16 = KP / 16;
+  float afr[MODE == kFrontMfma ? KS4 : 1];
+  kds_f16x4 ah16[MODE == kFrontSplitF16 ? KS16 : 1], al16[MODE == kFrontSplitF16 ? KS16 : 1];
+  kds_i16x4 ahb[MODE == kFrontSplitBf16 ? KS16 : 1], alb[MODE == kFrontSplitBf16 ? KS16 : 1];
+  auto wval = [&](int i, int r) -> float {
+    return (i < nn && r < Kd) ? (float)Wk[i * Kd + r] : 0.0f;
+  };
+  if constexpr (MODE == kFrontMfma) {
+#pragma unroll
+    for (int st = 0; st < KS4; ++st) afr[st] = 4 * st < Kpad ? wval(i0 + li, 4 * st + lk) : 0.0f;
+  } else if constexpr (MODE == kFrontSplitF16) {
+#pragma unroll
+    for (int st = 0; st < KS16; ++st)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float w = 16 * st < Kpad ? wval(i0 + li, 16 * st + 4 * lk + u) : 0.0f;
+        const _Float16 h = (_Float16)w;
+        ah16[st][u] = h;
+        al16[st][u] = (_Float16)((w - (float)h) * 2048.0f);
+      }
+  } else if constexpr (MODE == kFrontSplitBf16) {
+#pragma unroll
+    for (int st = 0; st < KS16; ++st)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float w = 16 * st < Kpad ? wval(i0 + li, 16 * st + 4 * lk + u) : 0.0f;
+        const unsigned short h = bf16_rne(w);
+        ahb[st][u] = (short)h;
+        alb[st][u] = (short)bf16_rne(w - bf16_to_f32(h));
+      }
   }
   int sgn[3], outn[3];
   for (int a = 0; a < 3; ++a) {
@@ -93,6 +132,17 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
     face_node[t] = a < g.dim ? node : 0;
   }
   __syncthreads();
+
+  // Gather: thread tid owns row r = tid % Kpad of X (a node of the cell, or
+  // a node of one inflow face) for the whole kernel, and the columns
+  // jr, jr + rstep, ...; everything about its row is decoded once.
+  const int rstep = bs / Kpad;
+  const int r = tid % Kpad, jr = tid / Kpad;
+  const bool row_on = jr < rstep;
+  const bool row_cell = r < nn;
+  const int row_face = (row_cell || r >= Kd) ? -1 : (r - nn) / nf;
+  const int row_q = row_face >= 0 ? r - nn - row_face * nf : 0;
+  const int row_node = row_face >= 0 ? face_node[r - nn] : 0;
 
   for (int lev = 0; lev < nlev; ++lev) {
     const int c0 = lvl_start[fp.lvl_off[k] + lev];
@@ -142,55 +192,52 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
         }
       }
       __syncthreads();
-      // ---- gather X[r][jj] (r fastest over threads: contiguous nodes); U
-      // independent loads per thread are issued before any is used
-      {
+      // ---- gather X[r][jj]: U independent loads per thread in flight
+      if (row_on) {
         constexpr int U = 4;
-        const int total = Kpad * CH;
-        for (int e0 = tid; e0 < total; e0 += U * bs) {
+        for (int jb0 = jr; jb0 < CH; jb0 += U * rstep) {
           T vo[U], vn[U];
-          int rr[U], jq[U];
-          int face[U];
-          bool isb[U];
+          int kind[U];  // -2: zero, -1: cell node, else the inflow face
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * bs;
-            const int jj = e / Kpad, r = e - jj * Kpad;
-            rr[u] = r;
-            jq[u] = jj;
+            const int jj = jb0 + u * rstep;
             int64_t at = 0;
-            int fa = -1;
-            bool live = e < total && jj < nc && r < Kd;
-            if (live) {
-              if (r < nn) {
+            int kd = -2;
+            const T* po = f_old;
+            const T* pn = f_prev;
+            if (jj < nc && r < Kd) {
+              if (row_cell) {
                 at = col_base[jj] + r;
+                kd = -1;
               } else {
-                const int a = (r - nn) / nf;
-                if (col_nb[a][jj] >= 0) {
-                  fa = a;
-                  // boundary values are numbered by face node (row q of face a)
-                  at = col_nb[a][jj] +
-                       (col_int[a][jj] == 2 ? (r - nn - a * nf) : face_node[r - nn]);
-                } else {
-                  live = false;
+                const int64_t nbo = col_nb[row_face][jj];
+                if (nbo >= 0) {
+                  const int ci = col_int[row_face][jj];
+                  // boundary values are numbered by face node (row q of the face)
+                  at = nbo + (ci == 2 ? row_q : row_node);
+                  kd = row_face;
+                  if (ci == 2) {
+                    po = bd.old;
+                    pn = bd.neu;
+                  } else if (ci == 1) {
+                    pn = f_cur;
+                  }
                 }
               }
             }
-            face[u] = live ? fa : -2;
-            isb[u] = live && fa >= 0 && col_int[fa][jj] == 2;
+            kind[u] = kd;
             // inactive slots re-read element 0 of the state (never used)
-            vo[u] = isb[u] ? bd.old[at] : f_old[live ? at : 0];
-            vn[u] = isb[u] ? bd.neu[at]
-                           : ((fa >= 0 && col_int[fa][jj]) ? f_cur[at] : f_prev[fa >= 0 ? at : 0]);
+            vo[u] = po[at];
+            vn[u] = pn[kd >= 0 ? at : 0];
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * bs;
-            if (e < total) {
+            const int jj = jb0 + u * rstep;
+            if (jj < CH) {
               T v = T(0);
-              if (face[u] == -1) v = vo[u];
-              else if (face[u] >= 0) v = th * vn[u] + (T(1) - th) * vo[u];
-              X[rr[u] * XS + jq[u]] = v;
+              if (kind[u] == -1) v = vo[u];
+              else if (kind[u] >= 0) v = th * vn[u] + (T(1) - th) * vo[u];
+              X[r * XS + jj] = v;
             }
           }
         }
@@ -206,54 +253,46 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
           store(i, jj, acc);
         }
       } else {
-        const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-        const int li = lane & 15, lk = lane >> 4;
-        const int mt_n = Mpad / 16, nt_n = (nc + 15) / 16;
+        const int nt_n = (nc + 15) / 16;
         for (int t = wave; t < mt_n * nt_n; t += nw) {
-          const int mt = t % mt_n, nt = t / mt_n;
-          const int i0 = mt * 16, jb = nt * 16;
+          const int jb = (t / mt_n) * 16;  // (t % mt_n = wave % mt_n: this wave's row tile)
           kds_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
           if constexpr (MODE == kFrontMfma) {
-            for (int kk = 0; kk < Kpad; kk += 4) {
-              const float av = (float)Wt[(i0 + li) * Kpad + kk + lk];
-              const float bv = (float)X[(kk + lk) * XS + jb + li];
-              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-            }
+#pragma unroll
+            for (int st = 0; st < KS4; ++st)
+              if (4 * st < Kpad)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[st], (float)X[(4 * st + lk) * XS + jb + li],
+                                                           acc, 0, 0, 0);
           } else {
             kds_f32x4 cor = {0.f, 0.f, 0.f, 0.f};
-            for (int kk = 0; kk < Kpad; kk += 16) {
-              float aw[4], bw[4];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                aw[u] = (float)Wt[(i0 + li) * Kpad + kk + 4 * lk + u];
-                bw[u] = (float)X[(kk + 4 * lk + u) * XS + jb + li];
-              }
+            for (int st = 0; st < KS16; ++st) {
+              if (16 * st >= Kpad) continue;
+              float bw[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) bw[u] = (float)X[(16 * st + 4 * lk + u) * XS + jb + li];
               if constexpr (MODE == kFrontSplitF16) {
-                kds_f16x4 ah, al, bh, bl;
+                kds_f16x4 bh, bl;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                  const _Float16 ha = (_Float16)aw[u], hb = (_Float16)bw[u];
-                  ah[u] = ha;
+                  const _Float16 hb = (_Float16)bw[u];
                   bh[u] = hb;
-                  al[u] = (_Float16)((aw[u] - (float)ha) * 2048.0f);
                   bl[u] = (_Float16)((bw[u] - (float)hb) * 2048.0f);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc, 0, 0, 0);
-                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, cor, 0, 0, 0);
-                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, cor, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah16[st], bh, acc, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(ah16[st], bl, cor, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16f16(al16[st], bh, cor, 0, 0, 0);
               } else {
-                kds_i16x4 ah, al, bh, bl;
+                kds_i16x4 bh, bl;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                  const unsigned short ha = bf16_rne(aw[u]), hb = bf16_rne(bw[u]);
-                  ah[u] = (short)ha;
+                  const unsigned short hb = bf16_rne(bw[u]);
                   bh[u] = (short)hb;
-                  al[u] = (short)bf16_rne(aw[u] - bf16_to_f32(ha));
                   bl[u] = (short)bf16_rne(bw[u] - bf16_to_f32(hb));
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, cor, 0, 0, 0);
-                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, cor, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahb[st], bh, acc, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahb[st], bl, cor, 0, 0, 0);
+                cor = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alb[st], bh, cor, 0, 0, 0);
               }
             }
             const float sc = MODE == kFrontSplitF16 ? 1.0f / 2048.0f : 1.0f;
@@ -275,7 +314,9 @@ __global__ __launch_bounds__(256) void k_sweep_front(const T* __restrict__ f_old
 size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp) {
   const int Mpad = (g.nn + 15) & ~15, Kpad = (fp.Kd + 15) & ~15;
   const size_t el = prec == KDS_FP64 ? 8 : 4;
-  return ((mode == kFrontFma ? 0 : (size_t)Mpad * Kpad) + (size_t)Kpad * (fp.col_chunk + 1)) * el;
+  (void)mode;
+  (void)Mpad;
+  return (size_t)Kpad * (fp.col_chunk + 1) * el;
 }
 
 hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontParams& fp,
@@ -285,18 +326,25 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const dim3 grid((unsigned)(nsd * g.nv)), block(256);
   const size_t lds = front_lds_bytes(prec, mode, g, fp);
+  const int Kpad = (fp.Kd + 15) & ~15;
+  if (Kpad > kFrontMaxKpad) return hipErrorInvalidValue;
   if (prec == KDS_FP64) {
     if (mode != kFrontFma) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sweep_front<double, kFrontFma>), grid, block, lds, s, (const double*)f_old,
+    hipLaunchKernelGGL((k_sweep_front<double, kFrontFma, kFrontMaxKpad>), grid, block, lds, s, (const double*)f_old,
                        (const double*)f_prev, (double*)f_cur, g, fp, (const double*)Wop, lvl_start,
                        lvl_cells, bnd_ref<double>(bnd));
   } else {
     switch (mode) {
 #define KDS_FRONT(MODE)                                                                         \
   case MODE:                                                                                    \
-    hipLaunchKernelGGL((k_sweep_front<float, MODE>), grid, block, lds, s, (const float*)f_old,  \
-                       (const float*)f_prev, (float*)f_cur, g, fp, (const float*)Wop, lvl_start, \
-                       lvl_cells, bnd_ref<float>(bnd));                                         \
+    if (Kpad <= 64)                                                                             \
+      hipLaunchKernelGGL((k_sweep_front<float, MODE, 64>), grid, block, lds, s, (const float*)f_old, \
+                         (const float*)f_prev, (float*)f_cur, g, fp, (const float*)Wop, lvl_start, \
+                         lvl_cells, bnd_ref<float>(bnd));                                       \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_sweep_front<float, MODE, kFrontMaxKpad>), grid, block, lds, s,       \
+                         (const float*)f_old, (const float*)f_prev, (float*)f_cur, g, fp,       \
+                         (const float*)Wop, lvl_start, lvl_cells, bnd_ref<float>(bnd));         \
     break;
       KDS_FRONT(kFrontFma)
       KDS_FRONT(kFrontMfma)
