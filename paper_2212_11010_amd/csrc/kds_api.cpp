@@ -29,6 +29,7 @@ struct kds_problem {
   Geom geom{};
   // host tables
   std::vector<unsigned char> eq_blob;
+  void* eq_dev = nullptr;             // device copy of eq_blob (read by the relaxation)
   std::vector<unsigned char> sweep_blob;  // SweepTab<T>
   LinePlan plan{};
   int line_Q[3] = {1, 1, 1}, line_bw[3] = {1, 1, 1};  // per-axis line-schedule choices
@@ -364,7 +365,8 @@ void free_device(kds_problem* p) {
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
-                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1], p->fb, p->Wb_dev};
+                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1], p->fb, p->Wb_dev,
+                  p->eq_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
@@ -372,6 +374,7 @@ void free_device(kds_problem* p) {
   p->front_lvl_start = p->front_lvl_cells = nullptr;
   p->fb = nullptr;
   p->Wb_dev = nullptr;
+  p->eq_dev = nullptr;
   p->stage = nullptr;
   p->flag = nullptr;
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
@@ -392,11 +395,11 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
                                     p->fit[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->fit[p->K & 1], p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->fit[p->K & 1], p->f, s));
   } else if (p->sched == KDS_SCHED_LINE) {
     KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->bnd(), s));
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, s));
   } else {
     for (int it = 1; it <= p->K; ++it) {
       const void* tr_prev = it == 1 ? nullptr : p->tr[(it - 1) & 1];
@@ -405,7 +408,7 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
                                     p->tr[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f_tmp, p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f_tmp, p->f, s));
   }
   // the boundary data at the end of this step are the start data of the next
   if (p->nbnd > 0) {
@@ -640,7 +643,11 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     if (ee != hipSuccess) { (void)hipGetLastError(); *ptr = nullptr; return false; }
     return true;
   };
-  bool ok = alloc(&p->f, state_bytes) && alloc((void**)&p->flag, sizeof(int));
+  bool ok = alloc(&p->f, state_bytes) && alloc((void**)&p->flag, sizeof(int)) &&
+            alloc(&p->eq_dev, p->eq_blob.size());
+  if (ok)
+    ok = hipMemcpy(p->eq_dev, p->eq_blob.data(), p->eq_blob.size(), hipMemcpyHostToDevice) ==
+         hipSuccess;
   if (ok && p->nbnd > 0)
     ok = alloc(&p->fb, 2 * (size_t)p->bnd_half() * p->elem) &&
          alloc((void**)&p->Wb_dev, (size_t)p->nbnd * p->m * sizeof(double));
@@ -917,7 +924,7 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
         return launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, p->f_tmp, nullptr,
                                   p->tr[0], p->bnd(), p->stream);
       }
-      return launch_relax(p->prec, p->law, g, p->eq_blob.data(), p->f, p->f, p->stream);
+      return launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, p->stream);
     };
     e = launch();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);

@@ -171,7 +171,8 @@ struct FrontParams {
 
 hipError_t launch_init(int prec, int law, const Geom& g, const void* eq, const double* W,
                        void* f, hipStream_t s);
-hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq, const void* fin,
+// eq_dev: a device copy of the equilibrium table (the blob of build_eq_blob)
+hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq_dev, const void* fin,
                         void* fout, hipStream_t s);
 hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s);
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s);

@@ -31,9 +31,8 @@ namespace kds {
 // M_k(W) = a_k W + sum_i b_{k,i} Q^i(W) (moment conditions, eq:maxwell_def),
 // evaluated in FP64.
 template <int LAW, int D, int M, int NV>
-__device__ __forceinline__ void equilibrium(const EqTab<D, M, NV>& t, const double (&W)[M],
-                                            double (&Mk)[NV][M]) {
-  double Q[D][M];
+__device__ __forceinline__ void flux(const EqTab<D, M, NV>& t, const double (&W)[M],
+                                     double (&Q)[D][M]) {
   if constexpr (LAW == KDS_LAW_LINEAR) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -64,15 +63,27 @@ __device__ __forceinline__ void equilibrium(const EqTab<D, M, NV>& t, const doub
       Q[i][D + 1] = (E + pr) * u[i];
     }
   }
+}
+
+// Component r of M_k from W and Q(W).
+template <int D, int M, int NV>
+__device__ __forceinline__ double eq_comp(const EqTab<D, M, NV>& t, const double (&W)[M],
+                                          const double (&Q)[D][M], int k, int r) {
+  double s = t.a[k] * W[r];
+#pragma unroll
+  for (int i = 0; i < D; ++i) s += t.b[k][i] * Q[i][r];
+  return s;
+}
+
+template <int LAW, int D, int M, int NV>
+__device__ __forceinline__ void equilibrium(const EqTab<D, M, NV>& t, const double (&W)[M],
+                                            double (&Mk)[NV][M]) {
+  double Q[D][M];
+  flux<LAW, D, M, NV>(t, W, Q);
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-      double s = t.a[k] * W[r];
-#pragma unroll
-      for (int i = 0; i < D; ++i) s += t.b[k][i] * Q[i][r];
-      Mk[k][r] = s;
-    }
+    for (int r = 0; r < M; ++r) Mk[k][r] = eq_comp(t, W, Q, k, r);
 }
 
 // ===================================================== pointwise kernels
@@ -99,46 +110,58 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ W, T* _
 template <typename T, int LAW, int D, int M, int NV>
 __device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
                                            const EqTab<D, M, NV>& t, int64_t i) {
-  double fv[NV][M];
+  // the kinetic values stay in their storage type until used (registers);
+  // W, Q(W) and every M_k component in FP64, one rounding per output
+  T fr[NV][M];
   double w[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) w[r] = 0.0;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-      fv[k][r] = (double)fin[(int64_t)(k * M + r) * plane + i];
-      w[r] += fv[k][r];
-    }
-  double Mk[NV][M];
-  if (t.has_source) {
-    // Crank-Nicolson source step on W; the kinetic data take the equilibrium
-    // part of the change so that sum_k f_k = W+ before relaxing towards M(W+)
-    double Mm[NV][M];
-    equilibrium<LAW, D, M, NV>(t, w, Mm);
-#pragma unroll
-    for (int r = 0; r < M; ++r) w[r] *= t.mu[r];
-    equilibrium<LAW, D, M, NV>(t, w, Mk);
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-      for (int r = 0; r < M; ++r) fv[k][r] += Mk[k][r] - Mm[k][r];
-  } else {
-    equilibrium<LAW, D, M, NV>(t, w, Mk);
-  }
+    for (int r = 0; r < M; ++r) fr[k][r] = fin[(int64_t)(k * M + r) * plane + i];
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int r = 0; r < M; ++r)
-      fout[(int64_t)(k * M + r) * plane + i] = (T)(fv[k][r] + t.omega * (Mk[k][r] - fv[k][r]));
+    for (int r = 0; r < M; ++r) w[r] += (double)fr[k][r];
+  double Q[D][M];
+  if (t.has_source) {
+    // Crank-Nicolson source step on W; the kinetic data take the equilibrium
+    // part of the change so that sum_k f_k = W+ before relaxing towards M(W+)
+    double Qm[D][M], wp[M];
+    flux<LAW, D, M, NV>(t, w, Qm);
+#pragma unroll
+    for (int r = 0; r < M; ++r) wp[r] = w[r] * t.mu[r];
+    flux<LAW, D, M, NV>(t, wp, Q);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double mk = eq_comp(t, wp, Q, k, r);
+        const double f = (double)fr[k][r] + (mk - eq_comp(t, w, Qm, k, r));
+        fout[(int64_t)(k * M + r) * plane + i] = (T)(f + t.omega * (mk - f));
+      }
+  } else {
+    flux<LAW, D, M, NV>(t, w, Q);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double mk = eq_comp(t, w, Q, k, r);
+        const double f = (double)fr[k][r];
+        fout[(int64_t)(k * M + r) * plane + i] = (T)(f + t.omega * (mk - f));
+      }
+  }
 }
 
 template <typename T, int LAW, int D, int M, int NV>
+// (the table is read from device memory where it is used: as a kernel
+// argument its FP64 coefficients would be held in registers throughout)
 __global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t plane,
-                                               EqTab<D, M, NV> t) {
+                                               const EqTab<D, M, NV>* __restrict__ t) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= plane) return;
-  relax_node<T, LAW, D, M, NV>(fin, fout, plane, t, i);
+  relax_node<T, LAW, D, M, NV>(fin, fout, plane, *t, i);
 }
 
 // Relaxation of many problems of one (law, d, m, n_vel) in one launch; the
@@ -357,7 +380,7 @@ struct EqCombo {
   static hipError_t relax(const Geom& g, const void* eq, const void* fin, void* fout, hipStream_t s) {
     const int64_t plane = g.ncell * g.nn;
     hipLaunchKernelGGL((k_relax<T, LAW, D, M, NV>), dim3(blocks_for(plane)), dim3(256), 0, s,
-                       (const T*)fin, (T*)fout, plane, *(const Tab*)eq);
+                       (const T*)fin, (T*)fout, plane, (const Tab*)eq);
     return hipGetLastError();
   }
 };
