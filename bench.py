@@ -58,6 +58,25 @@ def workload(name, cells=0, sub=0):
     return wl.make_workload(cfg, **kw)
 
 
+def device_copy_gbs(nbytes=1 << 30, reps=10):
+    """Practical streaming reference: torch device-to-device copy of nbytes,
+    timed with events (read + written bytes per second)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def time_problem(spec, W0, prec, sched, steps, warmup, tune=False):
     import torch
     from paper_2212_11010_amd import kds
@@ -350,6 +369,7 @@ def main():
             "kernel": kname, "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": dur_s * 1e3}
 
+    roof["device_copy_gbs"] = device_copy_gbs()  # context: what a plain copy reaches
     if sched == "front":
         # dense cell solves: 2 Kd flop per unknown per launch (one subdomain
         # iteration), Kd = nn + 3 nf; the split forms execute three products
