@@ -253,7 +253,7 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
 
 // Line schedule plan from the heuristic choices.
 bool plan_lines(kds_problem* p, std::string& why) {
-  if (line_qmax((int)p->elem, p->nn) * p->nn * (int)p->elem > 512) {
+  if (line_qmax((int)p->elem, p->nn) * line_cell_values(p->nn) * (int)p->elem > 512) {
     why = "line schedule: the cells of one lane do not fit the register budget";
     return false;
   }
@@ -597,9 +597,11 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED, why);
   }
-  // AUTO keeps the plain schedule where a lane would hold more than 64 state
-  // values (64-node cells): the line kernel's occupancy is too low there.
-  const bool line_preferred = line_qmax((int)p->elem, p->nn) * p->nn <= 64;
+  // AUTO keeps the plain schedule for 64-node cells: there the line kernel
+  // solves one group of node lines at a time out of the LDS tile, and
+  // measures slower than the plain sweep (96^3 Euler, p = 3: 8.1 ms against
+  // 3 x 2.0 ms per step).
+  const bool line_preferred = !line_grouped(p->nn);
   p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok ||
               (cfg->schedule == KDS_SCHED_AUTO && !line_preferred && p->K > 0))
                  ? KDS_SCHED_PLAIN

@@ -84,10 +84,17 @@ struct EqTab {
   int has_source;
 };
 
+// Cells of 64 nodes (p = 3 in 3-D) are solved one group of node lines at a
+// time from the LDS tile (16 values per cell in registers).
+__host__ __device__ constexpr bool line_grouped(int nn) { return nn > 27; }
+
+// State values per cell a lane holds in registers at once.
+__host__ __device__ constexpr int line_cell_values(int nn) { return line_grouped(nn) ? 16 : nn; }
+
 // Most cells per lane the line kernel keeps in registers (a budget of 64
-// state values per lane; nn = nodes per cell).
+// state values per lane).
 __host__ __device__ constexpr int line_qmax(int elem_bytes, int nn) {
-  return (void)elem_bytes, 64 / nn >= 8 ? 8 : 64 / nn >= 4 ? 4 : 2;
+  return (void)elem_bytes, 64 / line_cell_values(nn) >= 8 ? 8 : 64 / line_cell_values(nn) >= 4 ? 4 : 2;
 }
 
 // Line-schedule launch plan (per velocity).

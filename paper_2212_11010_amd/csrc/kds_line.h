@@ -259,19 +259,24 @@ struct LineLane {
 // One lane's part of the line solve.  d[q][node]: my Q cells in downwind
 // order (node indices physical); updated in place to the new state.
 // Lines O0 .. O0+PER-1 of the cells (groups keep the live registers small).
+// d[q][.]: either all NN nodes of my cells (COMPACT = false, physical node
+// offsets) or only the PER lines of this group, [line][physical index along
+// the axis] (COMPACT = true, NN = PER * P).
 template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0, int PER,
-          bool DIR>
+          bool DIR, bool COMPACT = false>
 __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
                                            const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
                                            T gg, T G, int K, const T* bo, const T* bn) {
-  static_assert(NN == ColShape<P, DIM>::NN, "cell size");
+  static_assert(COMPACT ? NN == PER * P : NN == ColShape<P, DIM>::NN, "cell size");
   const int Qn = ln.Q;  // cells per lane
   // Dirichlet axis: bo / bn point at this line's boundary values (inflow of
   // the first subdomain at the old / new time); nullptr on a periodic axis
   // (loaded where used: short live ranges; DIR = false compiles them out)
   const bool dir = DIR && bo != nullptr;
   // physical node of downwind node b along the axis, line O0 + o
-#define KDS_ND(o, b) node_of<P, DIM, AXIS>(O0 + (o), SIGN > 0 ? (b) : P - 1 - (b))
+#define KDS_ND(o, b)                                                         \
+  (COMPACT ? (o) * P + (SIGN > 0 ? (b) : P - 1 - (b))                        \
+           : node_of<P, DIM, AXIS>(O0 + (o), SIGN > 0 ? (b) : P - 1 - (b)))
   T last_old[PER], t_old0[PER], mB[PER];
   T beta[PER][QMAX];
 #pragma unroll
@@ -428,6 +433,44 @@ __device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
   }
 }
 
+// Cells of 64 nodes (p = 3 in 3-D): the lane's cells stay in the LDS tile and
+// each group of lines is brought into registers, solved and written back in
+// turn (registers for one group of lines instead of all 64 nodes).
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, bool DIR, int O0 = 0>
+__device__ __forceinline__ void line_lanes_tile(T* tile, int cbase, const int (&rows)[QMAX],
+                                                bool act, const LineLane& ln,
+                                                const T (&C)[P][P], const T (&e1)[P],
+                                                const T (&eth)[P], T gg, T G, int K, const T* bo,
+                                                const T* bn) {
+  constexpr int ALL = ColShape<P, DIM>::PER;
+  constexpr int GS = ALL <= 4 ? ALL : (ALL % 3 == 0 ? 3 : 4);
+  if constexpr (O0 < ALL) {
+    constexpr int n = ALL - O0 < GS ? ALL - O0 : GS;
+    T dg[QMAX][n * P];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+#pragma unroll
+      for (int o = 0; o < n; ++o)
+#pragma unroll
+        for (int b = 0; b < P; ++b)
+          dg[q][o * P + b] = tile[cbase + rows[q] * NN + node_of<P, DIM, AXIS>(O0 + o, b)];
+    line_group<T, P, DIM, AXIS, SIGN, QMAX, n * P, O0, n, DIR, true>(dg, ln, C, e1, eth, gg, G, K,
+                                                                     bo, bn);
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q)
+        if (q < ln.Q)
+#pragma unroll
+          for (int o = 0; o < n; ++o)
+#pragma unroll
+            for (int b = 0; b < P; ++b)
+              tile[cbase + rows[q] * NN + node_of<P, DIM, AXIS>(O0 + o, b)] = dg[q][o * P + b];
+    }
+    line_lanes_tile<T, P, DIM, AXIS, SIGN, QMAX, NN, DIR, O0 + n>(tile, cbase, rows, act, ln, C, e1,
+                                                                  eth, gg, G, K, bo, bn);
+  }
+}
+
 // Workgroups are dealt round-robin to the XCDs; give each XCD a contiguous
 // range of the nb work items so that neighbouring bundles, which share cache
 // lines at their edges, meet in the same L2.
@@ -466,7 +509,9 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
   // registers (no LDS tile, no barriers)
   using LVT = typename VecT<T, LineVec<T, QMAX * NN>::VW>::type;
   constexpr int LV = LineVec<T, QMAX * NN>::VW;
-  const bool direct = pl.xdirect && a == 0 && Q == QMAX && kc_base % LV == 0 && CS % LV == 0;
+  constexpr bool GROUPED = line_grouped(NN);
+  const bool direct = !GROUPED && pl.xdirect && a == 0 && Q == QMAX && kc_base % LV == 0 &&
+                      CS % LV == 0;
   const int64_t col0 = a == 0 ? bundle * bw : 0;
 
   // ------------------------------------------------------------ bundle
@@ -551,54 +596,70 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
     const int cbase = (act ? c : 0) * CS;
     // (lanes without a line and cells past Q re-read cell 0 of the column;
     // those values are never used)
-    T d[QMAX][NN];
-    // direct: my block starts at cell j0 (downwind = physical order) or at
-    // Na - j0 - QMAX (reversed); lanes without a line read column 0
-    const int64_t dbase = kc_base + (col0 + (act ? c : 0)) * CS +
-                          (int64_t)(act ? (sg > 0 ? j0 : Na - j0 - QMAX) : 0) * NN;
-    if (direct) {
-      LVT v[QMAX * NN / LV];
-      const LVT* src = reinterpret_cast<const LVT*>(f + dbase);
-#pragma unroll
-      for (int i = 0; i < QMAX * NN / LV; ++i) v[i] = src[i];
-      const T* vs = reinterpret_cast<const T*>(v);
+    if constexpr (GROUPED) {
+      int rows[QMAX];
 #pragma unroll
       for (int q = 0; q < QMAX; ++q)
-#pragma unroll
-        for (int n = 0; n < NN; ++n) d[q][n] = vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n];
-    } else {
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
-#pragma unroll
-        for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+        rows[q] = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
+      switch (a * 2 + (sg > 0 ? 1 : 0)) {
+        case 0: line_lanes_tile<T, P, DIM, 0, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 1: line_lanes_tile<T, P, DIM, 0, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 2: if constexpr (DIM > 1) line_lanes_tile<T, P, DIM, 1, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 3: if constexpr (DIM > 1) line_lanes_tile<T, P, DIM, 1, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 4: if constexpr (DIM > 2) line_lanes_tile<T, P, DIM, 2, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        default: if constexpr (DIM > 2) line_lanes_tile<T, P, DIM, 2, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
       }
-    }
-    switch (a * 2 + (sg > 0 ? 1 : 0)) {
-      case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-    }
-    if (act && direct) {
-      LVT v[QMAX * NN / LV];
-      T* vs = reinterpret_cast<T*>(v);
+      continue;
+    } else {
+      T d[QMAX][NN];
+      // direct: my block starts at cell j0 (downwind = physical order) or at
+      // Na - j0 - QMAX (reversed); lanes without a line read column 0
+      const int64_t dbase = kc_base + (col0 + (act ? c : 0)) * CS +
+                            (int64_t)(act ? (sg > 0 ? j0 : Na - j0 - QMAX) : 0) * NN;
+      if (direct) {
+        LVT v[QMAX * NN / LV];
+        const LVT* src = reinterpret_cast<const LVT*>(f + dbase);
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q)
+        for (int i = 0; i < QMAX * NN / LV; ++i) v[i] = src[i];
+        const T* vs = reinterpret_cast<const T*>(v);
 #pragma unroll
-        for (int n = 0; n < NN; ++n) vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n] = d[q][n];
-      LVT* dst = reinterpret_cast<LVT*>(f + dbase);
+        for (int q = 0; q < QMAX; ++q)
 #pragma unroll
-      for (int i = 0; i < QMAX * NN / LV; ++i) dst[i] = v[i];
-    } else if (act) {
+          for (int n = 0; n < NN; ++n) d[q][n] = vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n];
+      } else {
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        if (q < Q) {
-          const int row = sg > 0 ? j0 + q : Na - 1 - j0 - q;
+        for (int q = 0; q < QMAX; ++q) {
+          const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
 #pragma unroll
-          for (int n = 0; n < NN; ++n) tile[cbase + row * NN + n] = d[q][n];
+          for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+        }
+      }
+      switch (a * 2 + (sg > 0 ? 1 : 0)) {
+        case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+      }
+      if (act && direct) {
+        LVT v[QMAX * NN / LV];
+        T* vs = reinterpret_cast<T*>(v);
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q)
+#pragma unroll
+          for (int n = 0; n < NN; ++n) vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n] = d[q][n];
+        LVT* dst = reinterpret_cast<LVT*>(f + dbase);
+#pragma unroll
+        for (int i = 0; i < QMAX * NN / LV; ++i) dst[i] = v[i];
+      } else if (act) {
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          if (q < Q) {
+            const int row = sg > 0 ? j0 + q : Na - 1 - j0 - q;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) tile[cbase + row * NN + n] = d[q][n];
+          }
         }
       }
     }
