@@ -180,12 +180,18 @@ def cpu_baseline(spec, W0, budget_s=12.0):
 
 
 def bench_batch(args):
-    """The many-problem workload: 48 seeded uneven problems advanced together
-    by kds_batch_step (grouped launches, one captured graph per step)."""
+    """The many-problem workloads, advanced together by kds_batch_step (grouped
+    launches, one captured graph per step): "batch" = 48 seeded uneven
+    problems (3.4e9 unknowns); "batch_small" = 256 small ones (acoustics
+    32^2..64^2, Euler 8^3..16^3), each too small to fill the GPU alone."""
     import torch
     from paper_2212_11010_amd import kds
     from paper_2212_11010_amd import workloads as wl
-    specs = wl.make_batch_workload()
+    if args.workload == "batch_small":
+        specs = wl.make_batch_workload(n_problems=256, max_unknowns=4e9, acoustics_n=(32, 48, 64),
+                                       euler_n=(8, 12, 16), seed=wl.SEED_BASE + 55)
+    else:
+        specs = wl.make_batch_workload()
     U = sum(wl.unknowns(s) for s in specs)
     log("batch of %d problems, U=%d" % (len(specs), U))
 
@@ -214,8 +220,9 @@ def bench_batch(args):
     ms_total = b.step_timed(args.steps)        # HIP events on the batch stream
     ms32 = ms_total / args.steps
     kms = b.time_kernels(args.steps)          # grouped sweep / relax launches per step
-    # the same members stepped one problem at a time (own graphs), for the
-    # gain of grouping
+    # the same members stepped one problem at a time (each on its own
+    # stream, with its own graphs: concurrent up to the hardware queues), and
+    # step by step in turn, the order one stream would impose
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pb in members:
@@ -223,6 +230,12 @@ def bench_batch(args):
     for pb in members:
         pb.synchronize()
     ms_single = (time.perf_counter() - t0) * 1e3 / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for pb in members:
+            pb.step(1)
+            pb.synchronize()
+    ms_serial = (time.perf_counter() - t0) * 1e3 / args.steps
     # and their own kernels' durations (line members; HIP events per problem)
     single_k = [0.0, 0.0]
     for pb, sc in zip(members, scheds):
@@ -240,6 +253,8 @@ def bench_batch(args):
     extra = {"schedules": {k: scheds.count(k) for k in set(scheds)},
              "grouped_kernel_ms": {"sweep": kms[0], "relax": kms[1]},
              "one_by_one_ms_per_step": ms_single,
+             "serial_ms_per_step": ms_serial,
+             "speedup_batched_vs_serial": ms_serial / ms32,
              "one_by_one_line_member_kernel_ms": {"sweep": single_k[0], "relax": single_k[1]},
              "speedup_batched_vs_one_by_one": ms_single / ms32,
              "state_finite": ok}
@@ -267,7 +282,8 @@ def bench_batch(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batch48_acoustics2d_euler3d_mixed", "problems": len(specs),
+        "config": {"workload": ("batch256_small_acoustics2d_euler3d" if args.workload == "batch_small"
+                                else "batch48_acoustics2d_euler3d_mixed"), "problems": len(specs),
                    "unknowns": U, "n_iter": specs[0]["n_iter"]},
         "roofline": roof, "extra": extra,
     }
@@ -332,7 +348,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2212_11010_amd import workloads as wl
 
-    if args.workload == "batch":
+    if args.workload in ("batch", "batch_small"):
         bench_batch(args)
         return
     spec, W0 = workload(args.workload, args.cells, args.sub)
