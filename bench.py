@@ -363,7 +363,8 @@ def main():
              "fp32_state_finite": ok32, "line_plan": {"cells_per_lane": info32["line_Q"][:spec["dim"]],
                                                       "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
                                                       "autotuned": bool(info32["tuned"]),
-                                                      "x_direct": bool(info32["line_xdirect"])}}
+                                                      "x_direct": bool(info32["line_xdirect"]),
+                                                      "lds_bytes_per_workgroup": info32["line_lds_bytes"]}}
     if not args.no_fp64:
         base = "front" if sched == "front" else "plain"
         ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2)

@@ -207,6 +207,7 @@ typedef struct {
   int32_t line_bw[3];     /* line schedule, per axis: columns of cells per workgroup */
   int32_t tuned;          /* 1 after kds_tune */
   int32_t line_xdirect;   /* line schedule: x lines read / written straight to registers */
+  int32_t line_lds_bytes; /* line schedule: LDS allocated per workgroup */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

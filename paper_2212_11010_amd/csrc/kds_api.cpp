@@ -246,6 +246,7 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
   }
   pl.block_start[p->nv * p->m] = acc;
   pl.lds_elems = max_lds;
+  pl.lds_alloc = max_lds;
   pl.threads = threads;
   pl.xdirect = 0;  // the autotuner switches it on where it is faster
   return threads <= 256 && acc <= 0x7fffffffLL;
@@ -885,6 +886,23 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
       p->plan = pl;
     }
   }
+  // workgroups per CU: more LDS per workgroup than the tile needs lets fewer
+  // of them share a CU, so that later ones start while earlier ones compute
+  if (ok) {
+    const int cu_lds = 160 * 1024;
+    for (int per_cu : {8, 6, 4, 3, 2}) {
+      LinePlan pl = p->plan;
+      const int want = std::min(p->lds_cap, cu_lds / per_cu) / (int)p->elem - 64;
+      if (want <= pl.lds_elems) continue;
+      pl.lds_alloc = want;
+      float ms = 0.0f;
+      if (!(ok = time_plan(pl, &ms))) break;
+      if (ms < 0.97f * best) {
+        best = ms;
+        p->plan = pl;
+      }
+    }
+  }
   // restore the state and drop the graph captured with the old plan
   hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -1038,6 +1056,10 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
   }
   info->tuned = p->tuned ? 1 : 0;
   info->line_xdirect = p->sched == KDS_SCHED_LINE ? p->plan.xdirect : 0;
+  info->line_lds_bytes =
+      p->sched == KDS_SCHED_LINE
+          ? (int32_t)(std::max(p->plan.lds_elems, p->plan.lds_alloc) * (int)p->elem)
+          : 0;
   return KDS_OK;
 }
 
@@ -1156,7 +1178,7 @@ kds_status batch_build(kds_batch* b) {
     pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, p->bnd(),
                    br->line_tasks.data() + off);
     br->line_start.push_back(br->line_start.back() + p->plan.block_start[g.nv * g.m]);
-    br->lds_elems = std::max(br->lds_elems, (size_t)p->plan.lds_elems);
+    br->lds_elems = std::max(br->lds_elems, (size_t)std::max(p->plan.lds_elems, p->plan.lds_alloc));
     off = br->relax_tasks.size();
     br->relax_tasks.resize(off + rb);
     pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->f, p->f, p->plane(),

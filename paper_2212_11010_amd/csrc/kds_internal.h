@@ -104,6 +104,8 @@ struct LinePlan {
   int bw[kMaxVel];         // columns of cells per bundle
   int64_t block_start[kMaxVel * kMaxM + 1];  // prefix over (k, c) of bundles
   int lds_elems;           // max tile elements
+  int lds_alloc;           // elements of LDS allocated per workgroup (>= lds_elems; more
+                           // limits how many workgroups share a CU)
   int threads;             // block size
   int xdirect;             // x lines may bypass the LDS tile (cells per lane = QMAX)
 };

@@ -108,6 +108,38 @@ __device__ __forceinline__ void copy_rows(T* __restrict__ f, T* tile, int64_t ro
   }
 }
 
+// One contiguous block of n vectors: 32-bit offsets from a uniform base (the
+// loads and stores take the scalar-base addressing form), U in flight.
+template <typename T, int VW, bool LOAD>
+__device__ __forceinline__ void copy_block(T* __restrict__ f, T* tile, int64_t base, int n) {
+  using VT = typename VecT<T, VW>::type;
+  constexpr int U = 16;
+  VT* g = reinterpret_cast<VT*>(f + base);
+  VT* t = reinterpret_cast<VT*>(tile);
+  const int bs = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * bs) {
+    if (LOAD) {
+      VT v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * bs;
+        v[u] = g[e < n ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * bs;
+        if (e < n) t[e] = v[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * bs;
+        if (e < n) g[e] = t[e];
+      }
+    }
+  }
+}
+
 template <typename T, bool LOAD>
 __device__ __forceinline__ void copy_tile(T* __restrict__ f, T* tile, int64_t rowbase,
                                           int64_t rowstride, int R, int rows) {
@@ -117,6 +149,15 @@ __device__ __forceinline__ void copy_tile(T* __restrict__ f, T* tile, int64_t ro
     rows = 1;
   }
   constexpr int VMAX = 16 / sizeof(T);
+  if (rows == 1) {
+    if (VMAX >= 4 && R % 4 == 0 && rowbase % 4 == 0)
+      copy_block<T, (VMAX >= 4 ? 4 : 1), LOAD>(f, tile, rowbase, R / 4);
+    else if (R % 2 == 0 && rowbase % 2 == 0)
+      copy_block<T, 2, LOAD>(f, tile, rowbase, R / 2);
+    else
+      copy_block<T, 1, LOAD>(f, tile, rowbase, R);
+    return;
+  }
   if (VMAX >= 4 && R % 4 == 0 && rowbase % 4 == 0 && rowstride % 4 == 0) {
     copy_rows<T, (VMAX >= 4 ? 4 : 1), LOAD>(f, tile, rowbase, rowstride, R, rows);
   } else if (R % 2 == 0 && rowbase % 2 == 0 && rowstride % 2 == 0) {
@@ -714,7 +755,7 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
   const BndRef<T> bd = bnd_ref<T>(bnd);
   const SweepTab<T>& t = *(const SweepTab<T>*)tab;
   const int64_t nblocks = plan.block_start[g.nv * g.m];
-  const size_t lds = (size_t)plan.lds_elems * sizeof(T);
+  const size_t lds = (size_t)std::max(plan.lds_elems, plan.lds_alloc) * sizeof(T);
   const int key = g.P * 10 + g.dim;
   switch (key) {
 #define KDS_LINE(PP, DD)                                                                        \

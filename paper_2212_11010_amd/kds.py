@@ -57,7 +57,7 @@ class kds_info_t(C.Structure):
         ("precision", C.c_int32), ("steps_done", C.c_int32),
         ("max_kinetic_courant", C.c_double), ("min_subdomain_width", C.c_double),
         ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
-        ("tuned", C.c_int32), ("line_xdirect", C.c_int32),
+        ("tuned", C.c_int32), ("line_xdirect", C.c_int32), ("line_lds_bytes", C.c_int32),
     ]
 
 
