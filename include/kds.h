@@ -166,9 +166,10 @@ kds_status kds_step(kds_problem* p, int32_t n_steps);
 kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
 
 /* Autotuner of the line schedule: times the sweep kernel for candidate
- * launch plans (cells per lane, columns of cells per workgroup; one grid axis
- * at a time, reps launches each) on the current state, keeps the fastest,
- * restores the state.  Needs a state; a no-op for the plain schedule
+ * launch plans on the current state (reps launches each) and keeps the
+ * fastest: cells per lane and columns of cells per workgroup (one grid axis at
+ * a time), then the direct register path for x lines against the LDS tile,
+ * then fewer workgroups per CU (larger LDS allocation); restores the state.  Needs a state; a no-op for the plain schedule
  * (*sweep_ms = -1).  sweep_ms (nullable): best average sweep time.  Needs
  * one state's worth of free device memory (else KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
