@@ -132,3 +132,32 @@ def test_batch_member_without_state_rejected():
         assert e.value.status == kds.KDS_E_STATE
     a.close()
     c.close()
+
+
+def test_batch_with_dirichlet_member():
+    """A member with Dirichlet axes keeps its own kernel sequence inside the
+    batch (its boundary data held constant over the batched steps) and ends
+    bitwise equal to the same problem stepped on its own."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    specs = small_batch(seed=13, n=3)
+    dspec, dW0 = wl.make_workload(2, n_cells=[24, 16], sub_cells=[8, 8], periodic=[0, 1], steps=3)
+    Wb = wl.boundary_state(dspec, dW0)
+    members = make_members(specs, "fp32", ["auto"] * len(specs))
+    singles = make_members(specs, "fp32", ["auto"] * len(specs))
+    dm = kds.Problem(dspec, precision="fp32")
+    ds = kds.Problem(dspec, precision="fp32")
+    for pb in (dm, ds):
+        pb.set_state(torch.from_numpy(dW0).cuda())
+        pb.set_boundary(Wb)
+    with kds.Batch(members + [dm]) as b:
+        b.step(3)
+        b.synchronize()
+    for pb in singles + [ds]:
+        pb.step(3)
+    for pm, ps in zip(members + [dm], singles + [ds]):
+        assert pm.info()["steps_done"] == 3
+        assert np.array_equal(pm.get_kinetic(), ps.get_kinetic())
+    for pb in members + singles + [dm, ds]:
+        pb.close()
