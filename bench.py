@@ -387,6 +387,16 @@ def main():
             "avg_launch_ms": dur_s * 1e3}
 
     roof["device_copy_gbs"] = device_copy_gbs()  # context: what a plain copy reaches
+    # whole-step traffic: this schedule's algorithmic bytes per unknown, and
+    # the literal scheme's (K sweeps each reading the state and its traces,
+    # the last one writing it, then the relaxation: 32 B/U in FP32 at K = 3)
+    step_bpu = {"line": 16.0, "plain": 4.0 * spec["n_iter"] + 4.0 + 8.0,
+                "front": 8.0 * spec["n_iter"] + 8.0}[sched]
+    literal_bpu = 8.0 * spec["n_iter"] + 8.0
+    extra["step_hbm"] = {"bytes_per_unknown": step_bpu,
+                         "frac": step_bpu * U / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "literal_scheme_bytes_per_unknown": literal_bpu,
+                         "literal_scheme_frac": literal_bpu * U / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if sched == "front":
         # dense cell solves: 2 Kd flop per unknown per launch (one subdomain
         # iteration), Kd = nn + 3 nf; the split forms execute three products
