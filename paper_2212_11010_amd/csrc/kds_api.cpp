@@ -190,9 +190,11 @@ bool line_choice_ok(const kds_problem* p, int ax, int Q, int bw) {
   const int Na = p->N[ax], S = p->S[ax];
   const int qmax = line_qmax((int)p->elem, p->nn);
   if (Q < 1 || Q > qmax || S % Q || Na / Q > 64 || bw < 1) return false;
-  if ((int64_t)bw * Na * p->nn * (int)p->elem > p->lds_cap) return false;
+  if ((int64_t)bw * line_col_lds(Na, p->nn) * (int)p->elem > p->lds_cap) return false;
   if (ax == 0 && bw > p->ncell / Na) return false;
-  if (ax != 0 && (bw > p->N[0] || bw * p->nn > 256)) return false;
+  // (a row of a y / z bundle is copied by one pass of the workgroup, except
+  // in grouped mode, which copies 16-value runs)
+  if (ax != 0 && (bw > p->N[0] || (!line_grouped(p->nn) && bw * p->nn > 256))) return false;
   return true;
 }
 
@@ -210,7 +212,7 @@ bool heuristic_choice(const kds_problem* p, int ax, int* Qo, int* bwo) {
     if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
   }
   if (!bestQ) return false;
-  const int col = Na * p->nn * (int)p->elem;
+  const int col = line_col_lds(Na, p->nn) * (int)p->elem;
   int bw = std::max(1, 32 * 1024 / col);
   while (bw > 1 && !line_choice_ok(p, ax, bestQ, bw)) --bw;
   if (!line_choice_ok(p, ax, bestQ, bw)) return false;
@@ -233,9 +235,9 @@ bool finalize_plan(const kds_problem* p, const int* Qax, const int* bwax, LinePl
     pl.Q[k] = Q;
     pl.lpl2[k] = l2;
     pl.bw[k] = bw;
-    max_lds = std::max(max_lds, bw * Na * p->nn);
+    max_lds = std::max(max_lds, bw * line_col_lds(Na, p->nn));
     threads = std::max(threads, std::min(256, 64 * ((bw + lw - 1) / lw)));
-    if (ax != 0) threads = std::max(threads, ((bw * p->nn + 63) / 64) * 64);
+    if (ax != 0 && !line_grouped(p->nn)) threads = std::max(threads, ((bw * p->nn + 63) / 64) * 64);
     int64_t nb;
     if (ax == 0) nb = (p->ncell / Na + bw - 1) / bw;
     else nb = (int64_t)((p->N[0] + bw - 1) / bw) * (p->ncell / p->N[0] / Na);
@@ -598,15 +600,7 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED, why);
   }
-  // AUTO keeps the plain schedule for 64-node cells: there the line kernel
-  // solves one group of node lines at a time out of the LDS tile, and
-  // measures slower than the plain sweep (96^3 Euler, p = 3: 8.1 ms against
-  // 3 x 2.0 ms per step).
-  const bool line_preferred = !line_grouped(p->nn);
-  p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok ||
-              (cfg->schedule == KDS_SCHED_AUTO && !line_preferred && p->K > 0))
-                 ? KDS_SCHED_PLAIN
-                 : KDS_SCHED_LINE;
+  p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok) ? KDS_SCHED_PLAIN : KDS_SCHED_LINE;
   if (want_front) {
     p->sched = KDS_SCHED_FRONT;
     if (front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) > 64 * 1024) {

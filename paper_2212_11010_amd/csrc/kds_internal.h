@@ -88,13 +88,24 @@ struct EqTab {
 // time from the LDS tile (16 values per cell in registers).
 __host__ __device__ constexpr bool line_grouped(int nn) { return nn > 27; }
 
+// Grouped mode streams two groups of four node lines (32 values per cell)
+// through the LDS tile at a time; cells sit kGroupStride values apart there.
+constexpr int kGroupStride = 36;
+
+// LDS values per column of Na cells in the line kernel's tile.
+__host__ __device__ constexpr int line_col_lds(int Na, int nn) {
+  return line_grouped(nn) ? Na * kGroupStride : Na * nn;
+}
+
 // State values per cell a lane holds in registers at once.
 __host__ __device__ constexpr int line_cell_values(int nn) { return line_grouped(nn) ? 16 : nn; }
 
 // Most cells per lane the line kernel keeps in registers (a budget of 64
-// state values per lane).
+// state values per lane; 2 cells in grouped mode, whose copy passes need the
+// registers more than the solve needs long lane blocks).
 __host__ __device__ constexpr int line_qmax(int elem_bytes, int nn) {
-  return (void)elem_bytes, 64 / line_cell_values(nn) >= 8 ? 8 : 64 / line_cell_values(nn) >= 4 ? 4 : 2;
+  return (void)elem_bytes, line_grouped(nn) ? 2
+         : 64 / line_cell_values(nn) >= 8 ? 8 : 64 / line_cell_values(nn) >= 4 ? 4 : 2;
 }
 
 // Line-schedule launch plan (per velocity).

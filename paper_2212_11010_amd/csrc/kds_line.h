@@ -474,41 +474,161 @@ __device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
   }
 }
 
-// Cells of 64 nodes (p = 3 in 3-D): the lane's cells stay in the LDS tile and
-// each group of lines is brought into registers, solved and written back in
-// turn (registers for one group of lines instead of all 64 nodes).
-template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, bool DIR, int O0 = 0>
-__device__ __forceinline__ void line_lanes_tile(T* tile, int cbase, const int (&rows)[QMAX],
-                                                bool act, const LineLane& ln,
-                                                const T (&C)[P][P], const T (&e1)[P],
-                                                const T (&eth)[P], T gg, T G, int K, const T* bo,
-                                                const T* bn) {
-  constexpr int ALL = ColShape<P, DIM>::PER;
-  constexpr int GS = ALL <= 4 ? ALL : (ALL % 3 == 0 ? 3 : 4);
-  if constexpr (O0 < ALL) {
-    constexpr int n = ALL - O0 < GS ? ALL - O0 : GS;
-    T dg[QMAX][n * P];
+// ------------------------------------------------- grouped mode (64 nodes)
+//
+// Cells of 64 nodes (p = 3 in 3-D): the 16 node lines through a cell along
+// the velocity axis are solved in four groups of four lines, so a lane keeps
+// 16 values per cell in registers.  The lines of different groups share no
+// node, so the tile holds two groups at a time: pass h brings groups 2h and
+// 2h + 1 (32 values) of every cell of the bundle into LDS, solves them, and
+// writes them back while the next pass's values arrive.  A pass is eight runs
+// of four nodes contiguous along x; for lines along x or y they form one
+// contiguous half cell (128 B in FP32, a whole cache line).  In LDS a cell
+// takes kGroupStride values and the cells of a column are interleaved by lane
+// (cell j at slot (j mod Q) NL + j / Q, NL lanes per line), so the lanes of a
+// wave reading their q-th cells hit distinct banks.
+
+// node offset of run i (four nodes along x) of pass h of the lines along axis
+// (z lines: groups 2h + (i mod 2), their runs at z index i / 2)
+__device__ __forceinline__ constexpr int group_run(int axis, int h, int i) {
+  return axis == 2 ? 8 * h + 4 * (i & 1) + 16 * (i >> 1) : 32 * h + 4 * i;
+}
+
+// position inside a cell's LDS slot of node (line O0 + o, index b on AXIS)
+template <int P, int DIM, int AXIS>
+__device__ constexpr int group_pos(int O0, int o, int b) {
+  const int n = node_of<P, DIM, AXIS>(O0 + o, b);
+  for (int i = 0; i < 8; ++i)
+    if (group_run(AXIS, O0 / 8, i) == (n & ~3)) return 4 * i + (n & 3);
+  return 0;
+}
+
+// Solve group gi (wave-uniform) of the lanes' cells; cell q of this lane sits
+// at tile[cell[q]].
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, bool DIR, int O0 = 0>
+__device__ __forceinline__ void group_solve(int gi, T* tile, const int (&cell)[QMAX], bool act,
+                                            const LineLane& ln, const T (&C)[P][P],
+                                            const T (&e1)[P], const T (&eth)[P], T gg, T G, int K,
+                                            const T* bo, const T* bn) {
+  constexpr int PER = ColShape<P, DIM>::PER;
+  if constexpr (O0 < PER) {
+    if (gi > 0) {
+      group_solve<T, P, DIM, AXIS, SIGN, QMAX, DIR, O0 + 4>(gi - 1, tile, cell, act, ln, C, e1,
+                                                            eth, gg, G, K, bo, bn);
+      return;
+    }
+    T dg[QMAX][4 * P];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q)
 #pragma unroll
-      for (int o = 0; o < n; ++o)
+      for (int o = 0; o < 4; ++o)
 #pragma unroll
         for (int b = 0; b < P; ++b)
-          dg[q][o * P + b] = tile[cbase + rows[q] * NN + node_of<P, DIM, AXIS>(O0 + o, b)];
-    line_group<T, P, DIM, AXIS, SIGN, QMAX, n * P, O0, n, DIR, true>(dg, ln, C, e1, eth, gg, G, K,
+          dg[q][o * P + b] = tile[cell[q] + group_pos<P, DIM, AXIS>(O0, o, b)];
+    line_group<T, P, DIM, AXIS, SIGN, QMAX, 4 * P, O0, 4, DIR, true>(dg, ln, C, e1, eth, gg, G, K,
                                                                      bo, bn);
     if (act) {
 #pragma unroll
       for (int q = 0; q < QMAX; ++q)
         if (q < ln.Q)
 #pragma unroll
-          for (int o = 0; o < n; ++o)
+          for (int o = 0; o < 4; ++o)
 #pragma unroll
             for (int b = 0; b < P; ++b)
-              tile[cbase + rows[q] * NN + node_of<P, DIM, AXIS>(O0 + o, b)] = dg[q][o * P + b];
+              tile[cell[q] + group_pos<P, DIM, AXIS>(O0, o, b)] = dg[q][o * P + b];
     }
-    line_lanes_tile<T, P, DIM, AXIS, SIGN, QMAX, NN, DIR, O0 + n>(tile, cbase, rows, act, ln, C, e1,
-                                                                  eth, gg, G, K, bo, bn);
+  }
+}
+
+// x / d for x, d < 2^16 (m = ceil(2^32 / d)): a multiply instead of a division
+__device__ __forceinline__ int div_small(int x, uint64_t m) {
+  return (int)(((uint64_t)(unsigned)x * m) >> 32);
+}
+__host__ __device__ __forceinline__ uint64_t div_magic(int d) {
+  return ((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d;
+}
+
+// The runs of one group of a bundle: run e = (column c, cell j, run i), in
+// the order that keeps neighbouring threads on neighbouring global addresses
+// (x bundles: a column is contiguous; y / z bundles: a row of ncols cells is).
+struct GroupRuns {
+  int64_t gbase, cstride, jstride;  // cell j of column c at gbase + c cstride + j jstride
+  int ncols, Na, Q, NL, CSg, axis;
+  // a thread's runs: e = threadIdx.x + n blockDim.x; i = e mod 8 is the same
+  // for all of them (blockDim.x is a multiple of 64)
+  __device__ __forceinline__ int count() const { return ncols * Na * 8; }
+  __device__ __forceinline__ void at(int e, int64_t& go, int& lo, uint64_t m_inner,
+                                     uint64_t m_q) const {
+    const int i = e & 7;
+    const int cj = e >> 3;
+    const int inner = axis == 0 ? Na : ncols;
+    const int outer_i = div_small(cj, m_inner);
+    const int inner_i = cj - outer_i * inner;
+    const int c = axis == 0 ? outer_i : inner_i;
+    const int j = axis == 0 ? inner_i : outer_i;
+    const int jq = div_small(j, m_q);
+    go = gbase + c * cstride + j * jstride + 4 * i;
+    lo = c * CSg + ((j - jq * Q) * NL + jq) * kGroupStride + 4 * i;
+  }
+};
+
+template <typename T>
+struct Run4 {
+  using V = typename VecT<T, 16 / sizeof(T)>::type;
+  static constexpr int NV = 4 * sizeof(T) / 16;
+  V v[NV];
+  __device__ __forceinline__ void load(const T* p) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) v[u] = reinterpret_cast<const V*>(p)[u];
+  }
+  __device__ __forceinline__ void store(T* p) const {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) reinterpret_cast<V*>(p)[u] = v[u];
+  }
+};
+
+// Write pass gi_store (>= 0) back from LDS, then bring pass gi_load (>= 0)
+// into the same LDS places.  Each thread reads its own places before it
+// refills them, so no barrier is needed between the two; the stores are
+// still in flight while the loads are issued (U per thread).
+template <typename T>
+__device__ __forceinline__ void group_exchange(T* __restrict__ f, T* tile, const GroupRuns& gr,
+                                               int gi_store, int gi_load) {
+  constexpr int U = 8;
+  const int total = gr.count();
+  const int bs = blockDim.x;
+  const uint64_t m_inner = div_magic(gr.axis == 0 ? gr.Na : gr.ncols);
+  const uint64_t m_q = div_magic(gr.Q);
+  // run i of a pass sits at the cell's node group_run(axis, h, i); the
+  // address from at() carries 4 i, so add the rest
+  const int ti = threadIdx.x & 7;
+  if (gi_store >= 0) {
+    const int64_t gadd = group_run(gr.axis, gi_store, ti) - 4 * ti;
+    for (int e = threadIdx.x; e < total; e += bs) {
+      int64_t go;
+      int lo;
+      gr.at(e, go, lo, m_inner, m_q);
+      Run4<T> ov;
+      ov.load(tile + lo);
+      ov.store(f + go + gadd);
+    }
+  }
+  if (gi_load >= 0) {
+    const int64_t gadd = group_run(gr.axis, gi_load, ti) - 4 * ti;
+    for (int e0 = threadIdx.x; e0 < total; e0 += U * bs) {
+      int64_t go[U];
+      int lo[U];
+      Run4<T> nv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // slots past the end re-read the first run (never stored)
+        gr.at(e0 + u * bs < total ? e0 + u * bs : e0, go[u], lo[u], m_inner, m_q);
+        nv[u].load(f + go[u] + gadd);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u * bs < total) nv[u].store(tile + lo[u]);
+    }
   }
 }
 
@@ -556,21 +676,32 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
   const int64_t col0 = a == 0 ? bundle * bw : 0;
 
   // ------------------------------------------------------------ bundle
+  // cell j of column c of the bundle sits at gbase + c cstride + j rowstride
   int ncols;
+  int64_t gbase, rowstride;
   if (a == 0) {
     const int64_t nrows = g.ncell / Na;
     ncols = (int)min<int64_t>(bw, nrows - col0);
-    // consecutive rows of cells are one contiguous block
-    if (!direct) copy_tile<T, true>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
+    gbase = kc_base + col0 * CS;
+    rowstride = NN;
   } else {
     const int nbx = (g.N[0] + bw - 1) / bw;
     const int bx = (int)(bundle % nbx);
     const int64_t other = bundle / nbx;
     const int x0 = bx * bw;
     ncols = min(bw, g.N[0] - x0);
-    const int64_t gbase = a == 1 ? kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)NN
-                                 : kc_base + (other * g.N[0] + x0) * (int64_t)NN;
-    const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
+    gbase = a == 1 ? kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)NN
+                   : kc_base + (other * g.N[0] + x0) * (int64_t)NN;
+    rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
+  }
+  const GroupRuns gr{gbase, a == 0 ? (int64_t)CS : (int64_t)NN, rowstride, ncols, Na, Q, NL,
+                     Na * kGroupStride, a};
+  if constexpr (GROUPED) {
+    group_exchange<T>(f, tile, gr, -1, 0);
+  } else if (a == 0) {
+    // consecutive rows of cells are one contiguous block
+    if (!direct) copy_tile<T, true>(f, tile, gbase, CS, CS, ncols);
+  } else {
     copy_cols<T, NN, true>(f, tile, gbase, rowstride, ncols, Na, CS);
   }
   if (!direct) __syncthreads();
@@ -615,110 +746,119 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
   const int64_t boff = (DIR && bd.old != nullptr && bd.off[a][bside] >= 0)
                            ? (int64_t)kc * bd.nb + bd.off[a][bside] : -1;
 
-  for (int cb = wave * LW; cb < ncols; cb += nwaves * LW) {
-    const int c = cb + slot;
-    const bool act = (c < ncols) && (lil < NL);
-    const T* bo = nullptr;
-    const T* bn = nullptr;
-    if (boff >= 0 && act) {
-      // the column's cell index on the face (cells over the other axes, lower fastest)
-      int64_t fcell;
-      if (a == 0) {
-        fcell = bundle * bw + c;
-      } else {
-        const int nbx = (g.N[0] + bw - 1) / bw;
-        fcell = (bundle % nbx) * bw + c + (int64_t)g.N[0] * (bundle / nbx);
-      }
-      bo = bd.old + boff + fcell * PER;
-      bn = bd.neu + boff + fcell * PER;
+  // grouped mode: passes of two groups of node lines each
+  constexpr int NPASS = GROUPED ? ColShape<P, DIM>::PER / 8 : 1;
+  for (int h = 0; h < NPASS; ++h) {
+    if (GROUPED && h > 0) {
+      // write pass h - 1 back while pass h arrives
+      __syncthreads();
+      group_exchange<T>(f, tile, gr, h - 1, h);
+      __syncthreads();
     }
-    // my cells in downwind order: physical cells j0.. (SIGN > 0) or
-    // Na-1-j0 downwards (SIGN < 0)
-    const int cbase = (act ? c : 0) * CS;
-    // (lanes without a line and cells past Q re-read cell 0 of the column;
-    // those values are never used)
-    if constexpr (GROUPED) {
-      int rows[QMAX];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q)
-        rows[q] = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
-      switch (a * 2 + (sg > 0 ? 1 : 0)) {
-        case 0: line_lanes_tile<T, P, DIM, 0, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 1: line_lanes_tile<T, P, DIM, 0, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 2: if constexpr (DIM > 1) line_lanes_tile<T, P, DIM, 1, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 3: if constexpr (DIM > 1) line_lanes_tile<T, P, DIM, 1, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 4: if constexpr (DIM > 2) line_lanes_tile<T, P, DIM, 2, -1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        default: if constexpr (DIM > 2) line_lanes_tile<T, P, DIM, 2, 1, QMAX, NN, DIR>(tile, cbase, rows, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+    for (int cb = wave * LW; cb < ncols; cb += nwaves * LW) {
+      const int c = cb + slot;
+      const bool act = (c < ncols) && (lil < NL);
+      const T* bo = nullptr;
+      const T* bn = nullptr;
+      if (boff >= 0 && act) {
+        // the column's cell index on the face (cells over the other axes, lower fastest)
+        int64_t fcell;
+        if (a == 0) {
+          fcell = bundle * bw + c;
+        } else {
+          const int nbx = (g.N[0] + bw - 1) / bw;
+          fcell = (bundle % nbx) * bw + c + (int64_t)g.N[0] * (bundle / nbx);
+        }
+        bo = bd.old + boff + fcell * PER;
+        bn = bd.neu + boff + fcell * PER;
       }
-      continue;
-    } else {
-      T d[QMAX][NN];
-      // direct: my block starts at cell j0 (downwind = physical order) or at
-      // Na - j0 - QMAX (reversed); lanes without a line read column 0
-      const int64_t dbase = kc_base + (col0 + (act ? c : 0)) * CS +
-                            (int64_t)(act ? (sg > 0 ? j0 : Na - j0 - QMAX) : 0) * NN;
-      if (direct) {
-        LVT v[QMAX * NN / LV];
-        const LVT* src = reinterpret_cast<const LVT*>(f + dbase);
-#pragma unroll
-        for (int i = 0; i < QMAX * NN / LV; ++i) v[i] = src[i];
-        const T* vs = reinterpret_cast<const T*>(v);
-#pragma unroll
-        for (int q = 0; q < QMAX; ++q)
-#pragma unroll
-          for (int n = 0; n < NN; ++n) d[q][n] = vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n];
-      } else {
+      // my cells in downwind order: physical cells j0.. (SIGN > 0) or
+      // Na-1-j0 downwards (SIGN < 0)
+      const int cbase = (act ? c : 0) * CS;
+      // (lanes without a line and cells past Q re-read cell 0 of the column;
+      // those values are never used)
+      if constexpr (GROUPED) {
+        int cell[QMAX];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
           const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
-#pragma unroll
-          for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+          cell[q] = (act ? c : 0) * gr.CSg + ((row % Q) * NL + row / Q) * kGroupStride;
         }
-      }
-      switch (a * 2 + (sg > 0 ? 1 : 0)) {
-        case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-        default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
-      }
-      if (act && direct) {
-        LVT v[QMAX * NN / LV];
-        T* vs = reinterpret_cast<T*>(v);
+        for (int gi = 2 * h; gi < 2 * h + 2; ++gi) {
+          switch (a * 2 + (sg > 0 ? 1 : 0)) {
+            case 0: group_solve<T, P, DIM, 0, -1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+            case 1: group_solve<T, P, DIM, 0, 1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+            case 2: if constexpr (DIM > 1) group_solve<T, P, DIM, 1, -1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+            case 3: if constexpr (DIM > 1) group_solve<T, P, DIM, 1, 1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+            case 4: if constexpr (DIM > 2) group_solve<T, P, DIM, 2, -1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+            default: if constexpr (DIM > 2) group_solve<T, P, DIM, 2, 1, QMAX, DIR>(gi, tile, cell, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          }
+        }
+        continue;
+      } else {
+        T d[QMAX][NN];
+        // direct: my block starts at cell j0 (downwind = physical order) or at
+        // Na - j0 - QMAX (reversed); lanes without a line read column 0
+        const int64_t dbase = kc_base + (col0 + (act ? c : 0)) * CS +
+                              (int64_t)(act ? (sg > 0 ? j0 : Na - j0 - QMAX) : 0) * NN;
+        if (direct) {
+          LVT v[QMAX * NN / LV];
+          const LVT* src = reinterpret_cast<const LVT*>(f + dbase);
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q)
+          for (int i = 0; i < QMAX * NN / LV; ++i) v[i] = src[i];
+          const T* vs = reinterpret_cast<const T*>(v);
 #pragma unroll
-          for (int n = 0; n < NN; ++n) vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n] = d[q][n];
-        LVT* dst = reinterpret_cast<LVT*>(f + dbase);
+          for (int q = 0; q < QMAX; ++q)
 #pragma unroll
-        for (int i = 0; i < QMAX * NN / LV; ++i) dst[i] = v[i];
-      } else if (act) {
+            for (int n = 0; n < NN; ++n) d[q][n] = vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n];
+        } else {
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-          if (q < Q) {
-            const int row = sg > 0 ? j0 + q : Na - 1 - j0 - q;
+          for (int q = 0; q < QMAX; ++q) {
+            const int row = (act && q < Q) ? (sg > 0 ? j0 + q : Na - 1 - j0 - q) : 0;
 #pragma unroll
-            for (int n = 0; n < NN; ++n) tile[cbase + row * NN + n] = d[q][n];
+            for (int n = 0; n < NN; ++n) d[q][n] = tile[cbase + row * NN + n];
+          }
+        }
+        switch (a * 2 + (sg > 0 ? 1 : 0)) {
+          case 0: line_lanes<T, P, DIM, 0, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 1: line_lanes<T, P, DIM, 0, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 2: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 3: if constexpr (DIM > 1) line_lanes<T, P, DIM, 1, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 4: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, -1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          default: if constexpr (DIM > 2) line_lanes<T, P, DIM, 2, 1, QMAX, NN, DIR>(d, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        }
+        if (act && direct) {
+          LVT v[QMAX * NN / LV];
+          T* vs = reinterpret_cast<T*>(v);
+#pragma unroll
+          for (int q = 0; q < QMAX; ++q)
+#pragma unroll
+            for (int n = 0; n < NN; ++n) vs[(sg > 0 ? q : QMAX - 1 - q) * NN + n] = d[q][n];
+          LVT* dst = reinterpret_cast<LVT*>(f + dbase);
+#pragma unroll
+          for (int i = 0; i < QMAX * NN / LV; ++i) dst[i] = v[i];
+        } else if (act) {
+#pragma unroll
+          for (int q = 0; q < QMAX; ++q) {
+            if (q < Q) {
+              const int row = sg > 0 ? j0 + q : Na - 1 - j0 - q;
+#pragma unroll
+              for (int n = 0; n < NN; ++n) tile[cbase + row * NN + n] = d[q][n];
+            }
           }
         }
       }
     }
-  }
+  }  // passes
   if (direct) return;
   __syncthreads();
 
   // -------------------------------------------------------- write back
-  if (a == 0) {
-    copy_tile<T, false>(f, tile, kc_base + col0 * CS, CS, CS, ncols);
+  if constexpr (GROUPED) {
+    group_exchange<T>(f, tile, gr, NPASS - 1, -1);
+  } else if (a == 0) {
+    copy_tile<T, false>(f, tile, gbase, CS, CS, ncols);
   } else {
-    const int nbx = (g.N[0] + bw - 1) / bw;
-    const int bx = (int)(bundle % nbx);
-    const int64_t other = bundle / nbx;
-    const int x0 = bx * bw;
-    const int64_t gbase = a == 1 ? kc_base + (other * g.N[1] * g.N[0] + x0) * (int64_t)NN
-                                 : kc_base + (other * g.N[0] + x0) * (int64_t)NN;
-    const int64_t rowstride = a == 1 ? (int64_t)g.N[0] * NN : (int64_t)g.N[0] * g.N[1] * NN;
     copy_cols<T, NN, false>(f, tile, gbase, rowstride, ncols, Na, CS);
   }
 }

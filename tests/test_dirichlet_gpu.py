@@ -28,6 +28,8 @@ CASES = {
                     ("plain", "line")),
     "cfg3_dir_xz": (3, dict(n_cells=[8, 6, 8], sub_cells=[4, 3, 4], steps=2, periodic=[0, 1, 0]),
                     ("plain", "line")),
+    "cfg4_dir_yz": (4, dict(n_cells=[6, 8, 6], sub_cells=[3, 4, 2], steps=2, periodic=[1, 0, 0]),
+                    ("plain", "line")),
     "maxwell_dir_x": (6, dict(n_cells=[8, 4, 4], sub_cells=[4, 4, 2], steps=3,
                               periodic=[0, 1, 1]), ("front",)),
     "maxwell_dir_all": (6, dict(n_cells=[6, 4, 4], sub_cells=[3, 2, 4], steps=2, degree=1,

@@ -1,7 +1,7 @@
 """GPU parity at the full sizes of the measured workloads, in the launch
-configuration bench.py times (autotuned line plan, or the plain schedule the
-automatic choice takes for p = 3 in 3-D), on sampled outputs the FP64 oracle
-computes one by one.
+configuration bench.py times (the automatic schedule choice, the line schedule
+here, with the autotuned plan; for p = 3 in 3-D its node-line groups streamed
+through LDS), on sampled outputs the FP64 oracle computes one by one.
 
 For velocities parallel to a grid axis the transport of the whole grid is the
 independent 1-D transport of every node line along that axis (pinned on the

@@ -26,6 +26,10 @@ CASES = {
     "cfg2_q1_deg1": (2, dict(n_cells=[24, 36], sub_cells=[12, 12], degree=1, steps=5)),
     "cfg3_small": (3, dict(n_cells=[12, 10, 8], sub_cells=[6, 5, 4], steps=3)),
     "cfg4_small": (4, dict(n_cells=[12, 12, 6], sub_cells=[6, 4, 3], steps=2)),
+    # degree 3 in 3-D (64-node cells, node-line groups streamed through LDS):
+    # ragged bundles and odd cells per lane; the converged iteration
+    "cfg4_ragged": (4, dict(n_cells=[10, 6, 9], sub_cells=[5, 3, 3], steps=2)),
+    "cfg4_converged": (4, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 2], steps=2, n_iter=0)),
     "cfg3_k1": (3, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=2, n_iter=1)),
     "cfg2_theta1": (2, dict(n_cells=[32, 16], sub_cells=[8, 16], steps=3, theta=1.0)),
     "cfg2_full_2steps": (2, dict(steps=2)),
