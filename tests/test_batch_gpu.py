@@ -161,3 +161,38 @@ def test_batch_with_dirichlet_member():
         assert np.array_equal(pm.get_kinetic(), ps.get_kinetic())
     for pb in members + singles + [dm, ds]:
         pb.close()
+
+
+def test_batch_with_degree3_members():
+    """Degree-3 3-D members (64-node cells: node-line groups streamed through
+    LDS) share the batched line launch of their (precision, degree,
+    dimension); they end bitwise equal to the same problems stepped on their
+    own, and the first matches the FP64 oracle."""
+    import torch
+    from oracle import oracle
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    cases = [wl.make_workload(4, n_cells=[8, 6, 4], sub_cells=[4, 3, 2], steps=2, seed=41),
+             wl.make_workload(4, n_cells=[12, 8, 6], sub_cells=[6, 4, 3], steps=2, seed=42)]
+    members, singles = [], []
+    for spec, W0 in cases:
+        for lst in (members, singles):
+            pb = kds.Problem(spec, precision="fp32")
+            pb.set_state(torch.from_numpy(W0).cuda())
+            lst.append(pb)
+    with kds.Batch(members) as b:
+        b.step(2)
+        b.synchronize()
+    for pb in singles:
+        pb.step(2)
+    for pm, ps in zip(members, singles):
+        assert pm.info()["steps_done"] == 2
+        assert np.array_equal(pm.get_kinetic(), ps.get_kinetic())
+    spec, W0 = cases[0]
+    F, W = oracle.run(spec, W0, 2, threads=0)
+    ef = relerr(members[0].get_kinetic(), np.ascontiguousarray(F.transpose(0, 2, 3, 1)))
+    ew = relerr(members[0].moments(), W)
+    print("  degree-3 member err W %.2e F %.2e" % (ew, ef), flush=True)
+    assert ew <= TOL["fp32"] and ef <= TOL["fp32"], (ew, ef)
+    for pb in members + singles:
+        pb.close()
