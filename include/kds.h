@@ -71,7 +71,10 @@ typedef enum {
 } kds_prec;
 
 typedef enum {
-  KDS_SCHED_AUTO = 0,  /* the line schedule when the shape allows it, else plain */
+  KDS_SCHED_AUTO = 0,  /* the line schedule when the shape allows it (every grid
+                          line along a velocity fits one wavefront: at most
+                          64 x Q_max cells, Q_max = 8 for up to 8 nodes per
+                          cell, 4 for up to 16, else 2), else plain */
   KDS_SCHED_PLAIN = 1, /* literal sweep: one launch per subdomain iteration,
                           one thread per (velocity, component, line, subdomain)
                           walking its cells in downwind order */

@@ -548,7 +548,7 @@ __host__ __device__ __forceinline__ uint64_t div_magic(int d) {
   return ((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d;
 }
 
-// The runs of one group of a bundle: run e = (column c, cell j, run i), in
+// The runs of one pass over a bundle: run e = (column c, cell j, run i), in
 // the order that keeps neighbouring threads on neighbouring global addresses
 // (x bundles: a column is contiguous; y / z bundles: a row of ncols cells is).
 struct GroupRuns {
@@ -587,13 +587,13 @@ struct Run4 {
   }
 };
 
-// Write pass gi_store (>= 0) back from LDS, then bring pass gi_load (>= 0)
+// Write pass h_store (>= 0) back from LDS, then bring pass h_load (>= 0)
 // into the same LDS places.  Each thread reads its own places before it
 // refills them, so no barrier is needed between the two; the stores are
 // still in flight while the loads are issued (U per thread).
 template <typename T>
 __device__ __forceinline__ void group_exchange(T* __restrict__ f, T* tile, const GroupRuns& gr,
-                                               int gi_store, int gi_load) {
+                                               int h_store, int h_load) {
   constexpr int U = 8;
   const int total = gr.count();
   const int bs = blockDim.x;
@@ -602,8 +602,8 @@ __device__ __forceinline__ void group_exchange(T* __restrict__ f, T* tile, const
   // run i of a pass sits at the cell's node group_run(axis, h, i); the
   // address from at() carries 4 i, so add the rest
   const int ti = threadIdx.x & 7;
-  if (gi_store >= 0) {
-    const int64_t gadd = group_run(gr.axis, gi_store, ti) - 4 * ti;
+  if (h_store >= 0) {
+    const int64_t gadd = group_run(gr.axis, h_store, ti) - 4 * ti;
     for (int e = threadIdx.x; e < total; e += bs) {
       int64_t go;
       int lo;
@@ -613,8 +613,8 @@ __device__ __forceinline__ void group_exchange(T* __restrict__ f, T* tile, const
       ov.store(f + go + gadd);
     }
   }
-  if (gi_load >= 0) {
-    const int64_t gadd = group_run(gr.axis, gi_load, ti) - 4 * ti;
+  if (h_load >= 0) {
+    const int64_t gadd = group_run(gr.axis, h_load, ti) - 4 * ti;
     for (int e0 = threadIdx.x; e0 < total; e0 += U * bs) {
       int64_t go[U];
       int lo[U];
