@@ -155,6 +155,7 @@ def test_fullsize_sampled_parity(name):
         info = pb.info()
         print("  schedule", info["schedule"], "plan", info["line_Q"], info["line_bw"],
               info["line_xdirect"], flush=True)
+        assert info["schedule"] == kds.KDS_SCHED_LINE
         pb.step(1)
         Fd = torch.empty(pb.f_shape, dtype=torch.float64, device="cuda")
         pb.get_kinetic(Fd)
