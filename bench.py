@@ -7,7 +7,9 @@ state resident in HBM.  Prints ONE JSON line:
   value        cell-DOF-velocity updates per second (U / t_step), FP32 path
   roofline     dominant kernel vs the HBM roofline (algorithmic bytes / time)
   cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
-  extra        the plain FP64 GPU sweep (the reference GPU path) and speedup
+  extra        the plain FP64 GPU sweep (the reference GPU path) and speedup;
+               for the degree-3 workload (cfg4) also the front schedule's dense
+               cell GEMM on matrix cores in FP32 and the FP16 / BF16 split forms
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
        (--workload: cfg1..cfg4, maxwell, batch = 48 uneven problems together)
@@ -157,6 +159,54 @@ def pmc_summary(args):
     out = os.path.join(ROOT, "profiles", "traffic_%s_%s_fp32.json" % (kname, args.workload))
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec))
+
+
+def gemm_variants(spec, W0, U, steps=2):
+    """The front schedule (one dense cell GEMM per front on the matrix cores)
+    in FP32 and the FP16 / BF16 split three-product forms, each against the
+    FP64 front schedule (FMA; parity-tested against the FP64 oracle at 1e-12)
+    after the same `steps` steps from the same state: ms per step, kernel ms,
+    executed TFLOP/s against the variant's matrix peak, relative error of F."""
+    import torch
+    from paper_2212_11010_amd import kds
+
+    def run(prec):
+        pb = kds.Problem(spec, precision=prec, schedule="front")
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(steps)
+        F = torch.empty(pb.f_shape, dtype=torch.float64, device="cuda")
+        pb.get_kinetic(F)
+        pb.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.step(steps)
+        pb.synchronize()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        kms = pb.time_kernels(2)
+        pb.close()
+        return F, ms, kms
+
+    Fref, ms64, k64 = run("fp64")
+    scale = float(Fref.abs().max())
+    P = spec["degree"] + 1
+    nn = P ** spec["dim"]
+    Kd = nn + 3 * (nn // P)
+    out = {"steps_compared": steps, "fp64_front_ms_per_step": ms64,
+           "fp64_front_sweep_ms": k64[0]}
+    for prec in ("fp32", "fp32_split_f16", "fp32_split_bf16"):
+        F, ms, kms = run(prec)
+        err = float((F - Fref).abs().max()) / scale
+        del F
+        flops = 2.0 * Kd * U * (3 if "split" in prec else 1)
+        tf = flops / (kms[0] * 1e-3) / 1e12
+        out[prec] = {"ms_per_step": ms, "sweep_ms": kms[0], "executed_tflops": tf,
+                     "peak_tflops": MFMA_PEAK_TFS[prec], "frac": tf / MFMA_PEAK_TFS[prec],
+                     "rel_err_vs_fp64_front": err}
+        log("front %s: %.3f ms/step, sweep %.3f ms, %.1f TFLOP/s, rel err %.2e"
+            % (prec, ms, kms[0], tf, err))
+    del Fref
+    return out
 
 
 def cpu_baseline(spec, W0, budget_s=12.0):
@@ -321,6 +371,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-plan autotuner")
+    ap.add_argument("--no-gemm-variants", action="store_true",
+                    help="cfg4: skip the front-schedule GEMM variants (FP32 / FP16 / BF16 split)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM counters)")
     ap.add_argument("--pmc-summary", nargs=4, metavar="CSV",
@@ -409,6 +461,8 @@ def main():
                                "peak_tflops": MFMA_PEAK_TFS[args.precision],
                                "frac": flops / sweep_s / 1e12 / MFMA_PEAK_TFS[args.precision],
                                "hbm_gbs_algorithmic": 8.0 * U / sweep_s / 1e9}
+    if args.workload == "cfg4" and sched != "front" and not args.no_gemm_variants:
+        extra["front_gemm_variants"] = gemm_variants(spec, W0, U)
     out = {
         "metric": METRIC, "value": U / (ms32 * 1e-3), "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
