@@ -416,7 +416,8 @@ def main():
                                                       "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
                                                       "autotuned": bool(info32["tuned"]),
                                                       "x_direct": bool(info32["line_xdirect"]),
-                                                      "lds_bytes_per_workgroup": info32["line_lds_bytes"]}}
+                                                      "lds_bytes_per_workgroup": info32["line_lds_bytes"],
+                                                      "step_launch": "enqueued" if info32["step_eager"] else "graph"}}
     if not args.no_fp64:
         base = "front" if sched == "front" else "plain"
         ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2)

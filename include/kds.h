@@ -158,8 +158,10 @@ kds_status kds_set_boundary(kds_problem* p, const double* W_b, int32_t on_device
 
 /* n_steps time steps (Sec. 2.2): transport of every F_k (K subdomain
  * iterations of the downwind sweep, eq:dg_imp / eq:ibvp) then relaxation
- * (eq:over_relaxation).  Launched asynchronously on the problem's stream (a
- * captured HIP graph per step); returns KDS_E_STATE before set_state. */
+ * (eq:over_relaxation).  Launched asynchronously on the problem's stream: by
+ * default as replays of a captured HIP graph of 8 steps (plus one of 1 step
+ * for the rest), or the kernels enqueued step by step where kds_tune found
+ * that faster; returns KDS_E_STATE before set_state. */
 kds_status kds_step(kds_problem* p, int32_t n_steps);
 
 /* Same steps launched one kernel at a time with HIP events around each kernel;
@@ -172,7 +174,9 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * launch plans on the current state (reps launches each) and keeps the
  * fastest: cells per lane and columns of cells per workgroup (one grid axis at
  * a time), then the direct register path for x lines against the LDS tile,
- * then fewer workgroups per CU (larger LDS allocation); restores the state.  Needs a state; a no-op for the plain schedule
+ * then fewer workgroups per CU (larger LDS allocation), then the step launch
+ * mode of kds_step (graph replay or enqueued kernels; periodic problems
+ * only); restores the state.  Needs a state; a no-op for the plain schedule
  * (*sweep_ms = -1).  sweep_ms (nullable): best average sweep time.  Needs
  * one state's worth of free device memory (else KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
@@ -212,6 +216,8 @@ typedef struct {
   int32_t tuned;          /* 1 after kds_tune */
   int32_t line_xdirect;   /* line schedule: x lines read / written straight to registers */
   int32_t line_lds_bytes; /* line schedule: LDS allocated per workgroup */
+  int32_t step_eager;     /* kds_step enqueues each step's kernels instead of
+                             replaying a captured graph (kds_tune's choice) */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

@@ -40,6 +40,8 @@ struct kds_problem {
   int* front_lvl_cells = nullptr;
   void* fit[2] = {nullptr, nullptr};  // front schedule: iterates
   bool tuned = false;
+  bool eager_steps = false;  // kds_step enqueues the kernels itself instead of
+                             // replaying captured graphs (autotuner's choice)
   double max_nu = 0, min_sub_width = 0;
   bool proposition_ok = true;
   // device
@@ -771,6 +773,12 @@ kds_status kds_step(kds_problem* p, int32_t n_steps) {
     return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary before kds_step");
   if (n_steps == 0) return KDS_OK;
   int left = n_steps;
+  if (p->eager_steps) {
+    for (; left > 0; --left) {
+      kds_status st = enqueue_step(p, false, p->stream);
+      if (st != KDS_OK) return st;
+    }
+  }
   if (left >= kGraphSteps) {
     kds_status st = ensure_graph(p, kGraphSteps, &p->graph_n, &p->graph_n_exec);
     if (st != KDS_OK) return st;
@@ -896,6 +904,39 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
         p->plan = pl;
       }
     }
+  }
+  // step launch mode: captured graphs of kGraphSteps steps against the step's
+  // kernels enqueued one by one (for short steps the graph replay can cost
+  // more than it saves); whole steps, timed with events on the stream.  Not
+  // for Dirichlet axes, whose steps also advance the boundary data.
+  if (ok && p->nbnd == 0) {
+    drop_graphs(p);
+    p->eager_steps = false;
+    const int nrep = 2;
+    float ms_graph = 0.0f, ms_eager = 0.0f;
+    hipError_t e = hipSuccess;
+    st = ensure_graph(p, kGraphSteps, &p->graph_n, &p->graph_n_exec);
+    ok = st == KDS_OK;
+    for (int pass = 0; pass < 2 && ok; ++pass) {
+      e = hipGraphLaunch(p->graph_n_exec, p->stream);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
+      for (int r = 0; r < nrep && e == hipSuccess; ++r) e = hipGraphLaunch(p->graph_n_exec, p->stream);
+      if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
+      for (int i = 0; i < nrep * kGraphSteps && e == hipSuccess && ok; ++i)
+        ok = (st = enqueue_step(p, false, p->stream)) == KDS_OK;
+      if (e == hipSuccess && ok) e = hipEventRecord(p->ev[2], p->stream);
+      if (e == hipSuccess && ok) e = hipEventSynchronize(p->ev[2]);
+      float t01 = 0.0f, t12 = 0.0f;
+      if (e == hipSuccess && ok) e = hipEventElapsedTime(&t01, p->ev[0], p->ev[1]);
+      if (e == hipSuccess && ok) e = hipEventElapsedTime(&t12, p->ev[1], p->ev[2]);
+      if (e != hipSuccess) {
+        st = hip_fail(p, e, "kds_tune");
+        ok = false;
+      }
+      ms_graph += t01;
+      ms_eager += t12;
+    }
+    if (ok) p->eager_steps = ms_eager < 0.98f * ms_graph;
   }
   // restore the state and drop the graph captured with the old plan
   hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
@@ -1049,6 +1090,7 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
     info->line_bw[a] = p->sched == KDS_SCHED_LINE ? p->line_bw[a] : 0;
   }
   info->tuned = p->tuned ? 1 : 0;
+  info->step_eager = p->eager_steps ? 1 : 0;
   info->line_xdirect = p->sched == KDS_SCHED_LINE ? p->plan.xdirect : 0;
   info->line_lds_bytes =
       p->sched == KDS_SCHED_LINE

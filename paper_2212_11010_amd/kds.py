@@ -58,6 +58,7 @@ class kds_info_t(C.Structure):
         ("max_kinetic_courant", C.c_double), ("min_subdomain_width", C.c_double),
         ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
         ("tuned", C.c_int32), ("line_xdirect", C.c_int32), ("line_lds_bytes", C.c_int32),
+        ("step_eager", C.c_int32),
     ]
 
 
