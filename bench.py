@@ -420,7 +420,9 @@ def main():
                                                       "step_launch": "enqueued" if info32["step_eager"] else "graph"}}
     if not args.no_fp64:
         base = "front" if sched == "front" else "plain"
-        ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2)
+        # (its step launch mode tuned too, so that both sides launch their best way)
+        ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2,
+                                               tune=not args.no_tune)
         log("fp64 plain: %.4f ms/step, kernels %s ms" % (ms64, k64))
         extra.update({"fp64_plain_value": U / (ms64 * 1e-3), "fp64_plain_ms_per_step": ms64,
                       "fp64_plain_kernel_ms": {"sweep": k64[0], "relax": k64[1]},

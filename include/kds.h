@@ -176,9 +176,10 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * a time), then the direct register path for x lines against the LDS tile,
  * then fewer workgroups per CU (larger LDS allocation), then the step launch
  * mode of kds_step (graph replay or enqueued kernels; periodic problems
- * only); restores the state.  Needs a state; a no-op for the plain schedule
- * (*sweep_ms = -1).  sweep_ms (nullable): best average sweep time.  Needs
- * one state's worth of free device memory (else KDS_E_NOMEM). */
+ * only); restores the state.  Needs a state.  For the plain and front
+ * schedules only the step launch mode is tuned (*sweep_ms = -1).  sweep_ms
+ * (nullable): best average sweep time.  Needs one state's worth of free
+ * device memory (else KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
 
 /* Average duration of one launch of each kernel kind (sweep: the line kernel,

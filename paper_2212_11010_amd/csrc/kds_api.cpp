@@ -819,10 +819,8 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_tune needs a state (kds_set_state first)");
   if (p->nbnd > 0 && !p->bnd_set) return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary first");
-  if (p->sched != KDS_SCHED_LINE) {
-    if (sweep_ms) *sweep_ms = -1.0;
-    return KDS_OK;
-  }
+  // plain and front schedules: only the step launch mode is tuned
+  const bool line = p->sched == KDS_SCHED_LINE;
   reps = std::max(1, std::min(reps, 100));
   const size_t bytes = (size_t)p->n_unknowns() * p->elem;
   void* save = nullptr;
@@ -848,13 +846,13 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
     *ms /= reps;
     return true;
   };
-  float best = 0.0f;
-  bool ok = time_plan(p->plan, &best);
+  float best = -1.0f;
+  bool ok = !line || time_plan(p->plan, &best);
   bool used[3] = {false, false, false};
   for (int k = 0; k < p->nv; ++k) used[axis_of(p, k)] = true;
   const int bws[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 28, 32};
   // coordinate search: one axis at a time, over (cells per lane, bundle width)
-  for (int ax = 0; ax < 3 && ok; ++ax) {
+  for (int ax = 0; ax < 3 && ok && line; ++ax) {
     if (!used[ax]) continue;
     for (int Q = 1; Q <= kMaxQ && ok; ++Q)
       for (int bw : bws) {
@@ -878,7 +876,7 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   }
   // x lines: the direct register path where it is clearly faster than the
   // LDS tile (both timed again, back to back)
-  if (ok && used[0]) {
+  if (ok && line && used[0]) {
     LinePlan pl = p->plan;
     pl.xdirect = 1;
     float ms_tile = 0.0f, ms_direct = 0.0f;
@@ -890,7 +888,7 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   }
   // workgroups per CU: more LDS per workgroup than the tile needs lets fewer
   // of them share a CU, so that later ones start while earlier ones compute
-  if (ok) {
+  if (ok && line) {
     const int cu_lds = 160 * 1024;
     for (int per_cu : {8, 6, 4, 3, 2}) {
       LinePlan pl = p->plan;
@@ -945,9 +943,9 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   if (!ok) return st;
   if (e != hipSuccess) return hip_fail(p, e, "kds_tune restore");
   drop_graphs(p);
-  p->tuned = true;
-  ++p->plan_version;
-  if (sweep_ms) *sweep_ms = best;
+  p->tuned = line;
+  if (line) ++p->plan_version;
+  if (sweep_ms) *sweep_ms = line ? best : -1.0;
   return KDS_OK;
 }
 
