@@ -417,7 +417,8 @@ def main():
                                                       "autotuned": bool(info32["tuned"]),
                                                       "x_direct": bool(info32["line_xdirect"]),
                                                       "lds_bytes_per_workgroup": info32["line_lds_bytes"],
-                                                      "step_launch": "enqueued" if info32["step_eager"] else "graph"}}
+                                                      "step_launch": "enqueued" if info32["step_eager"] else "graph",
+                                                      "relax_16byte_access": bool(info32["relax_vec"])}}
     if not args.no_fp64:
         base = "front" if sched == "front" else "plain"
         # (its step launch mode tuned too, so that both sides launch their best way)

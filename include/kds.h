@@ -175,12 +175,22 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * fastest: cells per lane and columns of cells per workgroup (one grid axis at
  * a time), then the direct register path for x lines against the LDS tile,
  * then fewer workgroups per CU (larger LDS allocation), then the step launch
- * mode of kds_step (graph replay or enqueued kernels; periodic problems
- * only); restores the state.  Needs a state.  For the plain and front
+ * mode of kds_step (graph replay or enqueued kernels) and the access width of
+ * the relaxation (periodic problems only; whole steps timed); restores the
+ * state.  Needs a state.  For the plain and front
  * schedules only the step launch mode is tuned (*sweep_ms = -1).  sweep_ms
  * (nullable): best average sweep time.  Needs one state's worth of free
  * device memory (else KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
+
+/* Sets the two launch choices kds_tune otherwise makes for kds_step:
+ * step_eager = 1 enqueues each step's kernels (0: replays captured graphs),
+ * relax_vec = 1 runs the relaxation with 16-byte accesses, several nodes per
+ * thread (0: one node per thread; also used where the node count is not a
+ * multiple of the vector width).  Neither changes the arithmetic.  For callers
+ * that capture kds_step into their own graphs, and for tests.  Errors:
+ * KDS_E_INVALID for a NULL problem or a flag other than 0 / 1. */
+kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec);
 
 /* Average duration of one launch of each kernel kind (sweep: the line kernel,
  * or one plain subdomain iteration; relax), from HIP events around reps
@@ -219,6 +229,8 @@ typedef struct {
   int32_t line_lds_bytes; /* line schedule: LDS allocated per workgroup */
   int32_t step_eager;     /* kds_step enqueues each step's kernels instead of
                              replaying a captured graph (kds_tune's choice) */
+  int32_t relax_vec;      /* relaxation with 16-byte accesses, several nodes
+                             per thread (kds_tune's choice) */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

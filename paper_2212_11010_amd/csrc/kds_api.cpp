@@ -42,6 +42,7 @@ struct kds_problem {
   bool tuned = false;
   bool eager_steps = false;  // kds_step enqueues the kernels itself instead of
                              // replaying captured graphs (autotuner's choice)
+  bool relax_vec = false;    // relaxation with 16-byte accesses (autotuner's choice)
   double max_nu = 0, min_sub_width = 0;
   bool proposition_ok = true;
   // device
@@ -400,11 +401,11 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
                                     p->fit[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->fit[p->K & 1], p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->fit[p->K & 1], p->f, p->relax_vec, s));
   } else if (p->sched == KDS_SCHED_LINE) {
     KDS_HIP(p, launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->bnd(), s));
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, p->relax_vec, s));
   } else {
     for (int it = 1; it <= p->K; ++it) {
       const void* tr_prev = it == 1 ? nullptr : p->tr[(it - 1) & 1];
@@ -413,7 +414,7 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
                                     p->tr[it & 1], p->bnd(), s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
-    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f_tmp, p->f, s));
+    KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->f_tmp, p->f, p->relax_vec, s));
   }
   // the boundary data at the end of this step are the start data of the next
   if (p->nbnd > 0) {
@@ -905,36 +906,62 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   }
   // step launch mode: captured graphs of kGraphSteps steps against the step's
   // kernels enqueued one by one (for short steps the graph replay can cost
-  // more than it saves); whole steps, timed with events on the stream.  Not
-  // for Dirichlet axes, whose steps also advance the boundary data.
+  // more than it saves); then, in the chosen mode, the relaxation with 16-byte
+  // accesses against one node per thread.  Whole steps, timed with events on
+  // the stream, twice each.  Not for Dirichlet axes, whose steps also advance
+  // the boundary data.
   if (ok && p->nbnd == 0) {
-    drop_graphs(p);
-    p->eager_steps = false;
-    const int nrep = 2;
-    float ms_graph = 0.0f, ms_eager = 0.0f;
-    hipError_t e = hipSuccess;
-    st = ensure_graph(p, kGraphSteps, &p->graph_n, &p->graph_n_exec);
-    ok = st == KDS_OK;
-    for (int pass = 0; pass < 2 && ok; ++pass) {
-      e = hipGraphLaunch(p->graph_n_exec, p->stream);  // warm-up
+    int nrep = 1;
+    // ms per kGraphSteps * nrep steps in the current mode (graph or enqueued)
+    auto time_steps = [&](float* ms) -> bool {
+      hipError_t e = hipSuccess;
+      if (!p->eager_steps) {
+        st = ensure_graph(p, kGraphSteps, &p->graph_n, &p->graph_n_exec);
+        if (st != KDS_OK) return false;
+        e = hipGraphLaunch(p->graph_n_exec, p->stream);  // warm-up
+      } else {
+        st = enqueue_step(p, false, p->stream);
+        if (st != KDS_OK) return false;
+      }
       if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
-      for (int r = 0; r < nrep && e == hipSuccess; ++r) e = hipGraphLaunch(p->graph_n_exec, p->stream);
+      for (int r = 0; r < nrep && e == hipSuccess; ++r) {
+        if (!p->eager_steps) {
+          e = hipGraphLaunch(p->graph_n_exec, p->stream);
+        } else {
+          for (int i = 0; i < kGraphSteps; ++i)
+            if ((st = enqueue_step(p, false, p->stream)) != KDS_OK) return false;
+        }
+      }
       if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
-      for (int i = 0; i < nrep * kGraphSteps && e == hipSuccess && ok; ++i)
-        ok = (st = enqueue_step(p, false, p->stream)) == KDS_OK;
-      if (e == hipSuccess && ok) e = hipEventRecord(p->ev[2], p->stream);
-      if (e == hipSuccess && ok) e = hipEventSynchronize(p->ev[2]);
-      float t01 = 0.0f, t12 = 0.0f;
-      if (e == hipSuccess && ok) e = hipEventElapsedTime(&t01, p->ev[0], p->ev[1]);
-      if (e == hipSuccess && ok) e = hipEventElapsedTime(&t12, p->ev[1], p->ev[2]);
+      if (e == hipSuccess) e = hipEventSynchronize(p->ev[1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
       if (e != hipSuccess) {
         st = hip_fail(p, e, "kds_tune");
-        ok = false;
+        return false;
       }
-      ms_graph += t01;
-      ms_eager += t12;
-    }
-    if (ok) p->eager_steps = ms_eager < 0.98f * ms_graph;
+      return true;
+    };
+    // samples of about 4 ms (at least kGraphSteps steps, at most 8 times that)
+    float ms_one = 0.0f;
+    drop_graphs(p);
+    ok = time_steps(&ms_one);
+    if (ok) nrep = std::max(1, std::min(8, (int)std::ceil(4.0f / std::max(ms_one, 1e-3f))));
+    // each choice timed twice, alternating, so that drifts cancel
+    auto pick = [&](bool* flag) -> bool {
+      float t0 = 0.0f, t1 = 0.0f;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int v = 0; v < 2; ++v) {
+          *flag = v == 1;
+          drop_graphs(p);
+          float ms = 0.0f;
+          if (!time_steps(&ms)) return false;
+          (v ? t1 : t0) += ms;
+        }
+      *flag = t1 < 0.98f * t0;
+      drop_graphs(p);
+      return true;
+    };
+    ok = ok && pick(&p->eager_steps) && pick(&p->relax_vec);
   }
   // restore the state and drop the graph captured with the old plan
   hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
@@ -946,6 +973,16 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   p->tuned = line;
   if (line) ++p->plan_version;
   if (sweep_ms) *sweep_ms = line ? best : -1.0;
+  return KDS_OK;
+}
+
+kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if ((step_eager != 0 && step_eager != 1) || (relax_vec != 0 && relax_vec != 1))
+    return fail(p, KDS_E_INVALID, "kds_set_launch: flags must be 0 or 1");
+  p->eager_steps = step_eager == 1;
+  p->relax_vec = relax_vec == 1;
+  drop_graphs(p);  // captured with the previous relaxation kernel
   return KDS_OK;
 }
 
@@ -977,7 +1014,7 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
         return launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, p->f_tmp, nullptr,
                                   p->tr[0], p->bnd(), p->stream);
       }
-      return launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, p->stream);
+      return launch_relax(p->prec, p->law, g, p->eq_dev, p->f, p->f, p->relax_vec, p->stream);
     };
     e = launch();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
@@ -1089,6 +1126,7 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
   }
   info->tuned = p->tuned ? 1 : 0;
   info->step_eager = p->eager_steps ? 1 : 0;
+  info->relax_vec = p->relax_vec ? 1 : 0;
   info->line_xdirect = p->sched == KDS_SCHED_LINE ? p->plan.xdirect : 0;
   info->line_lds_bytes =
       p->sched == KDS_SCHED_LINE

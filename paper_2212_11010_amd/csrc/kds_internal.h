@@ -191,9 +191,11 @@ struct FrontParams {
 
 hipError_t launch_init(int prec, int law, const Geom& g, const void* eq, const double* W,
                        void* f, hipStream_t s);
-// eq_dev: a device copy of the equilibrium table (the blob of build_eq_blob)
+// eq_dev: a device copy of the equilibrium table (the blob of build_eq_blob);
+// vec: VW consecutive nodes per thread with 16-byte accesses where the node
+// count allows (same arithmetic)
 hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq_dev, const void* fin,
-                        void* fout, hipStream_t s);
+                        void* fout, bool vec, hipStream_t s);
 hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s);
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s);
 hipError_t launch_set_kinetic(int prec, const Geom& g, const double* F, void* f, hipStream_t s);

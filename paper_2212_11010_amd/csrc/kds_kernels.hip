@@ -108,18 +108,13 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ W, T* _
 // Relaxation (eq:over_relaxation): W = sum_k f_k in FP64, M_k(W) in FP64,
 // f_k <- f_k + omega (M_k - f_k), one rounding to T.  fin may equal fout.
 template <typename T, int LAW, int D, int M, int NV>
-__device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
-                                           const EqTab<D, M, NV>& t, int64_t i) {
+__device__ __forceinline__ void relax_values(const EqTab<D, M, NV>& t, const T (&fr)[NV][M],
+                                             T (&out)[NV][M]) {
   // the kinetic values stay in their storage type until used (registers);
   // W, Q(W) and every M_k component in FP64, one rounding per output
-  T fr[NV][M];
   double w[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) w[r] = 0.0;
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-#pragma unroll
-    for (int r = 0; r < M; ++r) fr[k][r] = fin[(int64_t)(k * M + r) * plane + i];
 #pragma unroll
   for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -139,7 +134,7 @@ __device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
       for (int r = 0; r < M; ++r) {
         const double mk = eq_comp(t, wp, Q, k, r);
         const double f = (double)fr[k][r] + (mk - eq_comp(t, w, Qm, k, r));
-        fout[(int64_t)(k * M + r) * plane + i] = (T)(f + t.omega * (mk - f));
+        out[k][r] = (T)(f + t.omega * (mk - f));
       }
   } else {
     flux<LAW, D, M, NV>(t, w, Q);
@@ -149,9 +144,24 @@ __device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
       for (int r = 0; r < M; ++r) {
         const double mk = eq_comp(t, w, Q, k, r);
         const double f = (double)fr[k][r];
-        fout[(int64_t)(k * M + r) * plane + i] = (T)(f + t.omega * (mk - f));
+        out[k][r] = (T)(f + t.omega * (mk - f));
       }
   }
+}
+
+template <typename T, int LAW, int D, int M, int NV>
+__device__ __forceinline__ void relax_node(const T* fin, T* fout, int64_t plane,
+                                           const EqTab<D, M, NV>& t, int64_t i) {
+  T fr[NV][M], out[NV][M];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int r = 0; r < M; ++r) fr[k][r] = fin[(int64_t)(k * M + r) * plane + i];
+  relax_values<T, LAW, D, M, NV>(t, fr, out);
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int r = 0; r < M; ++r) fout[(int64_t)(k * M + r) * plane + i] = out[k][r];
 }
 
 template <typename T, int LAW, int D, int M, int NV>
@@ -162,6 +172,40 @@ __global__ __launch_bounds__(256) void k_relax(const T* fin, T* fout, int64_t pl
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= plane) return;
   relax_node<T, LAW, D, M, NV>(fin, fout, plane, *t, i);
+}
+
+// The same with VW consecutive nodes per thread: one 16-byte load and store
+// per (velocity, component) plane (plane divisible by VW).
+template <typename T, int LAW, int D, int M, int NV, int VW>
+__global__ __launch_bounds__(256) void k_relax_vec(const T* fin, T* fout, int64_t plane,
+                                                   const EqTab<D, M, NV>* __restrict__ tp) {
+  const int64_t i0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * VW;
+  if (i0 >= plane) return;
+  struct alignas(16) V { T v[VW]; };
+  V in[NV][M], out[NV][M];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+      in[k][r] = *reinterpret_cast<const V*>(fin + (int64_t)(k * M + r) * plane + i0);
+#pragma unroll
+  for (int u = 0; u < VW; ++u) {
+    T fr[NV][M], o[NV][M];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) fr[k][r] = in[k][r].v[u];
+    relax_values<T, LAW, D, M, NV>(*tp, fr, o);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) out[k][r].v[u] = o[k][r];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+      *reinterpret_cast<V*>(fout + (int64_t)(k * M + r) * plane + i0) = out[k][r];
 }
 
 // Relaxation of many problems of one (law, d, m, n_vel) in one launch; the
@@ -377,10 +421,16 @@ struct EqCombo {
     return hipGetLastError();
   }
   template <typename T>
-  static hipError_t relax(const Geom& g, const void* eq, const void* fin, void* fout, hipStream_t s) {
+  static hipError_t relax(const Geom& g, const void* eq, const void* fin, void* fout, bool vec,
+                          hipStream_t s) {
     const int64_t plane = g.ncell * g.nn;
-    hipLaunchKernelGGL((k_relax<T, LAW, D, M, NV>), dim3(blocks_for(plane)), dim3(256), 0, s,
-                       (const T*)fin, (T*)fout, plane, (const Tab*)eq);
+    constexpr int VW = 16 / sizeof(T);
+    if (vec && plane % VW == 0)
+      hipLaunchKernelGGL((k_relax_vec<T, LAW, D, M, NV, VW>), dim3(blocks_for(plane / VW)), dim3(256),
+                         0, s, (const T*)fin, (T*)fout, plane, (const Tab*)eq);
+    else
+      hipLaunchKernelGGL((k_relax<T, LAW, D, M, NV>), dim3(blocks_for(plane)), dim3(256), 0, s,
+                         (const T*)fin, (T*)fout, plane, (const Tab*)eq);
     return hipGetLastError();
   }
 };
@@ -391,8 +441,8 @@ struct ComboEntry {
                 double, const std::vector<double>&, std::vector<unsigned char>&);
   hipError_t (*init64)(const Geom&, const void*, const double*, void*, hipStream_t);
   hipError_t (*init32)(const Geom&, const void*, const double*, void*, hipStream_t);
-  hipError_t (*relax64)(const Geom&, const void*, const void*, void*, hipStream_t);
-  hipError_t (*relax32)(const Geom&, const void*, const void*, void*, hipStream_t);
+  hipError_t (*relax64)(const Geom&, const void*, const void*, void*, bool, hipStream_t);
+  hipError_t (*relax32)(const Geom&, const void*, const void*, void*, bool, hipStream_t);
   size_t (*task_bytes)();
   void (*pack_task)(const void*, const void*, void*, int64_t, void*);
   hipError_t (*batch64)(const void*, const int64_t*, int, int64_t, hipStream_t);
@@ -473,10 +523,11 @@ hipError_t launch_init(int prec, int law, const Geom& g, const void* eq, const d
 }
 
 hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq, const void* fin,
-                        void* fout, hipStream_t s) {
+                        void* fout, bool vec, hipStream_t s) {
   const ComboEntry* c = combo_of(law, g);
   if (!c) return hipErrorInvalidValue;
-  return prec == KDS_FP64 ? c->relax64(g, eq, fin, fout, s) : c->relax32(g, eq, fin, fout, s);
+  return prec == KDS_FP64 ? c->relax64(g, eq, fin, fout, vec, s)
+                          : c->relax32(g, eq, fin, fout, vec, s);
 }
 
 hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s) {

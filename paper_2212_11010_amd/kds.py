@@ -27,7 +27,7 @@ SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED
              "front": KDS_SCHED_FRONT}
 N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_step_timed",
-            "kds_tune",
+            "kds_tune", "kds_set_launch",
             "kds_time_kernels", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
@@ -58,7 +58,7 @@ class kds_info_t(C.Structure):
         ("max_kinetic_courant", C.c_double), ("min_subdomain_width", C.c_double),
         ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
         ("tuned", C.c_int32), ("line_xdirect", C.c_int32), ("line_lds_bytes", C.c_int32),
-        ("step_eager", C.c_int32),
+        ("step_eager", C.c_int32), ("relax_vec", C.c_int32),
     ]
 
 
@@ -85,6 +85,7 @@ def lib():
         L.kds_step.argtypes = [vp, C.c_int32]
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_tune.argtypes = [vp, C.c_int32, dp]
+        L.kds_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
         L.kds_time_kernels.argtypes = [vp, C.c_int32, dp]
         L.kds_moments.argtypes = [vp, vp, C.c_int32]
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
@@ -223,6 +224,10 @@ def kds_tune(h, reps=3):
     best = C.c_double(0.0)
     _check(lib().kds_tune(h, int(reps), C.byref(best)), h)
     return best.value
+
+
+def kds_set_launch(h, step_eager, relax_vec):
+    _check(lib().kds_set_launch(h, int(step_eager), int(relax_vec)), h)
 
 
 def kds_time_kernels(h, reps=10):
@@ -375,6 +380,9 @@ class Problem:
 
     def time_kernels(self, reps=10):
         return kds_time_kernels(self.h, reps)
+
+    def set_launch(self, step_eager, relax_vec):
+        kds_set_launch(self.h, step_eager, relax_vec)
 
     def moments(self, out=None):
         if out is None:

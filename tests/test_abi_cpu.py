@@ -154,6 +154,7 @@ def test_null_arguments_are_rejected():
     assert L.kds_set_state(None, None, 0) == kds.KDS_E_INVALID
     assert L.kds_moments(None, None, 0) == kds.KDS_E_INVALID
     assert L.kds_synchronize(None) == kds.KDS_E_INVALID
+    assert L.kds_set_launch(None, 0, 0) == kds.KDS_E_INVALID
     L.kds_destroy(None)
 
 

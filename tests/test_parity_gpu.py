@@ -31,6 +31,8 @@ CASES = {
     "cfg4_ragged": (4, dict(n_cells=[10, 6, 9], sub_cells=[5, 3, 3], steps=2)),
     "cfg4_converged": (4, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 2], steps=2, n_iter=0)),
     "cfg3_k1": (3, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=2, n_iter=1)),
+    # an odd node count (135 cells x 27 nodes): the vector relaxation falls back
+    "cfg3_odd": (3, dict(n_cells=[9, 5, 3], sub_cells=[3, 5, 3], steps=2)),
     "cfg2_theta1": (2, dict(n_cells=[32, 16], sub_cells=[8, 16], steps=3, theta=1.0)),
     "cfg2_full_2steps": (2, dict(steps=2)),
     # one subdomain of 34 cells (2 cells per lane, 17-lane scan through
@@ -207,6 +209,35 @@ def test_autotuned_plan_restores_state_and_keeps_parity(name):
         F = pb.get_kinetic()
     print("tuned", name, info["line_Q"], info["line_bw"], "%.4f ms" % ms, flush=True)
     assert relerr(W, Wref) <= TOL["fp32"] and relerr(F, Fref) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("name,sched", [("cfg2_ragged", "line"), ("cfg3_small", "plain"),
+                                        ("cfg2_source", "line"), ("cfg3_odd", "line"),
+                                        ("maxwell_q1_ragged", "front")])
+def test_launch_choices_are_bitwise_equal(name, sched):
+    """The step launch mode (graph replay or enqueued kernels) and the
+    relaxation's access width (one node per thread, or 16-byte accesses over
+    several nodes) change no arithmetic: all four combinations end bitwise
+    equal, and match the oracle (cfg3_odd: a node count that is not a
+    multiple of 4, where the vector relaxation falls back)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    if name in CASES:
+        spec, W0, Fref, Wref = case(name)
+    else:
+        spec, W0, Fref, Wref = front_case(name)
+    outs = []
+    for eager in (0, 1):
+        for vec in (0, 1):
+            with kds.Problem(spec, precision="fp32", schedule=sched) as pb:
+                pb.set_state(torch.from_numpy(W0).cuda())
+                pb.set_launch(eager, vec)
+                assert pb.info()["step_eager"] == eager and pb.info()["relax_vec"] == vec
+                pb.step(spec["steps"])
+                outs.append((pb.get_kinetic(), pb.moments()))
+    for F, W in outs[1:]:
+        assert np.array_equal(F, outs[0][0])
+    assert relerr(outs[0][1], Wref) <= TOL["fp32"] and relerr(outs[0][0], Fref) <= TOL["fp32"]
 
 
 def test_converged_mode_rejected_by_plain_schedule():
