@@ -177,10 +177,10 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * then fewer workgroups per CU (larger LDS allocation), then the step launch
  * mode of kds_step (graph replay or enqueued kernels) and the access width of
  * the relaxation (periodic problems only; whole steps timed); restores the
- * state.  Needs a state.  For the plain and front
- * schedules only the step launch mode is tuned (*sweep_ms = -1).  sweep_ms
- * (nullable): best average sweep time.  Needs one state's worth of free
- * device memory (else KDS_E_NOMEM). */
+ * state.  Needs a state.  For the plain and front schedules only the last two
+ * choices are tuned (*sweep_ms = -1).  sweep_ms (nullable): best average
+ * sweep time.  Needs one state's worth of free device memory (else
+ * KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
 
 /* Sets the two launch choices kds_tune otherwise makes for kds_step:
