@@ -28,7 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "cell-DOF-velocity updates/s per step, FP32-MFMA batched vs plain FP64 sweep"
+# The FP32 form measured on the axis-aligned D2Q4 / D3Q6 workloads is the line
+# schedule (no dense cell operator: no matrix cores); the matrix-core front
+# form of the same step is timed beside it in extra.fp32_mfma_front.
+METRIC = ("cell-DOF-velocity updates/s per step, FP32 line-schedule sweep "
+          "(FP32-MFMA front form in extra) vs plain FP64 sweep")
+INFINITY_CACHE_BYTES = 256 << 20   # MI355X last-level (Infinity) cache
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {"line": "k_sweep_line", "plain": "k_sweep_plain", "front": "k_sweep_front",
                 "relax": "k_relax"}
@@ -79,14 +84,19 @@ def device_copy_gbs(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def time_problem(spec, W0, prec, sched, steps, warmup, tune=False):
+def time_problem(spec, W0, prec, sched, steps, warmup, tune=False, plan=None):
+    """Returns (ms per step, [sweep, relax] ms per launch, info, state finite,
+    launch plan)."""
     import torch
     from paper_2212_11010_amd import kds
     pb = kds.Problem(spec, precision=prec, schedule=sched)
     pb.set_state(torch.from_numpy(W0).cuda())
-    if tune:
+    if plan is not None:
+        pb.set_plan(plan)
+    elif tune:
         pb.tune(3)   # autotuner (setup, outside the timed region); restores the state
     info = pb.info()
+    plan = pb.get_plan()
     pb.step(warmup)
     pb.synchronize()
     torch.cuda.synchronize()
@@ -101,7 +111,33 @@ def time_problem(spec, W0, prec, sched, steps, warmup, tune=False):
     kms = pb.time_kernels(steps)
     ok = pb.check_finite()
     pb.close()
-    return ms_graph, kms, info, ok
+    return ms_graph, kms, info, ok, plan
+
+
+def gpu_state_after(spec, W0, prec, sched, plan, n_steps):
+    """(W, F) after n_steps from W0 with the given launch plan (host FP64)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    with kds.Problem(spec, precision=prec, schedule=sched) as pb:
+        pb.set_plan(plan)
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(n_steps)
+        return pb.moments(), pb.get_kinetic()
+
+
+def rel_errors(W, Wref, F, Fref):
+    """max |x - x_oracle| / max |x_oracle| over all values (W and F), and the
+    same per component of W / per (velocity, component) plane of F, each on
+    its own scale; F in the C ABI layout [k][cell][node][c]."""
+    def planes(a, b, red):
+        # (a plane below 1e-6 of the largest is zero in exact arithmetic:
+        # measured on the global scale)
+        num = np.max(np.abs(a - b), axis=red)
+        pmax, gmax = np.max(np.abs(b), axis=red), np.max(np.abs(b))
+        return float(np.max(num / np.where(pmax >= 1e-6 * gmax, pmax, gmax)))
+    g = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    return {"W": g(W, Wref), "F": g(F, Fref), "W_per_component": planes(W, Wref, (0, 1)),
+            "F_per_plane": planes(F, Fref, (1, 2))}
 
 
 def traffic_record(kernel, wname, prec):
@@ -209,24 +245,59 @@ def gemm_variants(spec, W0, U, steps=2):
     return out
 
 
-def cpu_baseline(spec, W0, budget_s=12.0):
+def host_cpu():
+    """nproc (affinity), os.cpu_count() and the CPU model of this host."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"nproc": nproc, "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(spec, W0, budget_s=10.0):
+    """The FP64 oracle on this host, one thread and all threads (OpenMP over
+    its independent (velocity, component) transports, so at most n_vel * m of
+    them are busy).  Each leg: one untimed step, then about budget_s seconds
+    of full steps.  Returns (record, oracle F after the all-thread leg
+    [k][c][cell][node], steps it took)."""
     from oracle import oracle
-    cfg = oracle.Config(spec)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-    F = oracle.init(cfg, W0)
-    t0 = time.perf_counter()
-    F = oracle.step(cfg, F, 1, threads)
-    t1 = time.perf_counter()
-    one = t1 - t0
-    n = max(1, min(20, int(budget_s / max(one, 1e-3))))
-    t2 = time.perf_counter()
-    F = oracle.step(cfg, F, n, threads)
-    t3 = time.perf_counter()
     from paper_2212_11010_amd import workloads as wl
+    cfg = oracle.Config(spec)
     U = wl.unknowns(spec)
-    return {"value": U * n / (t3 - t2), "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%d full time steps of the same workload (after 1 untimed), FP64 oracle, "
-                      "OpenMP over (velocity, component) transports" % n}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    tasks = spec["n_vel"] * spec["m"]
+    F0 = oracle.init(cfg, W0)
+
+    def leg(nt):
+        F = oracle.step(cfg, F0, 1, nt)
+        t0 = time.perf_counter()
+        F = oracle.step(cfg, F, 1, nt)
+        one = time.perf_counter() - t0
+        n = max(1, min(20, int(budget_s / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        F = oracle.step(cfg, F, n, nt)
+        dt = time.perf_counter() - t0
+        return U * (n + 1) / (dt + one), F, n + 2
+
+    v1, _, n1 = leg(1)
+    vt, F, nt_steps = leg(threads)
+    busy = min(threads, tasks)
+    rec = {"value": vt, "unit": "updates/s", "cores": busy, "kind": "oracle",
+           "threads_requested": threads, "parallel_tasks": tasks,
+           "single_thread_value": v1, "host": host_cpu(),
+           "sample": "%d and %d full time steps of the same workload (one untimed first) on 1 "
+                     "and on %d threads; FP64 oracle (g++ -O2), OpenMP over its %d independent "
+                     "(velocity, component) transports, so at most %d threads busy"
+                     % (n1 - 1, nt_steps - 1, threads, tasks, busy)}
+    return rec, F, nt_steps
 
 
 def bench_batch(args):
@@ -371,6 +442,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-plan autotuner")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the K = 1 and matrix-core front timings")
+    ap.add_argument("--no-hbm-leg", action="store_true",
+                    help="cfg2: skip the 128^3 Euler (HBM-bound) leg")
     ap.add_argument("--no-gemm-variants", action="store_true",
                     help="cfg4: skip the front-schedule GEMM variants (FP32 / FP16 / BF16 split)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -407,27 +482,62 @@ def main():
     U = wl.unknowns(spec)
     log("workload %s U=%d dt=%.5g nu=%.3f" % (spec["name"], U, spec["dt"], spec["kinetic_courant"]))
 
-    ms32, k32, info32, ok32 = time_problem(spec, W0, args.precision, args.schedule, args.steps,
-                                           args.warmup, tune=not args.no_tune)
+    ms32, k32, info32, ok32, plan32 = time_problem(spec, W0, args.precision, args.schedule,
+                                                   args.steps, args.warmup, tune=not args.no_tune)
     sched = {1: "plain", 2: "line", 3: "front"}[info32["schedule"]]
-    log("fp32 %s: %.4f ms/step (graph), kernels %s ms" % (sched, ms32, k32))
+    log("fp32 %s: %.4f ms/step, kernels %s ms" % (sched, ms32, k32))
     extra = {"fp32_schedule": sched, "fp32_kernel_ms": {"sweep": k32[0], "relax": k32[1]},
-             "fp32_state_finite": ok32, "line_plan": {"cells_per_lane": info32["line_Q"][:spec["dim"]],
-                                                      "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
-                                                      "autotuned": bool(info32["tuned"]),
-                                                      "x_direct": bool(info32["line_xdirect"]),
-                                                      "lds_bytes_per_workgroup": info32["line_lds_bytes"],
-                                                      "step_launch": "enqueued" if info32["step_eager"] else "graph",
-                                                      "relax_16byte_access": bool(info32["relax_vec"])}}
+             "fp32_state_finite": ok32, "fp32_plan": plan32,
+             "line_plan": {"cells_per_lane": info32["line_Q"][:spec["dim"]],
+                           "columns_per_workgroup": info32["line_bw"][:spec["dim"]],
+                           "autotuned": bool(info32["tuned"]),
+                           "x_direct": bool(info32["line_xdirect"]),
+                           "lds_bytes_per_workgroup": info32["line_lds_bytes"],
+                           "step_launch": "enqueued" if info32["step_eager"] else "graph",
+                           "relax_16byte_access": bool(info32["relax_vec"])}}
+    if sched == "line":
+        # the line kernel resolves all n_iter subdomain iterations in one launch
+        extra["fp32_sweep_ms_per_iteration_equivalent"] = k32[0] / max(1, spec["n_iter"])
+    plan64 = None
     if not args.no_fp64:
         base = "front" if sched == "front" else "plain"
         # (its step launch mode tuned too, so that both sides launch their best way)
-        ms64, k64, info64, ok64 = time_problem(spec, W0, "fp64", base, max(5, args.steps // 5), 2,
-                                               tune=not args.no_tune)
-        log("fp64 plain: %.4f ms/step, kernels %s ms" % (ms64, k64))
+        ms64, k64, info64, ok64, plan64 = time_problem(spec, W0, "fp64", base,
+                                                       max(5, args.steps // 5), 2,
+                                                       tune=not args.no_tune)
+        log("fp64 %s: %.4f ms/step, kernels %s ms" % (base, ms64, k64))
         extra.update({"fp64_plain_value": U / (ms64 * 1e-3), "fp64_plain_ms_per_step": ms64,
-                      "fp64_plain_kernel_ms": {"sweep": k64[0], "relax": k64[1]},
+                      "fp64_plain_kernel_ms": {"sweep_per_iteration": k64[0], "relax": k64[1]},
+                      "fp64_plain_launch": {
+                          "step_launch": "enqueued" if info64["step_eager"] else "graph",
+                          "relax_16byte_access": bool(info64["relax_vec"])},
+                      "fp64_plain_state_finite": ok64,
                       "speedup_fp32_vs_fp64_plain": ms64 / ms32})
+    if sched == "line" and not args.no_extra_legs:
+        # one subdomain iteration per step (K = 1): the step time the lag of
+        # interface data alone costs
+        spec1 = dict(spec, n_iter=1)
+        ms1, k1, _, ok1, _ = time_problem(spec1, W0, args.precision, "auto", args.steps,
+                                          args.warmup, tune=not args.no_tune)
+        extra["k1_step"] = {"ms_per_step": ms1, "value": U / (ms1 * 1e-3), "sweep_ms": k1[0],
+                            "relax_ms": k1[1], "state_finite": ok1}
+        log("fp32 K=1: %.4f ms/step" % ms1)
+        if spec["dim"] == 2 or U < 2e8:
+            # the same step in the matrix-core form: fronts of the cell graph,
+            # one dense GEMM (FP32 MFMA) per front, one launch per iteration
+            msf, kf, _, okf, _ = time_problem(spec, W0, "fp32", "front", max(5, args.steps // 5),
+                                              2, tune=not args.no_tune)
+            P = spec["degree"] + 1
+            nn = P ** spec["dim"]
+            Kd = nn + 3 * (nn // P)
+            tf = 2.0 * Kd * U / (kf[0] * 1e-3) / 1e12
+            extra["fp32_mfma_front"] = {
+                "ms_per_step": msf, "value": U / (msf * 1e-3), "sweep_ms_per_iteration": kf[0],
+                "relax_ms": kf[1], "executed_tflops": tf, "peak_tflops": MFMA_PEAK_TFS["fp32"],
+                "frac": tf / MFMA_PEAK_TFS["fp32"], "state_finite": okf,
+                "note": "executed flops 2 (nn + 3 nf) per unknown and iteration (dense cell "
+                        "operator); the axis-aligned velocities need ~2(p+1)+4 per unknown"}
+            log("fp32 MFMA front: %.4f ms/step" % msf)
 
     # dominant kernel and its algorithmic bytes: one read + one write of the
     # FP32 state per launch (sweep) -- see the design doc for the per-unknown figures
@@ -437,10 +547,16 @@ def main():
     alg_bytes = U * bytes_per_unknown
     dur_s = (k32[0] if dom == "sweep" else k32[1]) * 1e-3
     achieved = alg_bytes / dur_s / 1e9
+    state_bytes = info32["state_bytes"]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(kname, args.workload, "fp32"),
             "kernel": kname, "algorithmic_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": dur_s * 1e3}
+            "avg_launch_ms": dur_s * 1e3, "state_bytes": state_bytes,
+            "cache_resident": state_bytes <= INFINITY_CACHE_BYTES}
+    if roof["cache_resident"]:
+        roof["note"] = ("the %.1f MB state fits the 256 MB Infinity Cache: the fraction is of the "
+                        "HBM peak, the bytes mostly come from the cache (extra.hbm_leg_cfg3 is the "
+                        "HBM-bound case)" % (state_bytes / 1e6))
 
     roof["device_copy_gbs"] = device_copy_gbs()  # context: what a plain copy reaches
     # whole-step traffic: this schedule's algorithmic bytes per unknown, and
@@ -467,6 +583,8 @@ def main():
                                "hbm_gbs_algorithmic": 8.0 * U / sweep_s / 1e9}
     if args.workload == "cfg4" and sched != "front" and not args.no_gemm_variants:
         extra["front_gemm_variants"] = gemm_variants(spec, W0, U)
+    if args.workload == "cfg2" and not args.no_hbm_leg and args.cells == 0:
+        extra["hbm_leg_cfg3"] = hbm_leg(args)
     out = {
         "metric": METRIC, "value": U / (ms32 * 1e-3), "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
@@ -474,7 +592,7 @@ def main():
         "dtype": {"fp32": "f32", "fp32_split_f16": "f32 (f16x3 products)",
                   "fp32_split_bf16": "f32 (bf16x3 products)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": spec["name"], "n_cells": spec["n_cells"][:spec["dim"]],
+        "config": {"workload": spec["name"], "schedule": sched, "n_cells": spec["n_cells"][:spec["dim"]],
                    "sub_cells": spec["sub_cells"][:spec["dim"]], "degree": spec["degree"],
                    "m": spec["m"], "n_vel": spec["n_vel"], "n_iter": spec["n_iter"],
                    "omega": spec["omega"], "cfl": spec["beta"], "unknowns": U},
@@ -482,8 +600,50 @@ def main():
         "extra": extra,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, W0)
+        rec, Forc, n_orc = cpu_baseline(spec, W0)
+        out["cpu_baseline"] = rec
+        # the measured paths against the oracle's state after the same steps
+        # (the all-thread leg's): the FP32 path with the timed plan, and the
+        # FP64 plain leg
+        from oracle import oracle
+        Wo = oracle.moments(oracle.Config(spec), Forc)
+        Fo = np.ascontiguousarray(Forc.transpose(0, 2, 3, 1))
+        del Forc
+        err = {"steps": n_orc}
+        Wg, Fg = gpu_state_after(spec, W0, args.precision, args.schedule, plan32, n_orc)
+        err["fp32"] = rel_errors(Wg, Wo, Fg, Fo)
+        if plan64 is not None:
+            base = "front" if sched == "front" else "plain"
+            Wg, Fg = gpu_state_after(spec, W0, "fp64", base, plan64, n_orc)
+            err["fp64_plain"] = rel_errors(Wg, Wo, Fg, Fo)
+        err["tolerance"] = {"fp32": 1e-5, "fp64": 1e-12}
+        extra["error_vs_fp64_oracle"] = err
+        log("error vs oracle after %d steps: %s" % (n_orc, err))
     print(json.dumps(out), flush=True)
+
+
+def hbm_leg(args):
+    """The 128^3 Euler p = 2 workload (6.8 GB FP32 state, HBM-bound): the
+    FP32 step with the tuned plan, its kernels and their HBM fractions."""
+    from paper_2212_11010_amd import workloads as wl
+    t0 = time.perf_counter()
+    spec, W0 = workload("cfg3")
+    log("cfg3 state sampled in %.1f s" % (time.perf_counter() - t0))
+    U = wl.unknowns(spec)
+    ms, k, info, ok, plan = time_problem(spec, W0, "fp32", "auto", args.steps, args.warmup,
+                                         tune=not args.no_tune)
+    del W0
+    sched = {1: "plain", 2: "line", 3: "front"}[info["schedule"]]
+    log("cfg3 fp32 %s: %.3f ms/step, kernels %s ms" % (sched, ms, k))
+    gbs = lambda b, ms_: b / (ms_ * 1e-3) / 1e9
+    return {"workload": spec["name"], "n_cells": spec["n_cells"], "sub_cells": spec["sub_cells"],
+            "degree": spec["degree"], "unknowns": U, "schedule": sched, "plan": plan,
+            "ms_per_step": ms, "value": U / (ms * 1e-3), "sweep_ms": k[0], "relax_ms": k[1],
+            "sweep_hbm_frac": gbs(8.0 * U, k[0]) / HBM_PEAK_GBS,
+            "relax_hbm_frac": gbs(8.0 * U, k[1]) / HBM_PEAK_GBS,
+            "step_hbm_frac": gbs(16.0 * U, ms) / HBM_PEAK_GBS,
+            "literal_scheme_step_frac": gbs(32.0 * U, ms) / HBM_PEAK_GBS,
+            "state_bytes": info["state_bytes"], "state_finite": ok}
 
 
 if __name__ == "__main__":

@@ -192,6 +192,38 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
  * KDS_E_INVALID for a NULL problem or a flag other than 0 / 1. */
 kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec);
 
+/* The complete launch plan of a problem: every choice kds_tune makes.  For
+ * the line schedule (Sec. 5.1 iterations of whole grid lines, one wavefront
+ * per line): per grid axis a, Q[a] cells per lane (Q[a] divides sub_cells[a],
+ * n_cells[a] / Q[a] <= 64, Q[a] <= kds_info_t.line_qmax) and bw[a] columns of
+ * cells per workgroup; xdirect = 1 lets x lines with Q[0] = line_qmax be read
+ * and written straight between HBM and registers (no LDS tile); lds_bytes =
+ * LDS allocated per workgroup (0: what the tile needs; more lets fewer
+ * workgroups share a CU).  Axes that carry no velocity have Q = bw = 0.  For
+ * the plain and front schedules these fields are 0 (kds_get_plan) and
+ * ignored (kds_set_plan).  step_eager and relax_vec as in kds_set_launch.
+ * The FP64 results of every valid plan agree to rounding; FP32 results depend
+ * on Q (the association of the line scan), so a plan saved with kds_get_plan
+ * and restored with kds_set_plan reproduces results bitwise across runs. */
+typedef struct {
+  int32_t Q[3];
+  int32_t bw[3];
+  int32_t xdirect;
+  int32_t lds_bytes;
+  int32_t step_eager;
+  int32_t relax_vec;
+} kds_plan_t;
+
+/* Current plan into *plan.  KDS_E_INVALID for NULL arguments. */
+kds_status kds_get_plan(const kds_problem* p, kds_plan_t* plan);
+
+/* Replace the plan.  Errors (the plan is left unchanged): KDS_E_INVALID for
+ * NULL arguments, flags other than 0 / 1, a line-schedule choice outside the
+ * limits above (xdirect = 1 needs a velocity along x with Q[0] = line_qmax),
+ * or lds_bytes above the device's per-workgroup LDS; Q and bw entries of an
+ * axis without velocities are ignored. */
+kds_status kds_set_plan(kds_problem* p, const kds_plan_t* plan);
+
 /* Average duration of one launch of each kernel kind (sweep: the line kernel,
  * or one plain subdomain iteration; relax), from HIP events around reps
  * back-to-back launches on the problem's stream; the state is saved before
@@ -231,6 +263,8 @@ typedef struct {
                              replaying a captured graph (kds_tune's choice) */
   int32_t relax_vec;      /* relaxation with 16-byte accesses, several nodes
                              per thread (kds_tune's choice) */
+  int32_t line_qmax;      /* line schedule: most cells per lane (register
+                             budget of 64 state values per lane), 0 otherwise */
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

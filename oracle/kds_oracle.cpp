@@ -617,6 +617,35 @@ int orc_transport(const orc_config* c, int k, const double* f_old, double* f_new
   return transport_scalar(c, op, V, f_old, f_new, fb_old, fb_new);
 }
 
+// Transport of n_lines independent scalar fields of the 1-D problem c
+// (dim = 1, periodic): line l is f[l][cell][node], carried at velocity
+// v[l]; each line is exactly orc_transport of a one-velocity copy of c.  A
+// test helper for the sampled full-size checks, where the transport along
+// every grid line through the sampled cells is needed (an axis-aligned
+// velocity transports each node line on its own); OpenMP over the lines
+// (n_threads > 0), no change of arithmetic.
+int orc_transport_lines(const orc_config* c, int n_lines, const double* v, const double* f_old,
+                        double* f_new, int n_threads) {
+  if (validate(c) || c->dim != 1 || n_lines < 0 || !v) return 1;
+  if (c->periodic && c->periodic[0] != 1) return 1;
+  const long len = (long)c->n_cells[0] * P_of(c);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : err)
+  for (int l = 0; l < n_lines; ++l) {
+    orc_config cl = *c;
+    cl.n_vel = 1;
+    cl.vel = v + l;
+    CellOp op = build_cell_op(&cl, cl.vel);
+    err |= transport_scalar(&cl, op, cl.vel, f_old + l * len, f_new + l * len, nullptr, nullptr);
+  }
+  return err;
+}
+
 // Number of boundary nodes (faces of the non-periodic axes).
 long orc_n_boundary_nodes(const orc_config* c) {
   if (validate(c)) return -1;

@@ -63,6 +63,7 @@ def lib():
         _lib.orc_equilibrium.argtypes = [cp, dp, dp]
         _lib.orc_cell_residual.argtypes = [cp, dp, dp, dp, dp]
         _lib.orc_transport.argtypes = [cp, C.c_int, dp, dp, dp, dp]
+        _lib.orc_transport_lines.argtypes = [cp, C.c_int, dp, dp, dp, C.c_int]
         _lib.orc_n_boundary_nodes.argtypes = [cp]
         _lib.orc_n_boundary_nodes.restype = C.c_long
         _lib.orc_init.argtypes = [cp, dp, dp]
@@ -190,6 +191,18 @@ def transport(cfg: Config, k: int, f_old, fb_old=None, fb_new=None):
     bo, po = _opt(fb_old)
     bn, pn = _opt(fb_new)
     _check(lib().orc_transport(cfg.ref, k, _dp(f_old), _dp(out), po, pn), "transport")
+    return out
+
+
+def transport_lines(cfg: Config, v, f_old, threads: int = 0):
+    """Transport of many independent fields f[line, cell, node] of the 1-D
+    periodic problem cfg (dim = 1), line l at velocity v[l]."""
+    f_old = np.ascontiguousarray(f_old, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert cfg.dim == 1 and f_old.ndim == 3 and f_old.shape[0] == v.shape[0]
+    out = np.zeros_like(f_old)
+    _check(lib().orc_transport_lines(cfg.ref, int(v.shape[0]), _dp(v), _dp(f_old), _dp(out),
+                                     int(threads)), "transport_lines")
     return out
 
 

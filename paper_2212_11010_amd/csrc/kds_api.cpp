@@ -830,6 +830,11 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
     return fail(p, KDS_E_NOMEM, "kds_tune: no device memory to save the state");
   }
   KDS_HIP(p, hipMemcpyAsync(save, p->f, bytes, hipMemcpyDeviceToDevice, p->stream));
+  // the choices before tuning, restored if the tuner fails part way
+  const LinePlan plan0 = p->plan;
+  int Q0[3], bw0[3];
+  for (int a = 0; a < 3; ++a) { Q0[a] = p->line_Q[a]; bw0[a] = p->line_bw[a]; }
+  const bool eager0 = p->eager_steps, vec0 = p->relax_vec;
   kds_status st = KDS_OK;
   auto time_plan = [&](const LinePlan& pl, float* ms) -> bool {
     hipError_t e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->bnd(),
@@ -876,8 +881,10 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
       }
   }
   // x lines: the direct register path where it is clearly faster than the
-  // LDS tile (both timed again, back to back)
-  if (ok && line && used[0]) {
+  // LDS tile (both timed again, back to back); it applies to x lines with
+  // line_qmax cells per lane, outside grouped mode
+  if (ok && line && used[0] && !line_grouped(p->nn) &&
+      p->line_Q[0] == line_qmax((int)p->elem, p->nn)) {
     LinePlan pl = p->plan;
     pl.xdirect = 1;
     float ms_tile = 0.0f, ms_direct = 0.0f;
@@ -910,6 +917,15 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   // accesses against one node per thread.  Whole steps, timed with events on
   // the stream, twice each.  Not for Dirichlet axes, whose steps also advance
   // the boundary data.
+  if (ok && p->nbnd == 0) {
+    // whole steps start from the saved state (the plan search above swept it
+    // in place, without relaxing)
+    hipError_t er = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (er != hipSuccess) {
+      st = hip_fail(p, er, "kds_tune");
+      ok = false;
+    }
+  }
   if (ok && p->nbnd == 0) {
     int nrep = 1;
     // ms per kGraphSteps * nrep steps in the current mode (graph or enqueued)
@@ -967,8 +983,14 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   hipError_t e = hipMemcpyAsync(p->f, save, bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   (void)hipFree(save);
-  if (!ok) return st;
-  if (e != hipSuccess) return hip_fail(p, e, "kds_tune restore");
+  if (!ok || e != hipSuccess) {
+    p->plan = plan0;
+    for (int a = 0; a < 3; ++a) { p->line_Q[a] = Q0[a]; p->line_bw[a] = bw0[a]; }
+    p->eager_steps = eager0;
+    p->relax_vec = vec0;
+    drop_graphs(p);
+    return ok ? hip_fail(p, e, "kds_tune restore") : st;
+  }
   drop_graphs(p);
   p->tuned = line;
   if (line) ++p->plan_version;
@@ -983,6 +1005,69 @@ kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec)
   p->eager_steps = step_eager == 1;
   p->relax_vec = relax_vec == 1;
   drop_graphs(p);  // captured with the previous relaxation kernel
+  return KDS_OK;
+}
+
+kds_status kds_get_plan(const kds_problem* p, kds_plan_t* pl) {
+  if (!p || !pl) return fail(nullptr, KDS_E_INVALID, "NULL argument");
+  std::memset(pl, 0, sizeof(*pl));
+  if (p->sched == KDS_SCHED_LINE) {
+    for (int k = 0; k < p->nv; ++k) {
+      const int a = axis_of(p, k);
+      pl->Q[a] = p->line_Q[a];
+      pl->bw[a] = p->line_bw[a];
+    }
+    pl->xdirect = p->plan.xdirect;
+    pl->lds_bytes = p->plan.lds_alloc > p->plan.lds_elems ? p->plan.lds_alloc * (int)p->elem : 0;
+  }
+  pl->step_eager = p->eager_steps ? 1 : 0;
+  pl->relax_vec = p->relax_vec ? 1 : 0;
+  return KDS_OK;
+}
+
+kds_status kds_set_plan(kds_problem* p, const kds_plan_t* pl) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!pl) return fail(p, KDS_E_INVALID, "plan is NULL");
+  auto flag = [](int32_t v) { return v == 0 || v == 1; };
+  if (!flag(pl->xdirect) || !flag(pl->step_eager) || !flag(pl->relax_vec) || pl->lds_bytes < 0)
+    return fail(p, KDS_E_INVALID, "kds_set_plan: flags must be 0 or 1 and lds_bytes >= 0");
+  if (p->sched == KDS_SCHED_LINE) {
+    bool used[3] = {false, false, false};
+    for (int k = 0; k < p->nv; ++k) used[axis_of(p, k)] = true;
+    int tq[3], tb[3];
+    for (int a = 0; a < 3; ++a) {
+      tq[a] = used[a] ? pl->Q[a] : p->line_Q[a];
+      tb[a] = used[a] ? pl->bw[a] : p->line_bw[a];
+      if (used[a] && !line_choice_ok(p, a, tq[a], tb[a]))
+        return fail(p, KDS_E_INVALID,
+                    "kds_set_plan: cells per lane / columns per workgroup outside the limits on axis " +
+                        std::to_string(a));
+    }
+    LinePlan np;
+    if (!finalize_plan(p, tq, tb, np)) return fail(p, KDS_E_INVALID, "kds_set_plan: launch plan out of range");
+    if (pl->xdirect) {
+      if (!used[0] || line_grouped(p->nn) || tq[0] != line_qmax((int)p->elem, p->nn))
+        return fail(p, KDS_E_INVALID,
+                    "kds_set_plan: xdirect needs a velocity along x and Q[0] = line_qmax "
+                    "(and cells of at most 27 nodes)");
+      np.xdirect = 1;
+    }
+    if (pl->lds_bytes > 0) {
+      const int el = pl->lds_bytes / (int)p->elem;
+      if (pl->lds_bytes > p->lds_cap || el < np.lds_elems)
+        return fail(p, KDS_E_INVALID,
+                    "kds_set_plan: lds_bytes must cover the tile (" +
+                        std::to_string(np.lds_elems * (int)p->elem) + " bytes) and fit the device (" +
+                        std::to_string(p->lds_cap) + " bytes)");
+      np.lds_alloc = el;
+    }
+    for (int a = 0; a < 3; ++a) { p->line_Q[a] = tq[a]; p->line_bw[a] = tb[a]; }
+    p->plan = np;
+    ++p->plan_version;
+  }
+  p->eager_steps = pl->step_eager == 1;
+  p->relax_vec = pl->relax_vec == 1;
+  drop_graphs(p);
   return KDS_OK;
 }
 
@@ -1128,6 +1213,7 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
   info->step_eager = p->eager_steps ? 1 : 0;
   info->relax_vec = p->relax_vec ? 1 : 0;
   info->line_xdirect = p->sched == KDS_SCHED_LINE ? p->plan.xdirect : 0;
+  info->line_qmax = p->sched == KDS_SCHED_LINE ? line_qmax((int)p->elem, p->nn) : 0;
   info->line_lds_bytes =
       p->sched == KDS_SCHED_LINE
           ? (int32_t)(std::max(p->plan.lds_elems, p->plan.lds_alloc) * (int)p->elem)

@@ -222,15 +222,18 @@ __global__ __launch_bounds__(256) void k_relax_batch(const RelaxTask<D, M, NV>* 
   relax_node<T, LAW, D, M, NV>((const T*)t.fin, (T*)t.fout, t.plane, t.t, i);
 }
 
+// W = sum_k f_k (FP64) at the nodes i0 .. i0 + n - 1, written W[(i - i0) m + r].
 template <typename T>
 __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ f, double* __restrict__ W,
-                                                 int64_t plane, int m, int nv) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= plane) return;
+                                                 int64_t plane, int64_t i0, int64_t n, int m,
+                                                 int nv) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = i0 + j;
   for (int r = 0; r < m; ++r) {
     double s = 0.0;
     for (int k = 0; k < nv; ++k) s += (double)f[(int64_t)(k * m + r) * plane + i];
-    W[i * m + r] = s;
+    W[j * m + r] = s;
   }
 }
 
@@ -530,16 +533,24 @@ hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq, const 
                           : c->relax32(g, eq, fin, fout, vec, s);
 }
 
-hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s) {
+hipError_t launch_moments_range(int prec, const Geom& g, const void* f, int64_t i0, int64_t n,
+                                double* W, hipStream_t s) {
   const int64_t plane = g.ncell * g.nn;
+  if (i0 < 0 || n < 0 || i0 + n > plane) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
   if (prec == KDS_FP64)
-    hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(plane)), dim3(256), 0, s,
-                       (const double*)f, W, plane, g.m, g.nv);
+    hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       (const double*)f, W, plane, i0, n, g.m, g.nv);
   else
-    hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(plane)), dim3(256), 0, s,
-                       (const float*)f, W, plane, g.m, g.nv);
+    hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       (const float*)f, W, plane, i0, n, g.m, g.nv);
   return hipGetLastError();
 }
+
+hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s) {
+  return launch_moments_range(prec, g, f, 0, g.ncell * g.nn, W, s);
+}
+
 
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s) {
   const int64_t plane = g.ncell * g.nn;

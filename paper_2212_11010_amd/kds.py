@@ -27,7 +27,7 @@ SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED
              "front": KDS_SCHED_FRONT}
 N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_step_timed",
-            "kds_tune", "kds_set_launch",
+            "kds_tune", "kds_set_launch", "kds_get_plan", "kds_set_plan",
             "kds_time_kernels", "kds_moments",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
@@ -58,7 +58,14 @@ class kds_info_t(C.Structure):
         ("max_kinetic_courant", C.c_double), ("min_subdomain_width", C.c_double),
         ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
         ("tuned", C.c_int32), ("line_xdirect", C.c_int32), ("line_lds_bytes", C.c_int32),
-        ("step_eager", C.c_int32), ("relax_vec", C.c_int32),
+        ("step_eager", C.c_int32), ("relax_vec", C.c_int32), ("line_qmax", C.c_int32),
+    ]
+
+
+class kds_plan_t(C.Structure):
+    _fields_ = [
+        ("Q", C.c_int32 * 3), ("bw", C.c_int32 * 3), ("xdirect", C.c_int32),
+        ("lds_bytes", C.c_int32), ("step_eager", C.c_int32), ("relax_vec", C.c_int32),
     ]
 
 
@@ -86,6 +93,8 @@ def lib():
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_tune.argtypes = [vp, C.c_int32, dp]
         L.kds_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+        L.kds_get_plan.argtypes = [vp, C.POINTER(kds_plan_t)]
+        L.kds_set_plan.argtypes = [vp, C.POINTER(kds_plan_t)]
         L.kds_time_kernels.argtypes = [vp, C.c_int32, dp]
         L.kds_moments.argtypes = [vp, vp, C.c_int32]
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
@@ -230,6 +239,33 @@ def kds_set_launch(h, step_eager, relax_vec):
     _check(lib().kds_set_launch(h, int(step_eager), int(relax_vec)), h)
 
 
+def _struct_dict(st):
+    out = {}
+    for name, _ in st._fields_:
+        v = getattr(st, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+def kds_get_plan(h):
+    pl = kds_plan_t()
+    _check(lib().kds_get_plan(h, C.byref(pl)), h)
+    return _struct_dict(pl)
+
+
+def kds_set_plan(h, plan):
+    """plan: a dict with the fields of kds_plan_t (missing fields: 0)."""
+    pl = kds_plan_t()
+    for name, _ in kds_plan_t._fields_:
+        v = plan.get(name, 0)
+        if isinstance(v, (list, tuple)):
+            for i, x in enumerate(v):
+                getattr(pl, name)[i] = int(x)
+        else:
+            setattr(pl, name, int(v))
+    _check(lib().kds_set_plan(h, C.byref(pl)), h)
+
+
 def kds_time_kernels(h, reps=10):
     out = (C.c_double * N_KERNEL_KINDS)()
     _check(lib().kds_time_kernels(h, int(reps), out), h)
@@ -268,11 +304,7 @@ def kds_synchronize(h):
 def kds_info(h):
     info = kds_info_t()
     _check(lib().kds_info(h, C.byref(info)), h)
-    out = {}
-    for name, _ in kds_info_t._fields_:
-        v = getattr(info, name)
-        out[name] = list(v) if hasattr(v, "__len__") else v
-    return out
+    return _struct_dict(info)
 
 
 def kds_destroy(h):
@@ -383,6 +415,12 @@ class Problem:
 
     def set_launch(self, step_eager, relax_vec):
         kds_set_launch(self.h, step_eager, relax_vec)
+
+    def get_plan(self):
+        return kds_get_plan(self.h)
+
+    def set_plan(self, plan):
+        kds_set_plan(self.h, plan)
 
     def moments(self, out=None):
         if out is None:

@@ -37,10 +37,12 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     fields = [n for n, _ in kds.kds_config._fields_]
     ifields = [n for n, _ in kds.kds_info_t._fields_]
+    pfields = [n for n, _ in kds.kds_plan_t._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kds.h"', "int main(void) {",
-             'printf("%zu %zu\\n", sizeof(kds_config), sizeof(kds_info_t));']
+             'printf("%zu %zu %zu\\n", sizeof(kds_config), sizeof(kds_info_t), sizeof(kds_plan_t));']
     lines += ['printf("%%zu\\n", offsetof(kds_config, %s));' % f for f in fields]
     lines += ['printf("%%zu\\n", offsetof(kds_info_t, %s));' % f for f in ifields]
+    lines += ['printf("%%zu\\n", offsetof(kds_plan_t, %s));' % f for f in pfields]
     lines += ["return 0; }"]
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -48,9 +50,12 @@ def test_struct_layout_matches_header(tmp_path):
     out = subprocess.check_output([str(exe)]).decode().split()
     assert int(out[0]) == C.sizeof(kds.kds_config)
     assert int(out[1]) == C.sizeof(kds.kds_info_t)
-    offs = [int(v) for v in out[2:]]
-    assert offs[:len(fields)] == [getattr(kds.kds_config, f).offset for f in fields]
-    assert offs[len(fields):] == [getattr(kds.kds_info_t, f).offset for f in ifields]
+    assert int(out[2]) == C.sizeof(kds.kds_plan_t)
+    offs = [int(v) for v in out[3:]]
+    nf, ni = len(fields), len(ifields)
+    assert offs[:nf] == [getattr(kds.kds_config, f).offset for f in fields]
+    assert offs[nf:nf + ni] == [getattr(kds.kds_info_t, f).offset for f in ifields]
+    assert offs[nf + ni:] == [getattr(kds.kds_plan_t, f).offset for f in pfields]
 
 
 def _create_status(spec, **kw):
@@ -155,6 +160,8 @@ def test_null_arguments_are_rejected():
     assert L.kds_moments(None, None, 0) == kds.KDS_E_INVALID
     assert L.kds_synchronize(None) == kds.KDS_E_INVALID
     assert L.kds_set_launch(None, 0, 0) == kds.KDS_E_INVALID
+    assert L.kds_get_plan(None, None) == kds.KDS_E_INVALID
+    assert L.kds_set_plan(None, None) == kds.KDS_E_INVALID
     L.kds_destroy(None)
 
 

@@ -12,9 +12,14 @@ import functools
 import numpy as np
 import pytest
 
+from tests import parity as pt
+
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_split_f16": 1e-5, "fp32_split_bf16": 1e-4}
+# per plane on its own scale (BF16 split products: ~2^-16 of sum |W_ij| |X_j|,
+# up to ~30x a small component's own scale; see test_parity_gpu.FRONT_TOL_PLANE)
+TOL_PLANE = {"fp32_split_bf16": 5e-4}
 
 CASES = {
     # name: (cfg, overrides, schedules)
@@ -63,8 +68,7 @@ def case(name):
     return spec, W0, B, np.ascontiguousarray(F.transpose(0, 2, 3, 1)), W
 
 
-def relerr(a, b):
-    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+relerr = pt.relerr
 
 
 PARAMS = [(name, sched, prec) for name, (_, _, scheds) in CASES.items() for sched in scheds
@@ -90,9 +94,7 @@ def test_dirichlet_parity_against_oracle(name, sched, prec):
             pb.set_boundary(B[s + 1] if s % 2 == 0 else torch.from_numpy(B[s + 1]).cuda())
             pb.step(1)
         W, F = pb.moments(), pb.get_kinetic()
-    ew, ef = relerr(W, Wref), relerr(F, Fref)
-    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
-    assert ew <= TOL[prec] and ef <= TOL[prec], (ew, ef)
+    pt.check(W, Wref, F, Fref, TOL[prec], tol_plane=TOL_PLANE.get(prec))
 
 
 def test_constant_boundary_multi_step_graph_matches_single_steps():

@@ -677,3 +677,133 @@ def test_dirichlet_plane_wave_second_order_in_time(orc):
         errs.append(np.max(np.abs(W - wl.w_plane_wave(wl.node_coords(spec), T))))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert r1 > 3.3 and r2 > 3.3, errs
+
+
+# ------------------------------------------ finite-K budget, space order, entropy
+
+def _budget_terms(orc, dim, N, S, p, V, theta, K, seed):
+    """(change of sum_nodes h^d w f over one transport step with K subdomain
+    iterations, the interface term of the budget identity, scale)."""
+    rng = np.random.default_rng(seed)
+    pad = lambda x, v: list(x) + [v] * (3 - len(x))
+    spec = {"dim": dim, "n_cells": pad(N, 1), "sub_cells": pad(S, 1), "box_lo": [0.0] * 3,
+            "box_hi": [1.0] * 3, "degree": p, "m": 1, "law": 0, "law_params": [0.0] * dim,
+            "n_vel": 1, "vel": list(V), "omega": 1.0, "dt": 0.37, "theta": theta, "n_iter": K}
+    P, nn, ncell = p + 1, (p + 1) ** dim, int(np.prod(N))
+    f0 = rng.normal(size=(ncell, nn))
+    fK = orc.transport(orc.Config(spec), 0, f0)
+    # iterate K - 1 (iterate 0 is the state at the start of the step)
+    fKm = orc.transport(orc.Config(dict(spec, n_iter=K - 1)), 0, f0) if K > 1 else f0
+    _, w = orc.gl(p)
+    h = [1.0 / n for n in N]
+    vol = float(np.prod(h))
+    idx = np.indices((P,) * dim).reshape(dim, -1)[::-1]          # node -> index per axis
+    cc = np.indices(tuple(N[::-1])).reshape(dim, -1)[::-1]       # cell -> coordinate per axis
+    wn = np.ones(nn)
+    for a in range(dim):
+        wn = wn * w[idx[a]]
+    lhs = vol * np.sum((fK - f0) * wn[None, :])
+    rhs = 0.0
+    for a in range(dim):
+        if V[a] == 0:
+            continue
+        wf = wn / w[idx[a]]                       # weights over the face's tangential axes
+        # interface faces along a (subdomain boundaries and the periodic wrap):
+        # the upwind cell and its outflow face nodes
+        if V[a] > 0:
+            cells, on = np.flatnonzero((cc[a] + 1) % S[a] == 0), idx[a] == P - 1
+        else:
+            cells, on = np.flatnonzero(cc[a] % S[a] == 0), idx[a] == 0
+        rhs += abs(V[a]) * (vol / h[a]) * np.sum((fK - fKm)[cells][:, on] * wf[on][None, :])
+    rhs *= -spec["dt"] * theta
+    return lhs, rhs, vol * np.sum(np.abs(f0) * wn[None, :])
+
+
+@pytest.mark.parametrize("dim,N,S,p,V,theta,K", [
+    (1, [12], [4], 2, [1.3], 0.5, 3),
+    (1, [10], [5], 3, [-2.0], 1.0, 1),
+    (2, [8, 6], [4, 3], 1, [1.0, 0.0], 0.5, 2),
+    (2, [8, 6], [4, 3], 2, [0.7, -0.4], 1.0, 3),
+    (2, [8, 8], [8, 8], 3, [1.0, 0.6], 0.5, 3),
+    (3, [4, 4, 4], [2, 2, 4], 1, [0.5, -0.5, 0.5], 0.5, 1),
+    (3, [4, 6, 4], [2, 3, 2], 2, [0.0, 0.0, -1.1], 0.5, 4),
+])
+def test_finite_k_budget_identity(orc, dim, N, S, p, V, theta, K):
+    """With lagged interface data the transport conserves the weighted sum of
+    f only up to the interface defect (the subdomain iteration of Sec. 5.1
+    eq:ibvp, iterate 0 = the state at t^{n-1}): summing the cell equations of
+    eq:dg_imp (theta-scheme, collocated quadrature), the volume terms vanish
+    and the upwind fluxes cancel on faces inside a subdomain, so
+        sum h^d w (f^(K) - f^{n-1})
+          = -dt theta sum_{interface faces} (V.N) h^(d-1) sum_face w (tr^(K) - tr^(K-1)),
+    tr = the upwind cell's outflow face values.  Closes to rounding for every
+    K, theta and velocity direction; zero only once the iterates converge."""
+    lhs, rhs, scale = _budget_terms(orc, dim, N, S, p, V, theta, K, seed=K + 7 * dim)
+    assert abs(lhs - rhs) <= 1e-14 * scale, (lhs, rhs)
+    assert abs(lhs) > 1e-6 * scale       # the defect is real at finite K
+
+
+def _space_error(orc, N, p, dt=5e-5, T=0.05, a=1.0, lam=2.0):
+    """L2 error of W against the exact translate after time T, omega = 2,
+    converged transport, a time step small enough that the time error is far
+    below the space error."""
+    nsteps = int(round(T / dt))
+    spec = {
+        "dim": 1, "n_cells": [N, 1, 1], "sub_cells": [N // 4, 1, 1], "box_lo": [0.0] * 3,
+        "box_hi": [1.0] * 3, "degree": p, "m": 1, "law": 0, "law_params": [a],
+        "n_vel": 2, "vel": [lam, -lam], "omega": 2.0, "dt": T / nsteps, "theta": 0.5,
+        "n_iter": 0,
+    }
+    X = wl.node_coords(spec)
+    _, W = orc.run(spec, np.sin(2 * np.pi * X[..., 0])[..., None], nsteps)
+    exact = np.sin(2 * np.pi * (X[..., 0] - a * T))
+    _, w = orc.gl(p)
+    return math.sqrt(np.sum((W[..., 0] - exact) ** 2 * w[None, :]) / N)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_space_order_is_p_plus_1(orc, p):
+    """Degree-p DG on Gauss-Lobatto nodes converges in space with order p + 1
+    (Sec. 6: the degree-2 elements give space order 3)."""
+    e = [_space_error(orc, N, p) for N in (16, 32, 64)]
+    s = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert p + 1 - 0.2 < s[-1] < p + 1 + 0.3, (e, s)
+
+
+def _entropy(F, D, w2):
+    """sum_k sum_nodes w f_k^T D_k^-1 f_k, F [k][c][cell][node]."""
+    return float(sum(np.einsum("acn,ab,bcn,n->", F[k], np.linalg.inv(D[k]), F[k], w2)
+                     for k in range(F.shape[0])))
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.5, 2.0])
+@pytest.mark.parametrize("theta,beta", [(0.5, 10.0), (1.0, 40.0)])
+def test_converged_step_never_grows_the_entropy_norm(orc, omega, theta, beta):
+    """Acoustics with D2Q4 at lambda = 1.25 x the sub-characteristic bound
+    (Sec. 2.1): the linear equilibria M_k(W) = D_k W have D_k symmetric
+    positive definite with sum_k D_k = I.  The converged transport (any CFL,
+    theta >= 1/2) is non-expansive in the lumped-mass norm of each component
+    and the over-relaxation with omega in [0, 2] (eq:over_relaxation) is
+    non-expansive in sum_k f_k^T D_k^-1 f_k (an over-relaxed orthogonal
+    projection), so no full step grows that norm -- from a random kinetic
+    state far from equilibrium, at kinetic Courant numbers 6 and 25."""
+    spec, _ = wl.make_workload(2, n_cells=[12, 8], sub_cells=[4, 4], beta=beta, omega=omega,
+                               n_iter=0, theta=theta)
+    lam = 1.25 * 2.0
+    spec["vel"] = [lam, 0.0, -lam, 0.0, 0.0, lam, 0.0, -lam]
+    c = orc.Config(spec)
+    a, b = orc.eq_weights(c)
+    A = np.array(spec["law_params"]).reshape(2, 3, 3)
+    D = np.array([a[k] * np.eye(3) + b[k, 0] * A[0] + b[k, 1] * A[1] for k in range(4)])
+    assert np.allclose(D.sum(axis=0), np.eye(3), atol=1e-15)
+    for k in range(4):
+        assert np.allclose(D[k], D[k].T) and np.linalg.eigvalsh(D[k]).min() > 0.04
+    _, w = orc.gl(2)
+    w2 = np.kron(w, w)
+    F = np.random.default_rng(1).normal(size=(4, 3, 96, 9))
+    E = [_entropy(F, D, w2)]
+    for _ in range(12):
+        F = orc.step(c, F, 1)
+        E.append(_entropy(F, D, w2))
+    ratios = np.array(E[1:]) / np.array(E[:-1])
+    assert ratios.max() <= 1.0 + 1e-12, ratios

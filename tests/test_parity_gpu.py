@@ -3,7 +3,8 @@ element by element, on the seeded workloads at reduced sizes that span
 several bundles, subdomains and ragged tails, plus full-size configurations
 where the oracle finishes in seconds.
 
-Tolerances (max |x_gpu - x_oracle| / max |x_oracle|, on W and on F):
+Tolerances (max |x_gpu - x_oracle| / max |x_oracle|, on W and on F, over
+all values and also per (velocity, component) plane on its own scale):
   FP64 storage: 1e-12;  FP32 storage: 1e-5 (FP32 rounding of the state at
   every step, ~1e-7 per step, accumulated over the steps of the run).
 """
@@ -13,6 +14,8 @@ import functools
 
 import numpy as np
 import pytest
+
+from tests import parity as pt
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +51,8 @@ CASES = {
                             source_sigma=[0.0, 2.0, 2.0, 2.0, 0.0])),
     "cfg2_pec": (2, dict(n_cells=[16, 16], sub_cells=[8, 8], steps=3,
                          source_sigma=[float("inf"), 0.0, 0.0])),
+    # more steps than one captured multi-step graph holds (8 + 2 single steps)
+    "cfg2_10steps": (2, dict(n_cells=[32, 16], sub_cells=[8, 8], steps=10)),
 }
 
 
@@ -76,8 +81,7 @@ def run_gpu(spec, W0, prec, sched, steps=None):
     return W, F
 
 
-def relerr(a, b):
-    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+relerr = pt.relerr
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -89,9 +93,7 @@ def test_parity_against_oracle(name, prec, sched):
     spec, W0, Fref, Wref = case(name)
     print("case", name, prec, sched, spec["n_cells"], spec["sub_cells"], flush=True)
     W, F = run_gpu(spec, W0, prec, sched)
-    ew, ef = relerr(W, Wref), relerr(F, Fref)
-    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
-    assert ew <= TOL[prec] and ef <= TOL[prec], (ew, ef)
+    pt.check(W, Wref, F, Fref, TOL[prec])
 
 
 def test_plain_and_line_schedules_agree_fp64():
@@ -208,18 +210,23 @@ def test_autotuned_plan_restores_state_and_keeps_parity(name):
         W = pb.moments()
         F = pb.get_kinetic()
     print("tuned", name, info["line_Q"], info["line_bw"], "%.4f ms" % ms, flush=True)
-    assert relerr(W, Wref) <= TOL["fp32"] and relerr(F, Fref) <= TOL["fp32"]
+    pt.check(W, Wref, F, Fref, TOL["fp32"])
 
 
-@pytest.mark.parametrize("name,sched", [("cfg2_ragged", "line"), ("cfg3_small", "plain"),
-                                        ("cfg2_source", "line"), ("cfg3_odd", "line"),
-                                        ("maxwell_q1_ragged", "front")])
-def test_launch_choices_are_bitwise_equal(name, sched):
+LAUNCH_CASES = [("cfg2_ragged", "line"), ("cfg3_small", "plain"), ("cfg2_source", "line"),
+                ("cfg3_odd", "line"), ("maxwell_q1_ragged", "front"), ("cfg2_10steps", "line"),
+                ("cfg2_10steps", "plain")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,sched", LAUNCH_CASES)
+def test_launch_choices_are_bitwise_equal(name, sched, prec):
     """The step launch mode (graph replay or enqueued kernels) and the
     relaxation's access width (one node per thread, or 16-byte accesses over
-    several nodes) change no arithmetic: all four combinations end bitwise
-    equal, and match the oracle (cfg3_odd: a node count that is not a
-    multiple of 4, where the vector relaxation falls back)."""
+    4 FP32 / 2 FP64 nodes) change no arithmetic: all four combinations end
+    bitwise equal, and match the oracle (cfg3_odd: a node count that is not a
+    multiple of 4, where the FP32 vector relaxation falls back; cfg2_10steps:
+    one replay of the 8-step graph and two of the 1-step graph)."""
     import torch
     from paper_2212_11010_amd import kds
     if name in CASES:
@@ -229,7 +236,7 @@ def test_launch_choices_are_bitwise_equal(name, sched):
     outs = []
     for eager in (0, 1):
         for vec in (0, 1):
-            with kds.Problem(spec, precision="fp32", schedule=sched) as pb:
+            with kds.Problem(spec, precision=prec, schedule=sched) as pb:
                 pb.set_state(torch.from_numpy(W0).cuda())
                 pb.set_launch(eager, vec)
                 assert pb.info()["step_eager"] == eager and pb.info()["relax_vec"] == vec
@@ -237,7 +244,7 @@ def test_launch_choices_are_bitwise_equal(name, sched):
                 outs.append((pb.get_kinetic(), pb.moments()))
     for F, W in outs[1:]:
         assert np.array_equal(F, outs[0][0])
-    assert relerr(outs[0][1], Wref) <= TOL["fp32"] and relerr(outs[0][0], Fref) <= TOL["fp32"]
+    pt.check(outs[0][1], Wref, outs[0][0], Fref, TOL[prec])
 
 
 def test_converged_mode_rejected_by_plain_schedule():
@@ -264,8 +271,14 @@ FRONT_CASES = {
     "cfg4_front": (4, dict(n_cells=[6, 4, 4], sub_cells=[3, 4, 2], steps=2)),
 }
 # FP16 split: three FP16 products recover ~FP32 accuracy; BF16 split keeps ~16
-# significant bits per product (measured 1e-5 .. 4e-5 over 2-3 steps)
+# significant bits per operand (measured 1e-5 .. 5e-5 over 2-3 steps, globally)
 FRONT_TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_split_f16": 1e-5, "fp32_split_bf16": 1e-4}
+# Per plane on its own scale, BF16 split: each operand of W X carries a
+# relative error up to 2^-17 (8 + 8 mantissa bits), so a column's error is
+# ~2^-16 sum |W_ij| |X_j|; the implicit cell operator at kinetic Courant
+# numbers 4-11 has sum |W_ij| |X_j| up to ~30 |sum W_ij X_j| for the small
+# momentum components (cancellation), i.e. ~5e-4 of the plane's own scale.
+FRONT_TOL_PLANE = {"fp32_split_bf16": 5e-4}
 
 
 @functools.lru_cache(maxsize=None)
@@ -291,9 +304,7 @@ def test_front_schedule_parity(name, prec):
         pb.step(spec["steps"])
         W = pb.moments()
         F = pb.get_kinetic()
-    ew, ef = relerr(W, Wref), relerr(F, Fref)
-    print("  rel err W %.3e F %.3e" % (ew, ef), flush=True)
-    assert ew <= FRONT_TOL[prec] and ef <= FRONT_TOL[prec], (ew, ef)
+    pt.check(W, Wref, F, Fref, FRONT_TOL[prec], tol_plane=FRONT_TOL_PLANE.get(prec))
 
 
 def test_auto_picks_front_for_oblique_velocities():

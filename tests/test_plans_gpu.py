@@ -1,0 +1,206 @@
+"""Every line-schedule launch plan is parity-tested, not only the ones the
+autotuner happens to pick: kds_set_plan forces each plan family (cells per
+lane Q in {1, 2, Q_max} and columns per workgroup bw in {1, the largest the
+LDS allows} per axis, the direct register path for x lines on and off, a
+larger LDS allocation), and the result after a few steps is compared with
+the FP64 oracle element by element (W and F, globally and per plane),
+in FP64 (1e-12) and FP32 (1e-5).  The cases have velocities of both signs
+on every axis (D2Q4 / D3Q6), periodic and Dirichlet axes, and 64-node cells
+(grouped mode).  The line scan is the Sec. 5.1 subdomain iteration of
+Sec. 3.2 downwind sweeps along grid lines; every plan must give the same
+iterates up to rounding."""
+from __future__ import annotations
+
+import copy
+import functools
+
+import numpy as np
+import pytest
+
+from tests import parity as pt
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+PLAN_CASES = {
+    # name: (workload, overrides)
+    "acoustics_p2": (2, dict(n_cells=[32, 24], sub_cells=[8, 6], steps=3)),
+    "acoustics_p2_dir_x": (2, dict(n_cells=[32, 24], sub_cells=[8, 6], steps=3, periodic=[0, 1])),
+    "advection_p1_dir_xy": (1, dict(n_cells=[32, 32], sub_cells=[16, 8], steps=3,
+                                    periodic=[0, 0])),
+    "euler_p2": (3, dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=2)),
+    "euler_p2_dir_z": (3, dict(n_cells=[8, 6, 8], sub_cells=[4, 3, 4], steps=2,
+                               periodic=[1, 1, 0])),
+    "euler_p3_grouped": (4, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 2], steps=2)),
+}
+BWS = (32, 24, 16, 12, 8, 6, 4, 3, 2, 1)
+
+
+def boundary_series(spec, W0, n):
+    from paper_2212_11010_amd import workloads as wl
+    B = wl.boundary_state(spec, W0)
+    return [B * (1.0 + 0.05 * s) for s in range(n + 1)]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    from oracle import oracle
+    from paper_2212_11010_amd import workloads as wl
+    cfg, ov = PLAN_CASES[name]
+    spec, W0 = wl.make_workload(cfg, **ov)
+    n = spec["steps"]
+    dirichlet = 0 in spec.get("periodic", [1, 1, 1])[:spec["dim"]]
+    B = boundary_series(spec, W0, n) if dirichlet else None
+    c = oracle.Config(spec)
+    F = oracle.init(c, W0)
+    for s in range(n):
+        if B is None:
+            F = oracle.step(c, F, 1, threads=0)
+        else:
+            F = oracle.step(c, F, 1, threads=0, Wb_old=B[s], Wb_new=B[s + 1])
+    return spec, W0, B, np.ascontiguousarray(F.transpose(0, 2, 3, 1)), oracle.moments(c, F)
+
+
+def run(spec, W0, B, prec, plan):
+    """Steps with a forced plan; returns (W, F, plan read back) or None if the
+    plan is outside the limits (KDS_E_INVALID)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    with kds.Problem(spec, precision=prec, schedule="line") as pb:
+        try:
+            pb.set_plan(plan)
+        except kds.KdsError as e:
+            assert e.status == kds.KDS_E_INVALID, e
+            return None
+        got = pb.get_plan()
+        pb.set_state(torch.from_numpy(W0).cuda())
+        if B is not None:
+            pb.set_boundary(B[0])
+        for s in range(spec["steps"]):
+            if B is not None:
+                pb.set_boundary(B[s + 1])
+            pb.step(1)
+        return pb.moments(), pb.get_kinetic(), got
+
+
+def families(spec, prec):
+    """The plans to force: per used axis, Q in {1, 2, Q_max} x bw in {1, the
+    largest accepted}; Q_max on every axis with the direct x path on and off;
+    a larger LDS allocation."""
+    import torch  # noqa: F401
+    from paper_2212_11010_amd import kds
+    with kds.Problem(spec, precision=prec, schedule="line") as pb:
+        base = pb.get_plan()
+        qmax = pb.info()["line_qmax"]
+        tile = pb.info()["line_lds_bytes"]
+    used = [a for a in range(3) if base["Q"][a] > 0]
+    out = []
+    for a in used:
+        for Q in sorted({1, 2, qmax}):
+            for wide in (False, True):
+                p = copy.deepcopy(base)
+                p["Q"][a] = Q
+                p["bw"][a] = BWS[0] if wide else 1
+                out.append(("axis%d Q%d %s" % (a, Q, "bwmax" if wide else "bw1"), p))
+    # Q_max wherever it divides the subdomain (x always: the direct path needs it)
+    N, S = spec["n_cells"], spec["sub_cells"]
+    qm = [qmax if (S[a] % qmax == 0 and N[a] // qmax <= 64) else base["Q"][a] for a in range(3)]
+    for xd in (0, 1):
+        for wide in (False, True):
+            p = copy.deepcopy(base)
+            for a in used:
+                p["Q"][a] = qm[a]
+                p["bw"][a] = BWS[0] if wide else 1
+            p["xdirect"] = xd
+            out.append(("Qmax xdirect%d %s" % (xd, "bwmax" if wide else "bw1"), p))
+    p = copy.deepcopy(base)
+    p["lds_bytes"] = max(tile, 1) + 16 * 1024
+    out.append(("lds +16K", p))
+    return out, used, qmax
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(PLAN_CASES))
+def test_forced_plans_match_oracle(name, prec):
+    spec, W0, B, Fref, Wref = case(name)
+    plans, used, qmax = families(spec, prec)
+    print("case", name, prec, spec["n_cells"], spec["sub_cells"], "qmax", qmax, flush=True)
+    ran, direct = 0, 0
+    for label, plan in plans:
+        # the widest accepted bundle: step bw down until the plan is valid
+        res = None
+        for bw in BWS:
+            p = copy.deepcopy(plan)
+            for a in used:
+                if p["bw"][a] == BWS[0]:
+                    p["bw"][a] = bw
+            res = run(spec, W0, B, prec, p)
+            if res is not None or all(plan["bw"][a] != BWS[0] for a in used):
+                break
+        if res is None:
+            print("  %-26s outside the limits" % label, flush=True)
+            continue
+        W, F, got = res
+        for a in used:
+            assert got["Q"][a] == p["Q"][a] and got["bw"][a] == p["bw"][a], (got, p)
+        assert got["xdirect"] == p["xdirect"]
+        ran += 1
+        direct += got["xdirect"]
+        print("  %-26s Q %s bw %s xd %d lds %d" % (label, got["Q"], got["bw"], got["xdirect"],
+                                                   got["lds_bytes"]), flush=True)
+        pt.check(W, Wref, F, Fref, TOL[prec], label=label)
+    assert ran >= 6, ran
+    if 0 in used and spec["degree"] + 1 <= 3 and spec["n_cells"][0] // qmax <= 64 \
+            and spec["sub_cells"][0] % qmax == 0:
+        assert direct >= 1, "the direct x path was never run"
+
+
+def test_set_plan_rejects_invalid_choices():
+    from paper_2212_11010_amd import kds
+    spec, W0, _, _, _ = case("acoustics_p2")
+    with kds.Problem(spec, precision="fp32", schedule="line") as pb:
+        base = pb.get_plan()
+        qmax = pb.info()["line_qmax"]
+        for bad in (dict(Q=[3, base["Q"][1], 0]),        # 3 does not divide the 8-cell subdomain
+                    dict(Q=[qmax * 2, base["Q"][1], 0]),  # beyond the register budget
+                    dict(bw=[0, base["bw"][1], 0]),
+                    dict(xdirect=2), dict(step_eager=-1), dict(lds_bytes=-4),
+                    dict(lds_bytes=1 << 30)):
+            p = copy.deepcopy(base)
+            p.update(bad)
+            with pytest.raises(kds.KdsError) as e:
+                pb.set_plan(p)
+            assert e.value.status == kds.KDS_E_INVALID
+        assert pb.get_plan() == base   # unchanged after the rejections
+        # x direct needs Q[0] = Q_max
+        p = copy.deepcopy(base)
+        p["Q"][0] = 1
+        p["xdirect"] = 1
+        with pytest.raises(kds.KdsError):
+            pb.set_plan(p)
+
+
+def test_tuned_plan_restored_reproduces_bitwise():
+    """kds_get_plan after kds_tune, kds_set_plan on a fresh problem: the FP32
+    results are bitwise equal (the tuner's timing-driven choice is no longer a
+    source of run-to-run differences)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    spec, W0, _, Fref, Wref = case("euler_p2")
+    outs = []
+    with kds.Problem(spec, precision="fp32") as pb:
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.tune(2)
+        plan = pb.get_plan()
+        pb.step(spec["steps"])
+        outs.append(pb.get_kinetic())
+    with kds.Problem(spec, precision="fp32") as pb:
+        pb.set_plan(plan)
+        assert pb.get_plan() == plan
+        pb.set_state(torch.from_numpy(W0).cuda())
+        pb.step(spec["steps"])
+        outs.append(pb.get_kinetic())
+        W = pb.moments()
+    assert np.array_equal(outs[0], outs[1])
+    pt.check(W, Wref, outs[1], Fref, TOL["fp32"])
