@@ -234,6 +234,25 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms);
 /* W = sum_k F_k (FP64, Sec. 2.2 step 3) into W_out [cell][node][c]. */
 kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): kds_moments of
+ * the nodes node_begin .. node_begin + node_count - 1 (node = cell * (p+1)^d +
+ * node in cell) into HOST memory W_out [node_count][m], staged through a
+ * fixed device scratch array of 32 MiB that the library holds on each GPU
+ * until the process ends -- kds_moments with on_device = 0 instead allocates
+ * a staging buffer of the whole W on its first call.  This call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the address
+ * of the array is looked up in kds_create.  node_count * m * 8 bytes must fit
+ * the array (at most 4194304 / m nodes per call; larger ranges are rejected
+ * with KDS_E_INVALID, and the caller walks the nodes in several calls).
+ * Returns after the copy has finished.  Values are bitwise those of
+ * kds_moments.  Every call on one GPU shares its array: calls that overlap in
+ * time on one GPU (other host threads, other problems) race.
+ * Errors: KDS_E_INVALID (NULL, range outside the nodes or too large),
+ * KDS_E_STATE (no state), KDS_E_DEVICE. */
+kds_status kds_moments_static(kds_problem* p, int64_t node_begin, int64_t node_count,
+                              double* W_out);
+
 /* Checkpoint / resume of the kinetic state (F, not W: after the first step
  * F_k != M_k(W), Sec. 2.2 remark).  F: FP64 [k][cell][node][c]. */
 kds_status kds_get_kinetic(kds_problem* p, double* F_out, int32_t on_device);

@@ -56,6 +56,7 @@ struct kds_problem {
   double* stage = nullptr;  // FP64 staging for W / F transfers
   size_t stage_bytes = 0;
   int* flag = nullptr;
+  void* scratch = nullptr;  // device address of the library's static scratch array
   hipGraph_t graph = nullptr;           // one captured step
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph_n = nullptr;         // kGraphSteps captured steps
@@ -679,6 +680,14 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_NOMEM, "device allocation failed");
   }
+  // the static scratch of the allocation-free entry points: its address on
+  // this device (looked up once per device, the device current)
+  e = scratch_address(&p->scratch);
+  if (e != hipSuccess) {
+    free_device(p);
+    delete p;
+    return fail(nullptr, KDS_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  }
   if (hip_stream) {
     p->stream = (hipStream_t)hip_stream;
     p->own_stream = false;
@@ -1135,6 +1144,30 @@ kds_status kds_moments(kds_problem* p, double* W_out, int32_t on_device) {
     KDS_HIP(p, hipMemcpyAsync(W_out, p->stage, bytes, hipMemcpyDeviceToHost, p->stream));
     KDS_HIP(p, hipStreamSynchronize(p->stream));
   }
+  return KDS_OK;
+}
+
+kds_status kds_moments_static(kds_problem* p, int64_t node_begin, int64_t node_count,
+                              double* W_out) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!W_out) return fail(p, KDS_E_INVALID, "W_out is NULL");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_moments_static before kds_set_state");
+  if (node_begin < 0 || node_count < 0 || node_begin > p->plane() ||
+      node_count > p->plane() - node_begin)
+    return fail(p, KDS_E_INVALID, "kds_moments_static: node range outside the problem's nodes");
+  const int64_t max_nodes = (int64_t)(kScratchBytes / (sizeof(double) * (size_t)p->m));
+  if (node_count > max_nodes)
+    return fail(p, KDS_E_INVALID,
+                "kds_moments_static: at most " + std::to_string(max_nodes) +
+                    " nodes per call (the static scratch holds " +
+                    std::to_string(kScratchBytes >> 20) + " MiB)");
+  if (node_count == 0) return KDS_OK;
+  if (!p->scratch) return fail(p, KDS_E_DEVICE, "kds_moments_static: no scratch address");
+  double* w = static_cast<double*>(p->scratch);
+  KDS_HIP(p, launch_moments_range(p->prec, p->geom, p->f, node_begin, node_count, w, p->stream));
+  KDS_HIP(p, hipMemcpyAsync(W_out, w, (size_t)node_count * p->m * sizeof(double),
+                            hipMemcpyDeviceToHost, p->stream));
+  KDS_HIP(p, hipStreamSynchronize(p->stream));
   return KDS_OK;
 }
 

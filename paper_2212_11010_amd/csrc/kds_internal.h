@@ -197,6 +197,15 @@ hipError_t launch_init(int prec, int law, const Geom& g, const void* eq, const d
 hipError_t launch_relax(int prec, int law, const Geom& g, const void* eq_dev, const void* fin,
                         void* fout, bool vec, hipStream_t s);
 hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hipStream_t s);
+// W = sum_k f_k at nodes i0 .. i0 + n - 1 into W[(i - i0) m + r]
+hipError_t launch_moments_range(int prec, const Geom& g, const void* f, int64_t i0, int64_t n,
+                                double* W, hipStream_t s);
+
+// Size of the static device scratch array (one per GPU) used by the entry
+// points that allocate nothing, and its device address on the current device
+// (looked up once per device).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+hipError_t scratch_address(void** out);
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s);
 hipError_t launch_set_kinetic(int prec, const Geom& g, const double* F, void* f, hipStream_t s);
 hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag, hipStream_t s);

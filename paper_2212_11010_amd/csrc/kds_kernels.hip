@@ -21,6 +21,7 @@
 // prescribed boundary value on a Dirichlet axis.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "kds_device.h"
 
@@ -551,6 +552,35 @@ hipError_t launch_moments(int prec, const Geom& g, const void* f, double* W, hip
   return launch_moments_range(prec, g, f, 0, g.ncell * g.nn, W, s);
 }
 
+// ======================================================= static scratch
+//
+// Device memory of the entry points that allocate nothing (kds_moments_static):
+// a fixed array in the code object, one copy per GPU, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (on
+// the host the name is not a device address): scratch_address() looks the
+// array's device address up once per device, with that device current, and
+// every use goes through that address.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s) {
   const int64_t plane = g.ncell * g.nn;

@@ -28,7 +28,7 @@ SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED
 N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_step_timed",
             "kds_tune", "kds_set_launch", "kds_get_plan", "kds_set_plan",
-            "kds_time_kernels", "kds_moments",
+            "kds_time_kernels", "kds_moments", "kds_moments_static",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
             "kds_batch_create", "kds_batch_step", "kds_batch_step_timed",
@@ -97,6 +97,7 @@ def lib():
         L.kds_set_plan.argtypes = [vp, C.POINTER(kds_plan_t)]
         L.kds_time_kernels.argtypes = [vp, C.c_int32, dp]
         L.kds_moments.argtypes = [vp, vp, C.c_int32]
+        L.kds_moments_static.argtypes = [vp, C.c_int64, C.c_int64, vp]
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_set_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_check_finite.argtypes = [vp]
@@ -275,6 +276,15 @@ def kds_time_kernels(h, reps=10):
 def kds_moments(h, out, nbytes):
     ptr, dev = _buf(out, nbytes)
     _check(lib().kds_moments(h, ptr, dev), h)
+    return out
+
+
+def kds_moments_static(h, node_begin, node_count, out):
+    """out: host float64 array of node_count * m values (C-contiguous)."""
+    if not isinstance(out, np.ndarray) or out.dtype != np.float64 or not out.flags.c_contiguous:
+        raise ValueError("kds_moments_static writes a C-contiguous float64 host array")
+    _check(lib().kds_moments_static(h, int(node_begin), int(node_count),
+                                    C.c_void_p(out.ctypes.data)), h)
     return out
 
 
