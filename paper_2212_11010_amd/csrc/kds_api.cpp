@@ -38,6 +38,9 @@ struct kds_problem {
   void* front_W = nullptr;      // [k][nn][Kd] dense cell operators
   int* front_lvl_start = nullptr;
   int* front_lvl_cells = nullptr;
+  int4* front_desc = nullptr;   // wave kernel: per cell in front order (see front_wave_fits)
+  int front_ndesc = 0;
+  bool front_wave = false;      // the wave-per-task front kernel (else one workgroup per subdomain)
   void* fit[2] = {nullptr, nullptr};  // front schedule: iterates
   bool tuned = false;
   bool eager_steps = false;  // kds_step enqueues the kernels itself instead of
@@ -281,9 +284,13 @@ bool plan_lines(kds_problem* p, std::string& why) {
 
 // Front schedule tables: dense operators per velocity and, per velocity, the
 // cells of one subdomain sorted by level l = sum over axes with V^a != 0 of the
-// downwind cell index (packed lx | ly << 10 | lz << 20).
+// downwind cell index (packed lx | ly << 10 | lz << 20).  desc: the same cells
+// as the wave kernel's records (element offset of the cell inside its
+// subdomain, downwind coordinates, frontier positions); empty where an offset
+// or a position does not fit its field.
 bool build_front(kds_problem* p, const Basis1D& basis, std::vector<double>& W,
-                 std::vector<int>& lvl_start, std::vector<int>& lvl_cells, std::string& why) {
+                 std::vector<int>& lvl_start, std::vector<int>& lvl_cells,
+                 std::vector<int4>& desc, std::string& why) {
   FrontParams& fp = p->front;
   std::memset(&fp, 0, sizeof(fp));
   int nn = 0, nf = 0;
@@ -307,8 +314,12 @@ bool build_front(kds_problem* p, const Basis1D& basis, std::vector<double>& W,
   fp.col_chunk = 64;
   lvl_start.clear();
   lvl_cells.clear();
+  desc.clear();
   const int S0 = p->S[0], S1 = p->S[1], S2 = p->S[2];
   if (S0 > 1024 || S1 > 1024 || S2 > 1024) { why = "front schedule: subdomain wider than 1024 cells"; return false; }
+  // frontier slots per axis (a cell's position: its coordinates on the other two axes)
+  fp.fr_pos = std::max(S1 * S2, std::max(S0 * S2, S0 * S1));
+  bool desc_ok = fp.fr_pos <= 65536;
   for (int k = 0; k < p->nv; ++k) {
     int act[3];
     for (int a = 0; a < 3; ++a) act[a] = fp.sg[k][a] != 0;
@@ -316,15 +327,31 @@ bool build_front(kds_problem* p, const Basis1D& basis, std::vector<double>& W,
     fp.lvl_off[k] = (int)lvl_start.size();
     fp.nlev[k] = maxlev + 1;
     std::vector<std::vector<int>> by(maxlev + 1);
+    std::vector<std::vector<int4>> dby(maxlev + 1);
     for (int z = 0; z < S2; ++z)
       for (int y = 0; y < S1; ++y)
-        for (int x = 0; x < S0; ++x)
-          by[act[0] * x + act[1] * y + act[2] * z].push_back(x | (y << 10) | (z << 20));
+        for (int x = 0; x < S0; ++x) {
+          const int l = act[0] * x + act[1] * y + act[2] * z;
+          by[l].push_back(x | (y << 10) | (z << 20));
+          // physical local coordinates run against the velocity where V^a < 0
+          const int px = fp.sg[k][0] < 0 ? S0 - 1 - x : x;
+          const int py = fp.sg[k][1] < 0 ? S1 - 1 - y : y;
+          const int pz = fp.sg[k][2] < 0 ? S2 - 1 - z : z;
+          const int64_t loc = ((int64_t)px + (int64_t)p->N[0] * (py + (int64_t)p->N[1] * pz)) * nn;
+          if (loc > 0x7fffffffLL) desc_ok = false;
+          dby[l].push_back(make_int4((int)loc, x | (y << 10) | (z << 20),
+                                     (y + S1 * z) | ((x + S0 * z) << 16), x + S0 * y));
+        }
     for (int l = 0; l <= maxlev; ++l) {
       lvl_start.push_back((int)lvl_cells.size());
       lvl_cells.insert(lvl_cells.end(), by[l].begin(), by[l].end());
+      desc.insert(desc.end(), dby[l].begin(), dby[l].end());
     }
     lvl_start.push_back((int)lvl_cells.size());
+  }
+  if (!desc_ok) {
+    desc.clear();
+    fp.fr_pos = 0;
   }
   return true;
 }
@@ -372,13 +399,15 @@ void free_device(kds_problem* p) {
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
-                  p->front_lvl_start, p->front_lvl_cells, p->fit[0], p->fit[1], p->fb, p->Wb_dev,
+                  p->front_lvl_start, p->front_lvl_cells, p->front_desc, p->fit[0], p->fit[1],
+                  p->fb, p->Wb_dev,
                   p->eq_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   p->f = p->f_tmp = p->tr[0] = p->tr[1] = nullptr;
   p->front_W = p->fit[0] = p->fit[1] = nullptr;
   p->front_lvl_start = p->front_lvl_cells = nullptr;
+  p->front_desc = nullptr;
   p->fb = nullptr;
   p->Wb_dev = nullptr;
   p->eq_dev = nullptr;
@@ -386,6 +415,15 @@ void free_device(kds_problem* p) {
   p->flag = nullptr;
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   p->stream = nullptr;
+}
+
+// One subdomain iteration of the front schedule, with the problem's kernel choice.
+hipError_t launch_front_iter(kds_problem* p, const void* f_prev, void* f_cur, hipStream_t s) {
+  if (p->front_wave)
+    return launch_sweep_front_wave(p->front_mode, p->geom, p->front, p->front_W, p->front_lvl_start,
+                                   p->front_desc, p->front_ndesc, p->f, f_prev, f_cur, p->bnd(), s);
+  return launch_sweep_front(p->prec, p->front_mode, p->geom, p->front, p->front_W,
+                            p->front_lvl_start, p->front_lvl_cells, p->f, f_prev, f_cur, p->bnd(), s);
 }
 
 // Enqueue one time step (transport then relaxation) on the problem's stream.
@@ -397,9 +435,7 @@ kds_status enqueue_step(kds_problem* p, bool events, hipStream_t s) {
   if (p->sched == KDS_SCHED_FRONT) {
     for (int it = 1; it <= p->K; ++it) {
       const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
-      KDS_HIP(p, launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
-                                    p->front_lvl_start, p->front_lvl_cells, p->f, f_prev,
-                                    p->fit[it & 1], p->bnd(), s));
+      KDS_HIP(p, launch_front_iter(p, f_prev, p->fit[it & 1], s));
     }
     if (events) KDS_HIP(p, hipEventRecord(p->ev[1], s));
     KDS_HIP(p, launch_relax(p->prec, p->law, g, p->eq_dev, p->fit[p->K & 1], p->f, p->relax_vec, s));
@@ -557,7 +593,8 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   }
   std::vector<double> frontW;
   std::vector<int> lvl_start, lvl_cells;
-  if (want_front && !build_front(p, basis, frontW, lvl_start, lvl_cells, msg)) {
+  std::vector<int4> front_desc;
+  if (want_front && !build_front(p, basis, frontW, lvl_start, lvl_cells, front_desc, msg)) {
     delete p;
     return fail(nullptr, KDS_E_UNSUPPORTED, msg);
   }
@@ -607,7 +644,12 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   p->sched = (cfg->schedule == KDS_SCHED_PLAIN || !line_ok) ? KDS_SCHED_PLAIN : KDS_SCHED_LINE;
   if (want_front) {
     p->sched = KDS_SCHED_FRONT;
-    if (front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) > 64 * 1024) {
+    p->front_ndesc = (int)front_desc.size();
+    // the wave-per-task kernel where it applies (its records fit, FP32
+    // matrix-core modes, p <= 2 in 3-D), else one workgroup per subdomain
+    p->front_wave = p->front_ndesc > 0 && front_wave_fits(p->prec, p->front_mode, p->geom, p->front,
+                                                          p->nbnd);
+    if (!p->front_wave && front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) > 64 * 1024) {
       delete p;
       return fail(nullptr, KDS_E_UNSUPPORTED, "front schedule: cell operator too large for the LDS");
     }
@@ -660,7 +702,8 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     ok = alloc(&p->fit[0], state_bytes) && alloc(&p->fit[1], state_bytes) &&
          alloc(&p->front_W, frontW.size() * p->elem) &&
          alloc((void**)&p->front_lvl_start, lvl_start.size() * sizeof(int)) &&
-         alloc((void**)&p->front_lvl_cells, lvl_cells.size() * sizeof(int));
+         alloc((void**)&p->front_lvl_cells, lvl_cells.size() * sizeof(int)) &&
+         (front_desc.empty() || alloc((void**)&p->front_desc, front_desc.size() * sizeof(int4)));
     if (ok) {
       std::vector<float> w32;
       const void* src = frontW.data();
@@ -672,7 +715,10 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
            hipMemcpy(p->front_lvl_start, lvl_start.data(), lvl_start.size() * sizeof(int),
                      hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(p->front_lvl_cells, lvl_cells.data(), lvl_cells.size() * sizeof(int),
-                     hipMemcpyHostToDevice) == hipSuccess;
+                     hipMemcpyHostToDevice) == hipSuccess &&
+           (front_desc.empty() ||
+            hipMemcpy(p->front_desc, front_desc.data(), front_desc.size() * sizeof(int4),
+                      hipMemcpyHostToDevice) == hipSuccess);
     }
   }
   if (!ok) {
@@ -1098,9 +1144,7 @@ kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
     auto launch = [&]() -> hipError_t {
       if (kind == 0) {
         if (p->sched == KDS_SCHED_FRONT)
-          return launch_sweep_front(p->prec, p->front_mode, g, p->front, p->front_W,
-                                    p->front_lvl_start, p->front_lvl_cells, p->f, p->f,
-                                    p->fit[1], p->bnd(), p->stream);
+          return launch_front_iter(p, p->f, p->fit[1], p->stream);
         if (p->sched == KDS_SCHED_LINE)
           return launch_sweep_line(p->prec, g, p->sweep_blob.data(), p->plan, p->f, p->bnd(),
                                    p->stream);

@@ -1,0 +1,556 @@
+// kds_front_wave.hip -- the front schedule with one wave per
+// (velocity, subdomain, component): the FP32 matrix-core forms for cells of
+// at most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D).
+//
+// The same computation as k_sweep_front (the solves of one anti-diagonal
+// front of the V-oriented cell graph as one GEMM Y = W X per front, Sec. 3.2,
+// one launch per subdomain iteration, eq:ibvp), arranged for latency:
+//   * a wave owns a whole task and never waits at a barrier: the levels of a
+//     subdomain follow each other in program order, and many independent
+//     waves per SIMD hide each other's memory latency;
+//   * the GEMM input never goes through LDS: lane (j, g) of the wave gathers
+//     KS values of column j straight into the B operand registers of the
+//     16x16 matrix-core products.  The K index of the products is permuted
+//     so that register slot e holds the same kind of row in all four lane
+//     groups g: slots 0 .. CS-1 a run of CS consecutive cell nodes, then FS
+//     slots per inflow axis a with a run of face nodes.  Kind, axis and the
+//     address pattern of a slot are compile-time constants, so the cell
+//     values arrive with a few wide loads and a face slot costs one or two
+//     loads with an immediate offset;
+//   * the traces inside the subdomain stay in LDS: a cell writes
+//     theta t^n + (1 - theta) t^{n-1} on its outflow faces into the wave's
+//     frontier (one slot per grid line through the subdomain and axis),
+//     where the next cell of that line reads its inflow;
+//   * global memory is read through range-checked buffer loads with 32-bit
+//     offsets: a row without a global source reads from an offset past the
+//     buffer, which returns 0 (one load pattern for every lane, no 64-bit
+//     address selects); stores of padding outputs are dropped the same way;
+//   * the cell records (offset, downwind coordinates, frontier positions)
+//     are built on the host, 16 bytes per cell in front order, and the next
+//     tile's records load while the current tile computes.
+#include "kds_device.h"
+
+namespace kds {
+
+namespace {
+
+constexpr unsigned kOob = 0x80000000u;  // byte offset past every buffer of the kernel
+
+typedef float wf32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 wf16x4 __attribute__((ext_vector_type(4)));
+typedef short wi16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(const void* p, int64_t bytes) {
+  // raw buffer (stride 0), range `bytes`; word 3 = the gfx9 data format
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+// n consecutive values at byte offset o, with the widest loads
+template <int N>
+__device__ __forceinline__ void bload_run(__amdgpu_buffer_rsrc_t r, unsigned o, float* v) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u3 __attribute__((ext_vector_type(3)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if constexpr (N >= 4) {
+    const u4 x = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __uint_as_float(x[u]);
+    bload_run<N - 4>(r, o + 16u, v + 4);
+  } else if constexpr (N == 3) {
+    const u3 x = __builtin_amdgcn_raw_buffer_load_b96(r, o, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) v[u] = __uint_as_float(x[u]);
+  } else if constexpr (N == 2) {
+    const u2 x = __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0);
+    v[0] = __uint_as_float(x[0]);
+    v[1] = __uint_as_float(x[1]);
+  } else if constexpr (N == 1) {
+    v[0] = bload(r, o);
+  }
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+}
+
+__device__ __forceinline__ unsigned short wbf16_rne(float x) {
+  const unsigned int b = __float_as_uint(x);
+  return (unsigned short)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float wbf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+// Compile-time shape of a cell: nodes, face nodes, register slots.
+template <int DIM, int P>
+struct WaveShape {
+  static constexpr int NN = DIM == 3 ? P * P * P : P * P;
+  static constexpr int NF = DIM == 3 ? P * P : P;
+  static constexpr int CS = (NN + 3) / 4;       // cell slots
+  static constexpr int FS = (NF + 3) / 4;       // slots per inflow axis
+  static constexpr int FSTR = NF | 1;           // frontier values per line (odd: LDS banks)
+  static constexpr int KS0 = CS + DIM * FS;
+  static constexpr int MT = (NN + 15) / 16;     // 16-row output tiles
+  static constexpr int XOS = 16 * MT + 1;       // cell values of a tile, per column
+};
+
+template <int MODE, int KS0>
+struct WaveK {
+  // slots per lane: the 16x16x16 products take four per step
+  static constexpr int KS = MODE == kFrontMfma ? KS0 : (KS0 + 3) / 4 * 4;
+};
+
+// The tasks' work: levels of one subdomain, tiles of 16 cells of a level.
+// BND: Dirichlet box faces on the subdomain's inflow side (boundary traces
+// are a second pair of buffers).
+template <int MODE, int DIM, int P, bool BND>
+__device__ __forceinline__ void front_wave_task(
+    const Geom& g, const FrontParams& fp, const float* __restrict__ Wk,
+    const int* __restrict__ lvl_start, const int4* __restrict__ desc, int n_desc, int k,
+    const int (&sg)[3], const int (&sdc)[3], const int (&nbrel)[3], const int (&isb)[3],
+    const int (&boff)[3], unsigned sdb, __amdgpu_buffer_rsrc_t rfo, __amdgpu_buffer_rsrc_t rfp,
+    __amdgpu_buffer_rsrc_t rfc, __amdgpu_buffer_rsrc_t rbo, __amdgpu_buffer_rsrc_t rbn, float* FR,
+    float* XO) {
+  using S = WaveShape<DIM, P>;
+  constexpr int NN = S::NN, NF = S::NF, CS = S::CS, FS = S::FS, FSTR = S::FSTR, MT = S::MT,
+                XOS = S::XOS;
+  constexpr int KS = WaveK<MODE, S::KS0>::KS;
+  constexpr int KB = KS / 4 > 0 ? KS / 4 : 1;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const int Kd = fp.Kd;
+  const float th = (float)fp.theta, th1 = 1.0f - th;
+  const int frn = 3 * fp.fr_pos * FSTR;  // frontier values; FR[frn] is a write sink
+  // Slots of lane group lk: cell nodes cst .. cst + CS - 1 and face nodes
+  // fst .. fst + FS - 1, runs inside the cell and the face (the last group's
+  // run starts early; the slots it shares with the group before get zero
+  // operator columns), so that every read stays inside its cell or face.
+  const int cst = min(lk * CS, NN - CS), fst = min(lk * FS, NF - FS);
+
+  // ---- the operator slice: lane (i, g) of row tile t holds operator row
+  // 16 t + i at the K positions of slots e (e = st in the 16x16x4 products,
+  // 4 st + u in the 16x16x16 ones)
+  float afr[MODE == kFrontMfma ? MT : 1][MODE == kFrontMfma ? KS : 1];
+  wf16x4 ah16[MODE == kFrontSplitF16 ? MT : 1][KB], al16[MODE == kFrontSplitF16 ? MT : 1][KB];
+  wi16x4 ahb[MODE == kFrontSplitBf16 ? MT : 1][KB], alb[MODE == kFrontSplitBf16 ? MT : 1][KB];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int i = 16 * t + li;
+#pragma unroll
+    for (int e = 0; e < KS; ++e) {
+      // the operator column of slot e in lane group lk (-1: a slot that
+      // repeats a value of the group before)
+      int col = -1;
+      if (e < CS) {
+        const int node = cst + e;
+        col = node >= lk * CS ? node : -1;
+      } else if (e < CS + DIM * FS) {
+        const int a = (e - CS) / FS, q = fst + (e - CS) % FS;
+        col = q >= lk * FS ? NN + a * NF + q : -1;
+      }
+      const float w = (i < NN && col >= 0) ? Wk[i * Kd + col] : 0.0f;
+      if constexpr (MODE == kFrontMfma) {
+        afr[t][e] = w;
+      } else if constexpr (MODE == kFrontSplitF16) {
+        const _Float16 h = (_Float16)w;
+        ah16[t][e / 4][e % 4] = h;
+        al16[t][e / 4][e % 4] = (_Float16)((w - (float)h) * 2048.0f);
+      } else {
+        const unsigned short h = wbf16_rne(w);
+        ahb[t][e / 4][e % 4] = (short)h;
+        alb[t][e / 4][e % 4] = (short)wbf16_rne(w - wbf16_to_f32(h));
+      }
+    }
+  }
+
+  // ---- per lane: the byte offset of face node q = 4 j + lk inside the
+  // upwind neighbour's cell (its outflow index on axis a, the others from q,
+  // x fastest) and inside a boundary face block
+  unsigned nbn4[3][FS], bq4[FS];
+#pragma unroll
+  for (int j = 0; j < FS; ++j) {
+    const int q = fst + j;
+    bq4[j] = 4u * q;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int side = sg[a] > 0 ? P - 1 : 0;
+      const int node = a == 0 ? side + P * q
+                              : (a == 1 ? (q % P) + P * side + P * P * (q / P) : q + P * P * side);
+      nbn4[a][j] = a < DIM ? 4u * node : kOob;
+    }
+  }
+  // per output row: its indices on the outflow faces, 8 bits per axis (0xff: not on it)
+  int oq[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * t + 4 * lk + v;
+      const int id[3] = {i % P, (i / P) % P, DIM == 3 ? i / (P * P) : 0};
+      int w = 0xffffff;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const int side = sg[a] > 0 ? P - 1 : 0;
+        const int q = a == 0 ? id[1] + P * id[2] : (a == 1 ? id[0] + P * id[2] : id[0] + P * id[1]);
+        if (i < NN && sg[a] != 0 && id[a] == side) w = (w & ~(0xff << (8 * a))) | (q << (8 * a));
+      }
+      oq[t][v] = w;
+    }
+  // the frontier starts at zero (a read it serves before the upwind cell wrote
+  // it is discarded, but stays a finite number)
+  for (int x = lane; x <= frn; x += 64) FR[x] = 0.0f;
+
+  // ---- the global loads of a tile (records d; columns with `ok`): the cell
+  // values at t^{n-1}, and on inflow faces across an interface or a Dirichlet
+  // box face the old and new traces.  None of them depends on the sweep, so
+  // a tile's loads are issued while the tile before it computes.
+  auto issue = [&](const int4 d, bool ok, float (&pc)[CS], float (&pvo)[DIM * FS],
+                   float (&pvn)[DIM * FS]) {
+    const unsigned off = sdb + (unsigned)d.x;  // node 0 of the cell in its plane
+    const int pk = d.y;
+    // nodes cst .. cst + CS - 1: consecutive, read with wide loads
+    bload_run<CS>(rfo, ok ? (off + (unsigned)cst) * 4u : kOob, pc);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      // the first cell of the subdomain along a reads across the interface
+      // (iterate p-1, periodic wrap included) or the boundary data
+      const int la = (pk >> (10 * a)) & 1023;
+      const bool first = ok && sg[a] != 0 && la == 0;
+      const unsigned nb4 = (first && !isb[a]) ? ((unsigned)((int)off + nbrel[a])) * 4u : kOob;
+      unsigned bb4 = kOob;
+      if constexpr (BND) {
+        // the boundary node block of the cell's face: cells over the other axes
+        int fcell = 0, mul = 1;
+#pragma unroll
+        for (int o = 0; o < DIM; ++o)
+          if (o != a) {
+            const int lc = (pk >> (10 * o)) & 1023;
+            const int pl = sg[o] < 0 ? g.S[o] - 1 - lc : lc;
+            fcell += (sdc[o] * g.S[o] + pl) * mul;
+            mul *= g.N[o];
+          }
+        if (first && isb[a]) bb4 = (unsigned)(boff[a] + fcell * NF) * 4u;
+      }
+#pragma unroll
+      for (int j = 0; j < FS; ++j) {
+        const int s = a * FS + j;
+        pvo[s] = bload(rfo, nb4 + nbn4[a][j]);
+        pvn[s] = bload(rfp, nb4 + nbn4[a][j]);
+        if constexpr (BND) {
+          // a row reads the state or the boundary data, never both: the
+          // other load is out of range and adds an exact 0
+          pvo[s] += bload(rbo, bb4 + bq4[j]);
+          pvn[s] += bload(rbn, bb4 + bq4[j]);
+        }
+      }
+    }
+  };
+  // tiles: (first cell, end of its level, level); the successor of a tile is
+  // the rest of its level, or the next level
+  const int lo = fp.lvl_off[k], nlev = fp.nlev[k];
+  auto advance = [&](int cb, int ce, int lev, int& ncb, int& nce, int& nlv) {
+    ncb = cb + 16;
+    nce = ce;
+    nlv = lev;
+    if (ncb >= ce) {
+      ncb = ce;
+      nlv = lev + 1;
+      nce = nlv < nlev ? lvl_start[lo + nlv + 1] : ce;
+    }
+  };
+  int cb = lvl_start[lo], ce = lvl_start[lo + 1], lev = 0;
+  int ncb, nce, nlev2;
+  advance(cb, ce, lev, ncb, nce, nlev2);
+  int4 dc = desc[min(cb + li, n_desc - 1)];
+  int4 dn = desc[min(ncb + li, n_desc - 1)];
+  float pc[CS], pvo[DIM * FS], pvn[DIM * FS];
+  issue(dc, cb + li < ce, pc, pvo, pvn);
+  while (lev < nlev) {
+    // ---- this tile's columns: lane j's cell (its loads were issued a tile ago)
+    const bool valid = cb + li < ce;
+    const unsigned off = sdb + (unsigned)dc.x;
+    const int pk = dc.y;
+    const int pos[3] = {dc.z & 0xffff, (int)((unsigned)dc.z >> 16), dc.w};
+    int frb[3];
+    bool isfr[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      frb[a] = (a * fp.fr_pos + pos[a]) * FSTR;
+      isfr[a] = valid && sg[a] != 0 && ((pk >> (10 * a)) & 1023) > 0;
+    }
+    // ---- the GEMM input: cell slots, then face slots (frontier, or the
+    // theta-combined traces loaded with the cell values)
+    float bx[KS];
+#pragma unroll
+    for (int e = 0; e < CS; ++e) bx[e] = pc[e];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int j = 0; j < FS; ++j) {
+        const int s = a * FS + j;
+        const float fr = FR[frb[a] + fst + j];
+        bx[CS + s] = isfr[a] ? fr : th1 * pvo[s] + th * pvn[s];
+      }
+#pragma unroll
+    for (int e = CS + DIM * FS; e < KS; ++e) bx[e] = 0.0f;
+    // the cell's own values, for the outflow traces of the epilogue
+#pragma unroll
+    for (int e = 0; e < CS; ++e) XO[li * XOS + cst + e] = bx[e];
+
+    // ---- the next tile's loads, and the records of the one after
+    int nncb, nnce, nlev3;
+    advance(ncb, nce, nlev2, nncb, nnce, nlev3);
+    const int4 dnn = desc[min(nncb + li, n_desc - 1)];
+    issue(dn, nlev2 < nlev && ncb + li < nce, pc, pvo, pvn);
+
+    // ---- Y = W X
+    wf32x4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = wf32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == kFrontMfma) {
+#pragma unroll
+      for (int e = 0; e < KS; ++e)
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[t][e], bx[e], acc[t], 0, 0, 0);
+    } else {
+      wf32x4 cor[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) cor[t] = wf32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < KS / 4; ++st) {
+        if constexpr (MODE == kFrontSplitF16) {
+          wf16x4 bh, bl;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float b = bx[4 * st + u];
+            const _Float16 hb = (_Float16)b;
+            bh[u] = hb;
+            bl[u] = (_Float16)((b - (float)hb) * 2048.0f);
+          }
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah16[t][st], bh, acc[t], 0, 0, 0);
+            cor[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah16[t][st], bl, cor[t], 0, 0, 0);
+            cor[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(al16[t][st], bh, cor[t], 0, 0, 0);
+          }
+        } else {
+          wi16x4 bh, bl;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float b = bx[4 * st + u];
+            const unsigned short hb = wbf16_rne(b);
+            bh[u] = (short)hb;
+            bl[u] = (short)wbf16_rne(b - wbf16_to_f32(hb));
+          }
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahb[t][st], bh, acc[t], 0, 0, 0);
+            cor[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahb[t][st], bl, cor[t], 0, 0, 0);
+            cor[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alb[t][st], bh, cor[t], 0, 0, 0);
+          }
+        }
+      }
+      const float sc = MODE == kFrontSplitF16 ? 1.0f / 2048.0f : 1.0f;
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] += sc * cor[t][v];
+    }
+
+    // ---- the iterate, and the outflow traces into the frontier (rows off
+    // every outflow face write into the sink FR[frn])
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * t + 4 * lk + v;
+        const bool ok = valid && i < NN;
+        const float y = acc[t][v];
+        bstore(rfc, ok ? (off + (unsigned)i) * 4u : kOob, y);
+      }
+    // (the cell values first: XO and the frontier share the LDS array, so a
+    // read placed after a frontier write would wait for it)
+    float xo[MT][4];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xo[t][v] = XO[li * XOS + 16 * t + 4 * lk + v];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float z = th * acc[t][v] + th1 * xo[t][v];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const int qf = (oq[t][v] >> (8 * a)) & 0xff;
+          FR[(valid && qf != 0xff) ? frb[a] + qf : frn] = z;
+        }
+      }
+
+    cb = ncb;
+    ce = nce;
+    lev = nlev2;
+    ncb = nncb;
+    nce = nnce;
+    nlev2 = nlev3;
+    dc = dn;
+    dn = dnn;
+  }
+}
+
+// waves per SIMD the register budget aims at: the 27-node cell holds the
+// two-tile operator slice and a tile of prefetched loads, which needs more
+// than a quarter of the register file
+template <int DIM, int P>
+constexpr int wave_occupancy() {
+  return WaveShape<DIM, P>::NN > 16 ? 3 : 4;
+}
+
+template <int MODE, int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<DIM, P>())))
+void k_sweep_front_wave(
+    const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
+    Geom g, FrontParams fp, const float* __restrict__ Wop, const int* __restrict__ lvl_start,
+    const int4* __restrict__ desc, int n_desc, BndRef<float> bd) {
+  extern __shared__ float wave_lds[];
+  using S = WaveShape<DIM, P>;
+  const int m = g.m, nn = S::NN;
+  const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
+  const int task = blockIdx.x;
+  const int c = task % m;
+  const int sd = (task / m) % nsd;
+  const int k = task / (m * nsd);
+  float* FR = wave_lds;                                // [3][fr_pos][FSTR], then the sink
+  float* XO = FR + 3 * fp.fr_pos * S::FSTR + 4;        // [16][XOS]
+
+  int sg[3], sdc[3], nbrel[3], isb[3], boff[3];
+  sdc[0] = sd % fp.nsub[0];
+  sdc[1] = (sd / fp.nsub[0]) % fp.nsub[1];
+  sdc[2] = sd / (fp.nsub[0] * fp.nsub[1]);
+  bool any_bnd = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sg[a] = a < DIM ? fp.sg[k][a] : 0;
+    nbrel[a] = 0;
+    isb[a] = 0;
+    boff[a] = 0;
+    if (sg[a] == 0) continue;
+    // the upwind neighbour of the subdomain's first cells along a: across an
+    // interface (iterate p-1), across the periodic wrap, or a Dirichlet box face
+    const int Sa = g.S[a], Na = g.N[a];
+    const int ga = sdc[a] * Sa + (sg[a] > 0 ? 0 : Sa - 1);
+    int nb = ga - sg[a];
+    const int64_t bo = bd.old != nullptr ? bd.off[a][sg[a] > 0 ? 0 : 1] : -1;
+    if ((nb < 0 || nb >= Na) && bo >= 0) {
+      isb[a] = 1;
+      boff[a] = (int)bo;
+      any_bnd = true;
+      continue;
+    }
+    if (nb < 0) nb += Na;
+    if (nb >= Na) nb -= Na;
+    const int stride = a == 0 ? 1 : (a == 1 ? g.N[0] : g.N[0] * g.N[1]);
+    nbrel[a] = (nb - ga) * stride * nn;
+  }
+  const int64_t plane = g.ncell * nn;
+  const int64_t pc = (int64_t)k * m + c;
+  const unsigned sdb = (unsigned)((sdc[0] * g.S[0] +
+                                   (int64_t)g.N[0] * (sdc[1] * g.S[1] + (int64_t)g.N[1] * sdc[2] * g.S[2])) *
+                                  nn);
+  const __amdgpu_buffer_rsrc_t rfo = wave_rsrc(f_old + pc * plane, plane * 4);
+  const __amdgpu_buffer_rsrc_t rfp = wave_rsrc(f_prev + pc * plane, plane * 4);
+  const __amdgpu_buffer_rsrc_t rfc = wave_rsrc(f_cur + pc * plane, plane * 4);
+  const float* Wk = Wop + (int64_t)k * nn * fp.Kd;
+  if (any_bnd) {
+    const __amdgpu_buffer_rsrc_t rbo = wave_rsrc(bd.old + pc * bd.nb, bd.nb * 4);
+    const __amdgpu_buffer_rsrc_t rbn = wave_rsrc(bd.neu + pc * bd.nb, bd.nb * 4);
+    front_wave_task<MODE, DIM, P, true>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel, isb,
+                                        boff, sdb, rfo, rfp, rfc, rbo, rbn, FR, XO);
+  } else {
+    front_wave_task<MODE, DIM, P, false>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel,
+                                         isb, boff, sdb, rfo, rfp, rfc, rfo, rfp, FR, XO);
+  }
+}
+
+// the (dim, nodes per axis) shapes the kernel is built for: 0..4, or -1
+int front_wave_shape(const Geom& g) {
+  if (g.dim == 3 && g.P == 2) return 0;
+  if (g.dim == 3 && g.P == 3) return 1;
+  if (g.dim == 2 && g.P == 2) return 2;
+  if (g.dim == 2 && g.P == 3) return 3;
+  if (g.dim == 2 && g.P == 4) return 4;
+  return -1;
+}
+
+template <int DIM, int P>
+size_t wave_lds_size(const FrontParams& fp) {
+  using S = WaveShape<DIM, P>;
+  return (3 * (size_t)fp.fr_pos * S::FSTR + 4 + 16 * (size_t)S::XOS) * sizeof(float);
+}
+
+}  // namespace
+
+size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp) {
+  switch (front_wave_shape(g)) {
+    case 0: return wave_lds_size<3, 2>(fp);
+    case 1: return wave_lds_size<3, 3>(fp);
+    case 2: return wave_lds_size<2, 2>(fp);
+    case 3: return wave_lds_size<2, 3>(fp);
+    case 4: return wave_lds_size<2, 4>(fp);
+    default: return 0;
+  }
+}
+
+bool front_wave_fits(int prec, int mode, const Geom& g, const FrontParams& fp, int64_t nb) {
+  const int64_t plane = g.ncell * g.nn;
+  return prec == KDS_FP32 && mode != kFrontFma && front_wave_shape(g) >= 0 &&
+         fp.Kd == g.nn + 3 * fp.nf && plane * 4 < ((int64_t)1 << 31) &&
+         nb * 4 < ((int64_t)1 << 31) && fp.fr_pos > 0 && front_wave_lds_bytes(g, fp) <= 64 * 1024;
+}
+
+hipError_t launch_sweep_front_wave(int mode, const Geom& g, const FrontParams& fp, const void* Wop,
+                                   const int* lvl_start, const int4* desc, int n_desc,
+                                   const void* f_old, const void* f_prev, void* f_cur,
+                                   const BndArgs& bnd, hipStream_t s) {
+  if (!front_wave_fits(KDS_FP32, mode, g, fp, bnd.nb) || n_desc <= 0) return hipErrorInvalidValue;
+  const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
+  const dim3 grid((unsigned)(nsd * g.nv * g.m)), block(64);
+  const size_t lds = front_wave_lds_bytes(g, fp);
+  const int shape = front_wave_shape(g);
+  const float* fo = (const float*)f_old;
+  const float* fpv = (const float*)f_prev;
+  float* fc = (float*)f_cur;
+  const float* W = (const float*)Wop;
+  const BndRef<float> bd = bnd_ref<float>(bnd);
+#define KDS_WAVE_LAUNCH(MODE, DIM, P)                                                            \
+  hipLaunchKernelGGL((k_sweep_front_wave<MODE, DIM, P>), grid, block, lds, s, fo, fpv, fc, g, fp, \
+                     W, lvl_start, desc, n_desc, bd)
+#define KDS_WAVE(MODE)                              \
+  switch (shape) {                                  \
+    case 0: KDS_WAVE_LAUNCH(MODE, 3, 2); break;     \
+    case 1: KDS_WAVE_LAUNCH(MODE, 3, 3); break;     \
+    case 2: KDS_WAVE_LAUNCH(MODE, 2, 2); break;     \
+    case 3: KDS_WAVE_LAUNCH(MODE, 2, 3); break;     \
+    default: KDS_WAVE_LAUNCH(MODE, 2, 4); break;    \
+  }
+  switch (mode) {
+    case kFrontMfma:
+      KDS_WAVE(kFrontMfma)
+      break;
+    case kFrontSplitF16:
+      KDS_WAVE(kFrontSplitF16)
+      break;
+    case kFrontSplitBf16:
+      KDS_WAVE(kFrontSplitBf16)
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef KDS_WAVE
+#undef KDS_WAVE_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace kds

@@ -695,6 +695,7 @@ hipError_t line_kernels_allow_lds(size_t bytes) {
   hipError_t e = line_allow_lds_f32(bytes);
   if (e == hipSuccess) e = line_allow_lds_f64(bytes);
   if (e == hipSuccess) done = bytes;
+  else (void)hipGetLastError();
   return e;
 }
 
