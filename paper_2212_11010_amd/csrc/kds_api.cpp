@@ -343,9 +343,23 @@ bool build_front(kds_problem* p, const Basis1D& basis, std::vector<double>& W,
                                      (y + S1 * z) | ((x + S0 * z) << 16), x + S0 * y));
         }
     for (int l = 0; l <= maxlev; ++l) {
+      // inside a front any order will do: the cells first along some active
+      // axis (their inflow comes across an interface or a box face) go first,
+      // so that the wave kernel's tiles of other cells skip those loads
+      std::vector<int> ord(by[l].size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+      auto first = [&](int i) {
+        const int pk = by[l][i];
+        for (int a = 0; a < 3; ++a)
+          if (act[a] && ((pk >> (10 * a)) & 1023) == 0) return true;
+        return false;
+      };
+      std::stable_partition(ord.begin(), ord.end(), first);
       lvl_start.push_back((int)lvl_cells.size());
-      lvl_cells.insert(lvl_cells.end(), by[l].begin(), by[l].end());
-      desc.insert(desc.end(), dby[l].begin(), dby[l].end());
+      for (int i : ord) {
+        lvl_cells.push_back(by[l][i]);
+        desc.push_back(dby[l][i]);
+      }
     }
     lvl_start.push_back((int)lvl_cells.size());
   }

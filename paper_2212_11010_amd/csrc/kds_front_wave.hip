@@ -70,8 +70,26 @@ __device__ __forceinline__ void bload_run(__amdgpu_buffer_rsrc_t r, unsigned o, 
     v[0] = bload(r, o);
   }
 }
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+// n consecutive values to byte offset o, with the widest stores
+template <int N>
+__device__ __forceinline__ void bstore_run(__amdgpu_buffer_rsrc_t r, unsigned o, const float* v) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u3 __attribute__((ext_vector_type(3)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if constexpr (N >= 4) {
+    const u4 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                  __float_as_uint(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, o, 0, 0);
+    bstore_run<N - 4>(r, o + 16u, v + 4);
+  } else if constexpr (N == 3) {
+    const u3 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
+    __builtin_amdgcn_raw_buffer_store_b96(x, r, o, 0, 0);
+  } else if constexpr (N == 2) {
+    const u2 x = {__float_as_uint(v[0]), __float_as_uint(v[1])};
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, o, 0, 0);
+  } else if constexpr (N == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, o, 0, 0);
+  }
 }
 
 __device__ __forceinline__ unsigned short wbf16_rne(float x) {
@@ -233,15 +251,20 @@ __device__ __forceinline__ void front_wave_task(
         if (first && isb[a]) bb4 = (unsigned)(boff[a] + fcell * NF) * 4u;
       }
 #pragma unroll
-      for (int j = 0; j < FS; ++j) {
-        const int s = a * FS + j;
-        pvo[s] = bload(rfo, nb4 + nbn4[a][j]);
-        pvn[s] = bload(rfp, nb4 + nbn4[a][j]);
-        if constexpr (BND) {
-          // a row reads the state or the boundary data, never both: the
-          // other load is out of range and adds an exact 0
-          pvo[s] += bload(rbo, bb4 + bq4[j]);
-          pvn[s] += bload(rbn, bb4 + bq4[j]);
+      for (int j = 0; j < FS; ++j) pvo[a * FS + j] = pvn[a * FS + j] = 0.0f;
+      // (the host puts a front's first cells first: most tiles have none)
+      if (__any(first)) {
+#pragma unroll
+        for (int j = 0; j < FS; ++j) {
+          const int s = a * FS + j;
+          pvo[s] = bload(rfo, nb4 + nbn4[a][j]);
+          pvn[s] = bload(rfp, nb4 + nbn4[a][j]);
+          if constexpr (BND) {
+            // a row reads the state or the boundary data, never both: the
+            // other load is out of range and adds an exact 0
+            pvo[s] += bload(rbo, bb4 + bq4[j]);
+            pvn[s] += bload(rbn, bb4 + bq4[j]);
+          }
         }
       }
     }
@@ -359,19 +382,11 @@ __device__ __forceinline__ void front_wave_task(
         for (int v = 0; v < 4; ++v) acc[t][v] += sc * cor[t][v];
     }
 
-    // ---- the iterate, and the outflow traces into the frontier (rows off
-    // every outflow face write into the sink FR[frn])
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * t + 4 * lk + v;
-        const bool ok = valid && i < NN;
-        const float y = acc[t][v];
-        bstore(rfc, ok ? (off + (unsigned)i) * 4u : kOob, y);
-      }
-    // (the cell values first: XO and the frontier share the LDS array, so a
-    // read placed after a frontier write would wait for it)
+    // ---- the outflow traces into the frontier (rows off every outflow face
+    // write into the sink FR[frn]), and the iterate through the tile buffer:
+    // the cell values at t^{n-1} are read out of it first and replaced by
+    // the new ones, which each lane then stores as its run of consecutive
+    // nodes with wide stores (a product row is spread over the lanes)
     float xo[MT][4];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
@@ -382,12 +397,17 @@ __device__ __forceinline__ void front_wave_task(
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float z = th * acc[t][v] + th1 * xo[t][v];
+        XO[li * XOS + 16 * t + 4 * lk + v] = acc[t][v];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           const int qf = (oq[t][v] >> (8 * a)) & 0xff;
           FR[(valid && qf != 0xff) ? frb[a] + qf : frn] = z;
         }
       }
+    float yr[CS];
+#pragma unroll
+    for (int e = 0; e < CS; ++e) yr[e] = XO[li * XOS + cst + e];
+    bstore_run<CS>(rfc, valid ? (off + (unsigned)cst) * 4u : kOob, yr);
 
     cb = ncb;
     ce = nce;
@@ -400,16 +420,16 @@ __device__ __forceinline__ void front_wave_task(
   }
 }
 
-// waves per SIMD the register budget aims at: the 27-node cell holds the
-// two-tile operator slice and a tile of prefetched loads, which needs more
-// than a quarter of the register file
-template <int DIM, int P>
+// waves per SIMD the register budget aims at: with the 27-node cell, the
+// split forms (operator slice as hi / lo halves) need more than a quarter of
+// the register file
+template <int MODE, int DIM, int P>
 constexpr int wave_occupancy() {
-  return WaveShape<DIM, P>::NN > 16 ? 3 : 4;
+  return (WaveShape<DIM, P>::NN > 16 && MODE != kFrontMfma) ? 3 : 4;
 }
 
 template <int MODE, int DIM, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<DIM, P>())))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
 void k_sweep_front_wave(
     const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
     Geom g, FrontParams fp, const float* __restrict__ Wop, const int* __restrict__ lvl_start,
