@@ -198,23 +198,6 @@ __device__ __forceinline__ void front_wave_task(
       nbn4[a][j] = a < DIM ? 4u * node : kOob;
     }
   }
-  // per output row: its indices on the outflow faces, 8 bits per axis (0xff: not on it)
-  int oq[MT][4];
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * t + 4 * lk + v;
-      const int id[3] = {i % P, (i / P) % P, DIM == 3 ? i / (P * P) : 0};
-      int w = 0xffffff;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const int side = sg[a] > 0 ? P - 1 : 0;
-        const int q = a == 0 ? id[1] + P * id[2] : (a == 1 ? id[0] + P * id[2] : id[0] + P * id[1]);
-        if (i < NN && sg[a] != 0 && id[a] == side) w = (w & ~(0xff << (8 * a))) | (q << (8 * a));
-      }
-      oq[t][v] = w;
-    }
   // the frontier starts at zero (a read it serves before the upwind cell wrote
   // it is discarded, but stays a finite number)
   for (int x = lane; x <= frn; x += 64) FR[x] = 0.0f;
@@ -382,32 +365,38 @@ __device__ __forceinline__ void front_wave_task(
         for (int v = 0; v < 4; ++v) acc[t][v] += sc * cor[t][v];
     }
 
-    // ---- the outflow traces into the frontier (rows off every outflow face
-    // write into the sink FR[frn]), and the iterate through the tile buffer:
-    // the cell values at t^{n-1} are read out of it first and replaced by
-    // the new ones, which each lane then stores as its run of consecutive
-    // nodes with wide stores (a product row is spread over the lanes)
+    // ---- the iterate and the outflow traces, through the tile buffer (a
+    // product row is spread over four lanes; the buffer regroups the values
+    // by cell): it holds the values at t^{n-1}, then the new ones, which each
+    // lane stores as its run of nodes with wide stores, then the traces
+    // theta y + (1 - theta) f^{n-1}, which each lane copies into the frontier
+    // for its face-node runs (a cell's outflow node with face index q on axis
+    // a is the node its downwind neighbour reads as the upwind one)
+    float* TB = XO + li * XOS;
     float xo[MT][4];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xo[t][v] = XO[li * XOS + 16 * t + 4 * lk + v];
+      for (int v = 0; v < 4; ++v) xo[t][v] = TB[16 * t + 4 * lk + v];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float z = th * acc[t][v] + th1 * xo[t][v];
-        XO[li * XOS + 16 * t + 4 * lk + v] = acc[t][v];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          const int qf = (oq[t][v] >> (8 * a)) & 0xff;
-          FR[(valid && qf != 0xff) ? frb[a] + qf : frn] = z;
-        }
-      }
+      for (int v = 0; v < 4; ++v) TB[16 * t + 4 * lk + v] = acc[t][v];
     float yr[CS];
 #pragma unroll
-    for (int e = 0; e < CS; ++e) yr[e] = XO[li * XOS + cst + e];
+    for (int e = 0; e < CS; ++e) yr[e] = TB[cst + e];
     bstore_run<CS>(rfc, valid ? (off + (unsigned)cst) * 4u : kOob, yr);
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) TB[16 * t + 4 * lk + v] = th * acc[t][v] + th1 * xo[t][v];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int j = 0; j < FS; ++j) {
+        const float z = TB[nbn4[a][j] >> 2];
+        FR[(valid && sg[a] != 0) ? frb[a] + fst + j : frn] = z;
+      }
 
     cb = ncb;
     ce = nce;
