@@ -202,9 +202,15 @@ kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec)
  * workgroups share a CU).  Axes that carry no velocity have Q = bw = 0.  For
  * the plain and front schedules these fields are 0 (kds_get_plan) and
  * ignored (kds_set_plan).  step_eager and relax_vec as in kds_set_launch.
+ * front_kernel (front schedule; 0 elsewhere): 1 = one workgroup per
+ * (velocity, subdomain), any cell size and precision; 2 = one wave per
+ * (velocity, subdomain, component), the FP32 matrix-core forms with cells of
+ * at most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D) and frontiers that fit the
+ * LDS; kds_set_plan with front_kernel = 0 keeps the current kernel.
  * The FP64 results of every valid plan agree to rounding; FP32 results depend
- * on Q (the association of the line scan), so a plan saved with kds_get_plan
- * and restored with kds_set_plan reproduces results bitwise across runs. */
+ * on Q (the association of the line scan) and on the front kernel (the order
+ * of the products' sums), so a plan saved with kds_get_plan and restored with
+ * kds_set_plan reproduces results bitwise across runs. */
 typedef struct {
   int32_t Q[3];
   int32_t bw[3];
@@ -212,6 +218,7 @@ typedef struct {
   int32_t lds_bytes;
   int32_t step_eager;
   int32_t relax_vec;
+  int32_t front_kernel;
 } kds_plan_t;
 
 /* Current plan into *plan.  KDS_E_INVALID for NULL arguments. */
@@ -220,8 +227,9 @@ kds_status kds_get_plan(const kds_problem* p, kds_plan_t* plan);
 /* Replace the plan.  Errors (the plan is left unchanged): KDS_E_INVALID for
  * NULL arguments, flags other than 0 / 1, a line-schedule choice outside the
  * limits above (xdirect = 1 needs a velocity along x with Q[0] = line_qmax),
- * or lds_bytes above the device's per-workgroup LDS; Q and bw entries of an
- * axis without velocities are ignored. */
+ * lds_bytes above the device's per-workgroup LDS, or a front_kernel that does
+ * not apply to the problem; Q and bw entries of an axis without velocities
+ * are ignored. */
 kds_status kds_set_plan(kds_problem* p, const kds_plan_t* plan);
 
 /* Average duration of one launch of each kernel kind (sweep: the line kernel,

@@ -440,6 +440,14 @@ hipError_t launch_front_iter(kds_problem* p, const void* f_prev, void* f_cur, hi
                             p->front_lvl_start, p->front_lvl_cells, p->f, f_prev, f_cur, p->bnd(), s);
 }
 
+// Which front kernels can run this problem.
+bool front_wave_ok(const kds_problem* p) {
+  return p->front_ndesc > 0 && front_wave_fits(p->prec, p->front_mode, p->geom, p->front, p->nbnd);
+}
+bool front_wg_ok(const kds_problem* p) {
+  return front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) <= 64 * 1024;
+}
+
 // Enqueue one time step (transport then relaxation) on the problem's stream.
 // With events, records ev[0] before the transport, ev[1] between transport and
 // relaxation, ev[2] after.
@@ -661,9 +669,8 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     p->front_ndesc = (int)front_desc.size();
     // the wave-per-task kernel where it applies (its records fit, FP32
     // matrix-core modes, p <= 2 in 3-D), else one workgroup per subdomain
-    p->front_wave = p->front_ndesc > 0 && front_wave_fits(p->prec, p->front_mode, p->geom, p->front,
-                                                          p->nbnd);
-    if (!p->front_wave && front_lds_bytes(p->prec, p->front_mode, p->geom, p->front) > 64 * 1024) {
+    p->front_wave = front_wave_ok(p);
+    if (!p->front_wave && !front_wg_ok(p)) {
       delete p;
       return fail(nullptr, KDS_E_UNSUPPORTED, "front schedule: cell operator too large for the LDS");
     }
@@ -903,7 +910,7 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   const LinePlan plan0 = p->plan;
   int Q0[3], bw0[3];
   for (int a = 0; a < 3; ++a) { Q0[a] = p->line_Q[a]; bw0[a] = p->line_bw[a]; }
-  const bool eager0 = p->eager_steps, vec0 = p->relax_vec;
+  const bool eager0 = p->eager_steps, vec0 = p->relax_vec, wave0 = p->front_wave;
   kds_status st = KDS_OK;
   auto time_plan = [&](const LinePlan& pl, float* ms) -> bool {
     hipError_t e = launch_sweep_line(p->prec, p->geom, p->sweep_blob.data(), pl, p->f, p->bnd(),
@@ -978,6 +985,33 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
         best = ms;
         p->plan = pl;
       }
+    }
+  }
+  // front schedule: the wave-per-task kernel against the workgroup kernel,
+  // where both apply (one subdomain iteration from the saved state each;
+  // the arithmetic is the same up to rounding order)
+  if (ok && p->sched == KDS_SCHED_FRONT && front_wave_ok(p) && front_wg_ok(p)) {
+    float ms_k[2] = {0.0f, 0.0f};
+    for (int pass = 0; pass < 2 && ok; ++pass)
+      for (int w = 0; w < 2 && ok; ++w) {
+        p->front_wave = w == 1;
+        hipError_t e = launch_front_iter(p, p->f, p->fit[1], p->stream);
+        if (e == hipSuccess) e = hipEventRecord(p->ev[0], p->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+          e = launch_front_iter(p, p->f, p->fit[1], p->stream);
+        if (e == hipSuccess) e = hipEventRecord(p->ev[1], p->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(p->ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->ev[0], p->ev[1]);
+        if (e != hipSuccess) {
+          st = hip_fail(p, e, "kds_tune");
+          ok = false;
+        }
+        ms_k[w] += ms / reps;
+      }
+    if (ok) {
+      p->front_wave = ms_k[1] < 0.97f * ms_k[0];
+      best = 0.5f * (p->front_wave ? ms_k[1] : ms_k[0]);
     }
   }
   // step launch mode: captured graphs of kGraphSteps steps against the step's
@@ -1057,13 +1091,14 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
     for (int a = 0; a < 3; ++a) { p->line_Q[a] = Q0[a]; p->line_bw[a] = bw0[a]; }
     p->eager_steps = eager0;
     p->relax_vec = vec0;
+    p->front_wave = wave0;
     drop_graphs(p);
     return ok ? hip_fail(p, e, "kds_tune restore") : st;
   }
   drop_graphs(p);
   p->tuned = line;
   if (line) ++p->plan_version;
-  if (sweep_ms) *sweep_ms = line ? best : -1.0;
+  if (sweep_ms) *sweep_ms = (line || best > 0.0f) ? best : -1.0;
   return KDS_OK;
 }
 
@@ -1089,6 +1124,7 @@ kds_status kds_get_plan(const kds_problem* p, kds_plan_t* pl) {
     pl->xdirect = p->plan.xdirect;
     pl->lds_bytes = p->plan.lds_alloc > p->plan.lds_elems ? p->plan.lds_alloc * (int)p->elem : 0;
   }
+  if (p->sched == KDS_SCHED_FRONT) pl->front_kernel = p->front_wave ? 2 : 1;
   pl->step_eager = p->eager_steps ? 1 : 0;
   pl->relax_vec = p->relax_vec ? 1 : 0;
   return KDS_OK;
@@ -1133,6 +1169,15 @@ kds_status kds_set_plan(kds_problem* p, const kds_plan_t* pl) {
     for (int a = 0; a < 3; ++a) { p->line_Q[a] = tq[a]; p->line_bw[a] = tb[a]; }
     p->plan = np;
     ++p->plan_version;
+  }
+  if (p->sched == KDS_SCHED_FRONT && pl->front_kernel != 0) {
+    if (pl->front_kernel == 2 && front_wave_ok(p)) p->front_wave = true;
+    else if (pl->front_kernel == 1 && front_wg_ok(p)) p->front_wave = false;
+    else
+      return fail(p, KDS_E_INVALID,
+                  std::string("kds_set_plan: front_kernel ") + std::to_string(pl->front_kernel) +
+                      " does not apply (1: workgroup kernel" + (front_wg_ok(p) ? "" : ", not here") +
+                      "; 2: wave kernel" + (front_wave_ok(p) ? "" : ", not here") + ")");
   }
   p->eager_steps = pl->step_eager == 1;
   p->relax_vec = pl->relax_vec == 1;

@@ -66,6 +66,7 @@ class kds_plan_t(C.Structure):
     _fields_ = [
         ("Q", C.c_int32 * 3), ("bw", C.c_int32 * 3), ("xdirect", C.c_int32),
         ("lds_bytes", C.c_int32), ("step_eager", C.c_int32), ("relax_vec", C.c_int32),
+        ("front_kernel", C.c_int32),
     ]
 
 

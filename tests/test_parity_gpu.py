@@ -264,6 +264,9 @@ FRONT_CASES = {
     "maxwell_q3": (6, dict(n_cells=[4, 4, 4], sub_cells=[2, 4, 4], steps=2, degree=3)),
     "maxwell_q2_k1_theta1": (6, dict(n_cells=[8, 4, 4], sub_cells=[4, 2, 4], steps=2,
                                      n_iter=1, theta=1.0)),
+    # 8^3 subdomains: fronts of up to 48 cells, several 16-cell tiles of the
+    # wave kernel per front (first cells first, then the rest)
+    "maxwell_q2_sub8": (6, dict(n_cells=[16, 8, 8], sub_cells=[8, 8, 8], steps=2)),
     # axis-aligned sets through the front kernel (cross-check of the schedules)
     "cfg2_front": (2, dict(n_cells=[24, 16], sub_cells=[8, 8], steps=3)),
     "cfg3_front": (3, dict(n_cells=[8, 6, 4], sub_cells=[4, 3, 4], steps=2)),
@@ -293,13 +296,28 @@ def front_case(name):
 
 @pytest.mark.parametrize("name", list(FRONT_CASES))
 @pytest.mark.parametrize("prec", list(FRONT_TOL))
-def test_front_schedule_parity(name, prec):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_front_schedule_parity(name, prec, kernel):
+    """Both front kernels, forced through the plan (1: workgroup per
+    (velocity, subdomain); 2: wave per (velocity, subdomain, component), FP32
+    matrix-core forms and cells of at most 32 nodes only)."""
     import torch
     from paper_2212_11010_amd import kds
     spec, W0, Fref, Wref = front_case(name)
-    print("front case", name, prec, flush=True)
+    print("front case", name, prec, "kernel", kernel, flush=True)
     with kds.Problem(spec, precision=prec, schedule="front") as pb:
         assert pb.info()["schedule"] == kds.KDS_SCHED_FRONT
+        plan = pb.get_plan()
+        plan["front_kernel"] = kernel
+        try:
+            pb.set_plan(plan)
+        except kds.KdsError as e:
+            assert e.status == kds.KDS_E_INVALID, e
+            nodes = (spec["degree"] + 1) ** len(spec["n_cells"])
+            wave_ok = prec != "fp64" and nodes <= 32
+            assert kernel == 2 and not wave_ok, "front kernel %d refused" % kernel
+            pytest.skip("the wave kernel does not apply (%s, degree %d)" % (prec, spec["degree"]))
+        assert pb.get_plan()["front_kernel"] == kernel
         pb.set_state(torch.from_numpy(W0).cuda())
         pb.step(spec["steps"])
         W = pb.moments()
@@ -312,3 +330,8 @@ def test_auto_picks_front_for_oblique_velocities():
     spec, _, _, _ = front_case("maxwell_q2")
     with kds.Problem(spec, precision="fp32") as pb:
         assert pb.info()["schedule"] == kds.KDS_SCHED_FRONT
+    # the wave kernel by default where it applies, the workgroup kernel elsewhere
+    with kds.Problem(spec, precision="fp32_split_bf16") as pb:
+        assert pb.get_plan()["front_kernel"] == 2
+    with kds.Problem(spec, precision="fp64") as pb:
+        assert pb.get_plan()["front_kernel"] == 1
