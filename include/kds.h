@@ -136,7 +136,10 @@ typedef struct {
 kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out);
 
 /* Initial kinetic state F_k = M_k(W) at every node (Sec. 2.2).
- * W: FP64 [cell][node][c].  Resets the step counter. */
+ * W: FP64 [cell][node][c].  Resets the step counter.  A W with NaN or Inf
+ * (or whose equilibria overflow the storage precision) is refused with
+ * KDS_E_NONFINITE and leaves no state (kds_step then returns KDS_E_STATE).
+ * Euler law: also records the state's largest wave speed (kds_info). */
 kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device);
 
 /* Dirichlet data on the faces of the axes with periodic[a] = 0 (the exact
@@ -292,6 +295,23 @@ typedef struct {
                              per thread (kds_tune's choice) */
   int32_t line_qmax;      /* line schedule: most cells per lane (register
                              budget of 64 state values per lane), 0 otherwise */
+  /* Stability warnings (the problem runs regardless):
+   * eq_monotone: 1 if every equilibrium derivative dM_k/dW =
+   *   a_k I + sum_i b_{k,i} A^i is positive semidefinite (linear law with
+   *   symmetric A^i, checked at create; the bound on lambda that keeps the
+   *   relaxation monotone, under which the entropy argument of Sec. 2.2
+   *   holds), 0 if one has a negative eigenvalue (eq_min_eig, the smallest),
+   *   -1 if not checked (Euler law, non-symmetric A^i);
+   * max_wave_speed: linear law, max_i of the spectral radius of A^i (at
+   *   create); Euler, max over the nodes of the last kds_set_state and the
+   *   axes of |u_i| + c (+inf where rho <= 0 or p <= 0); -1 if unknown;
+   * subchar_ok: 1 if min_k |V_k| > max_wave_speed (the sub-characteristic
+   *   condition of Sec. 2.1, along the coordinate directions), 0 if not, -1
+   *   if max_wave_speed is unknown. */
+  int32_t eq_monotone;
+  double eq_min_eig;
+  double max_wave_speed;
+  int32_t subchar_ok;
 } kds_info_t;
 kds_status kds_info(const kds_problem* p, kds_info_t* info);
 

@@ -17,7 +17,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kds_oracle.cpp")
-LIB = os.path.join(HERE, "liboracle.so")
+# KDS_ORACLE_LIB: another build of the same source (the sanitizer test's)
+LIB = os.environ.get("KDS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 
 def build(force: bool = True) -> str:

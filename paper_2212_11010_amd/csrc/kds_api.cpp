@@ -48,6 +48,11 @@ struct kds_problem {
   bool relax_vec = false;    // relaxation with 16-byte accesses (autotuner's choice)
   double max_nu = 0, min_sub_width = 0;
   bool proposition_ok = true;
+  // stability warnings (kds_info): equilibrium monotonicity (linear law),
+  // largest wave speed against the smallest kinetic speed
+  int eq_monotone = -1;
+  double eq_min_eig = 0.0, wave_speed = -1.0, min_speed = 0.0;
+  unsigned long long* wmax = nullptr;  // device: reduction of the Euler wave speed
   // device
   int device = 0;
   hipStream_t stream = nullptr;
@@ -412,7 +417,7 @@ void free_device(kds_problem* p) {
   drop_graphs(p);
   for (auto& e : p->ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
-  void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->front_W,
+  void* bufs[] = {p->f, p->f_tmp, p->tr[0], p->tr[1], p->stage, p->flag, p->wmax, p->front_W,
                   p->front_lvl_start, p->front_lvl_cells, p->front_desc, p->fit[0], p->fit[1],
                   p->fb, p->Wb_dev,
                   p->eq_dev};
@@ -427,6 +432,7 @@ void free_device(kds_problem* p) {
   p->eq_dev = nullptr;
   p->stage = nullptr;
   p->flag = nullptr;
+  p->wmax = nullptr;
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   p->stream = nullptr;
 }
@@ -587,6 +593,24 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     delete p;
     return fail(nullptr, KDS_E_INVALID, msg);
   }
+  // warnings: sub-characteristic condition (Sec. 2.1) and equilibrium
+  // monotonicity; for Euler the wave speed is taken from each kds_set_state
+  p->min_speed = 1e300;
+  for (int k = 0; k < p->nv; ++k) {
+    double v2 = 0.0;
+    for (int i = 0; i < p->dim; ++i) v2 += p->vel[k * p->dim + i] * p->vel[k * p->dim + i];
+    p->min_speed = std::min(p->min_speed, std::sqrt(v2));
+  }
+  if (p->law == KDS_LAW_LINEAR) {
+    const EqChecks ec = check_linear_law(p->dim, p->m, p->nv, p->law_params, a, b);
+    if (ec.checked) {
+      p->wave_speed = ec.wave_speed;
+      p->eq_min_eig = ec.min_eig;
+      double amax = 1.0;
+      for (double x : a) amax = std::max(amax, std::fabs(x));
+      p->eq_monotone = ec.min_eig >= -1e-12 * amax ? 1 : 0;
+    }
+  }
   std::vector<double> mu;
   if (cfg->source_sigma) {
     mu.resize(p->m);
@@ -708,6 +732,7 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     return true;
   };
   bool ok = alloc(&p->f, state_bytes) && alloc((void**)&p->flag, sizeof(int)) &&
+            alloc((void**)&p->wmax, sizeof(unsigned long long)) &&
             alloc(&p->eq_dev, p->eq_blob.size());
   if (ok)
     ok = hipMemcpy(p->eq_dev, p->eq_blob.data(), p->eq_blob.size(), hipMemcpyHostToDevice) ==
@@ -809,7 +834,32 @@ kds_status kds_set_state(kds_problem* p, const double* W, int32_t on_device) {
     src = p->stage;
   }
   KDS_HIP(p, launch_init(p->prec, p->law, p->geom, p->eq_blob.data(), src, p->f, p->stream));
+  // a state with NaN / Inf (or equilibria that overflow the storage) is refused
+  const int zero = 0;
+  int flag = 0;
+  KDS_HIP(p, hipMemcpyAsync(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  KDS_HIP(p, launch_check_finite(p->prec, p->geom, p->f, p->flag, p->stream));
+  KDS_HIP(p, hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  // Euler: the largest wave speed of this state (sub-characteristic check)
+  unsigned long long wbits = 0;
+  if (p->law == KDS_LAW_EULER) {
+    const unsigned long long z = 0;
+    KDS_HIP(p, hipMemcpyAsync(p->wmax, &z, sizeof(z), hipMemcpyHostToDevice, p->stream));
+    KDS_HIP(p, launch_euler_wave_speed(src, p->plane(), p->dim, p->law_params[0], p->wmax, p->stream));
+    KDS_HIP(p, hipMemcpyAsync(&wbits, p->wmax, sizeof(wbits), hipMemcpyDeviceToHost, p->stream));
+  }
   KDS_HIP(p, hipStreamSynchronize(p->stream));
+  if (flag) {
+    p->state_set = false;
+    return fail(p, KDS_E_NONFINITE,
+                "kds_set_state: W holds NaN or Inf (or values whose equilibria overflow the "
+                "storage precision)");
+  }
+  if (p->law == KDS_LAW_EULER) {
+    double ws;
+    std::memcpy(&ws, &wbits, sizeof(ws));
+    p->wave_speed = ws;
+  }
   p->state_set = true;
   p->steps_done = 0;
   return KDS_OK;
@@ -1354,6 +1404,10 @@ kds_status kds_info(const kds_problem* p, kds_info_t* info) {
       p->sched == KDS_SCHED_LINE
           ? (int32_t)(std::max(p->plan.lds_elems, p->plan.lds_alloc) * (int)p->elem)
           : 0;
+  info->eq_monotone = p->eq_monotone;
+  info->eq_min_eig = p->eq_min_eig;
+  info->max_wave_speed = p->wave_speed;
+  info->subchar_ok = p->wave_speed < 0.0 ? -1 : (p->min_speed > p->wave_speed ? 1 : 0);
   return KDS_OK;
 }
 

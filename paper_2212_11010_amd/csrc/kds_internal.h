@@ -49,6 +49,20 @@ bool make_dense_op(const Basis1D& b, int dim, const double* V, const double* h, 
 bool eq_weights(int dim, int nv, const double* vel, const double* eq_a, const double* eq_b,
                 std::vector<double>& a, std::vector<double>& b, std::string& err);
 
+// Eigenvalues of a symmetric n x n matrix (row-major), Jacobi rotations.
+void sym_eigenvalues(int n, std::vector<double> A, std::vector<double>& ev);
+
+// Stability checks of a linear law's kinetic model: largest wave speed
+// max_i rho(A^i) and smallest eigenvalue of the equilibrium derivatives
+// a_k I + sum_i b_{k,i} A^i (checked only for symmetric A^i).
+struct EqChecks {
+  bool checked = false;
+  double wave_speed = 0.0;
+  double min_eig = 0.0;
+};
+EqChecks check_linear_law(int dim, int m, int nv, const std::vector<double>& A,
+                          const std::vector<double>& a, const std::vector<double>& b);
+
 // ------------------------------------------------------- device parameters
 
 struct Geom {
@@ -211,6 +225,10 @@ hipError_t scratch_address(void** out);
 hipError_t launch_get_kinetic(int prec, const Geom& g, const void* f, double* F, hipStream_t s);
 hipError_t launch_set_kinetic(int prec, const Geom& g, const double* F, void* f, hipStream_t s);
 hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag, hipStream_t s);
+// Largest |u_i| + c of an Euler state W [node][d + 2] (FP64, device), as the
+// bits of a double max-reduced into *out (which the caller zeroes).
+hipError_t launch_euler_wave_speed(const double* W, int64_t nodes, int dim, double gamma,
+                                   unsigned long long* out, hipStream_t s);
 hipError_t launch_sweep_plain(int prec, const Geom& g, const void* tab, const void* f_old,
                               void* f_new, const void* tr_prev, void* tr_out, const BndArgs& bnd,
                               hipStream_t s);

@@ -268,6 +268,35 @@ __global__ __launch_bounds__(256) void k_check_finite(const T* __restrict__ f, i
   if (bad) flag[0] = 1;  // every writer stores the same value
 }
 
+// Largest wave speed of a compressible Euler state W [node][d + 2] (FP64):
+// max over nodes and axes of |u_i| + c, c = sqrt(gamma p / rho).  A node
+// without a real wave speed (rho <= 0, p <= 0, NaN) counts as +inf.  The
+// result is reduced as the bits of a non-negative double with an unsigned
+// maximum, which orders non-negative doubles like their values.
+__global__ __launch_bounds__(256) void k_euler_wave_speed(const double* __restrict__ W,
+                                                          int64_t nodes, int dim, double gamma,
+                                                          unsigned long long* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double best = 0.0;
+  for (; i < nodes; i += stride) {
+    const double* w = W + i * (dim + 2);
+    const double rho = w[0], E = w[dim + 1];
+    double ke = 0.0, umax = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      const double u = w[1 + a] / rho;
+      ke += u * u;
+      umax = fmax(umax, fabs(u));
+    }
+    const double pr = (gamma - 1.0) * (E - 0.5 * rho * ke);
+    // (a NaN anywhere fails one of the comparisons: +inf)
+    const double sp = (rho > 0.0 && pr > 0.0) ? umax + sqrt(gamma * pr / rho) : INFINITY;
+    best = fmax(best, sp);
+  }
+  for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
 // ====================================================== plain sweep
 
 // One subdomain iteration p of the downwind sweep for every (velocity,
@@ -611,6 +640,13 @@ hipError_t launch_check_finite(int prec, const Geom& g, const void* f, int* flag
     hipLaunchKernelGGL(k_check_finite<double>, dim3(nb), dim3(256), 0, s, (const double*)f, n, flag);
   else
     hipLaunchKernelGGL(k_check_finite<float>, dim3(nb), dim3(256), 0, s, (const float*)f, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_wave_speed(const double* W, int64_t nodes, int dim, double gamma,
+                                   unsigned long long* out, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nodes), 1024));
+  hipLaunchKernelGGL(k_euler_wave_speed, dim3(nb), dim3(256), 0, s, W, nodes, dim, gamma, out);
   return hipGetLastError();
 }
 

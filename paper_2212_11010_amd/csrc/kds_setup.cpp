@@ -1,6 +1,7 @@
 // kds_setup.cpp -- one-time FP64 host setup of libkds: Gauss-Lobatto basis,
 // the 1-D cell operator of the implicit upwind DG transport and its local
 // inverse, equilibrium weights.
+#include <algorithm>
 #include <cmath>
 
 #include "kds_internal.h"
@@ -217,6 +218,84 @@ bool eq_weights(int dim, int nv, const double* vel, const double* eq_a, const do
 }  // namespace kds
 
 namespace kds {
+
+// Eigenvalues of a symmetric n x n matrix (row-major), by cyclic Jacobi
+// rotations: each rotation zeroes one off-diagonal pair; sweeps until the
+// off-diagonal mass is negligible.
+void sym_eigenvalues(int n, std::vector<double> A, std::vector<double>& ev) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-30 * (tot + 1e-300)) break;
+    for (int pq = 0; pq < n * n; ++pq) {
+      const int pp = pq / n, q = pq % n;
+      if (q <= pp || A[pp * n + q] == 0.0) continue;
+      // the angle that zeroes A[pp][q]
+      const double tau = (A[q * n + q] - A[pp * n + pp]) / (2.0 * A[pp * n + q]);
+      const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+      const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+      for (int k = 0; k < n; ++k) {  // columns pp, q
+        const double akp = A[k * n + pp], akq = A[k * n + q];
+        A[k * n + pp] = c * akp - sn * akq;
+        A[k * n + q] = sn * akp + c * akq;
+      }
+      for (int k = 0; k < n; ++k) {  // rows pp, q
+        const double apk = A[pp * n + k], aqk = A[q * n + k];
+        A[pp * n + k] = c * apk - sn * aqk;
+        A[q * n + k] = sn * apk + c * aqk;
+      }
+    }
+  }
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+}
+
+// Checks of a linear law's kinetic model (warnings; the problem still runs).
+//   * Sub-characteristic condition (Sec. 2.1): the kinetic speeds must
+//     exceed the largest wave speed, max over directions of |eig(sum_i N_i A^i)|;
+//     with symmetric A^i that is at most max_i rho(A^i) times sqrt(d) and at
+//     least max_i rho(A^i) -- the check uses the coordinate directions,
+//     max_i rho(A^i).
+//   * Monotonicity of the equilibrium (the bound lambda must satisfy so that
+//     the relaxation keeps the kinetic entropy argument of Sec. 2.2): every
+//     dM_k/dW = a_k I + sum_i b_{k,i} A^i positive semidefinite.
+// Both need symmetric A^i (then the eigenvalues are real and the Jacobi
+// method applies); otherwise checked = false.
+EqChecks check_linear_law(int dim, int m, int nv, const std::vector<double>& A,
+                          const std::vector<double>& a, const std::vector<double>& b) {
+  EqChecks r;
+  const double scale = [&] {
+    double s = 0.0;
+    for (double x : A) s = std::max(s, std::fabs(x));
+    return s + 1.0;
+  }();
+  for (int i = 0; i < dim; ++i)
+    for (int u = 0; u < m; ++u)
+      for (int v = 0; v < u; ++v)
+        if (std::fabs(A[(size_t)i * m * m + u * m + v] - A[(size_t)i * m * m + v * m + u]) >
+            1e-12 * scale)
+          return r;
+  r.checked = true;
+  std::vector<double> ev;
+  for (int i = 0; i < dim; ++i) {
+    sym_eigenvalues(m, std::vector<double>(A.begin() + (size_t)i * m * m, A.begin() + (size_t)(i + 1) * m * m), ev);
+    for (double e : ev) r.wave_speed = std::max(r.wave_speed, std::fabs(e));
+  }
+  r.min_eig = 1e300;
+  for (int k = 0; k < nv; ++k) {
+    std::vector<double> D(m * m, 0.0);
+    for (int u = 0; u < m; ++u) D[u * m + u] = a[k];
+    for (int i = 0; i < dim; ++i)
+      for (int u = 0; u < m * m; ++u) D[u] += b[k * dim + i] * A[(size_t)i * m * m + u];
+    sym_eigenvalues(m, D, ev);
+    for (double e : ev) r.min_eig = std::min(r.min_eig, e);
+  }
+  return r;
+}
 
 // Dense cell operator for a velocity V in any direction (Sec. 3.1, eq:dg_imp
 // on a Cartesian cell with the tensor Gauss-Lobatto basis).  Per axis a with

@@ -59,6 +59,8 @@ class kds_info_t(C.Structure):
         ("proposition_ok", C.c_int32), ("line_Q", C.c_int32 * 3), ("line_bw", C.c_int32 * 3),
         ("tuned", C.c_int32), ("line_xdirect", C.c_int32), ("line_lds_bytes", C.c_int32),
         ("step_eager", C.c_int32), ("relax_vec", C.c_int32), ("line_qmax", C.c_int32),
+        ("eq_monotone", C.c_int32), ("eq_min_eig", C.c_double), ("max_wave_speed", C.c_double),
+        ("subchar_ok", C.c_int32),
     ]
 
 
