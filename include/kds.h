@@ -198,7 +198,10 @@ kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec)
 /* The complete launch plan of a problem: every choice kds_tune makes.  For
  * the line schedule (Sec. 5.1 iterations of whole grid lines, one wavefront
  * per line): per grid axis a, Q[a] cells per lane (Q[a] divides sub_cells[a],
- * n_cells[a] / Q[a] <= 64, Q[a] <= kds_info_t.line_qmax) and bw[a] columns of
+ * n_cells[a] / Q[a] <= 64; up to kds_info_t.line_qmax the lane holds its
+ * cells in registers, above it -- at most 64, not for cells of 64 nodes --
+ * it streams them through the LDS tile in rounds, which is how lines longer
+ * than 64 x line_qmax cells run) and bw[a] columns of
  * cells per workgroup; xdirect = 1 lets x lines with Q[0] = line_qmax be read
  * and written straight between HBM and registers (no LDS tile); lds_bytes =
  * LDS allocated per workgroup (0: what the tile needs; more lets fewer
@@ -293,8 +296,9 @@ typedef struct {
                              replaying a captured graph (kds_tune's choice) */
   int32_t relax_vec;      /* relaxation with 16-byte accesses, several nodes
                              per thread (kds_tune's choice) */
-  int32_t line_qmax;      /* line schedule: most cells per lane (register
-                             budget of 64 state values per lane), 0 otherwise */
+  int32_t line_qmax;      /* line schedule: most cells per lane held in
+                             registers (budget of 64 state values per lane;
+                             more are streamed in rounds), 0 otherwise */
   /* Stability warnings (the problem runs regardless):
    * eq_monotone: 1 if every equilibrium derivative dM_k/dW =
    *   a_k I + sum_i b_{k,i} A^i is positive semidefinite (linear law with

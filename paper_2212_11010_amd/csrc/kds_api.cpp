@@ -201,7 +201,10 @@ int pow2_at_least(int n) {
 bool line_choice_ok(const kds_problem* p, int ax, int Q, int bw) {
   const int Na = p->N[ax], S = p->S[ax];
   const int qmax = line_qmax((int)p->elem, p->nn);
-  if (Q < 1 || Q > qmax || S % Q || Na / Q > 64 || bw < 1) return false;
+  if (Q < 1 || S % Q || Na / Q > 64 || bw < 1) return false;
+  // more cells per lane than the registers hold: rounds through the tile
+  // (not in grouped mode, whose tile holds only part of each cell)
+  if (Q > qmax && (line_grouped(p->nn) || Q > kMaxRoundQ)) return false;
   if ((int64_t)bw * line_col_lds(Na, p->nn) * (int)p->elem > p->lds_cap) return false;
   if (ax == 0 && bw > p->ncell / Na) return false;
   // (a row of a y / z bundle is copied by one pass of the workgroup, except
@@ -211,7 +214,9 @@ bool line_choice_ok(const kds_problem* p, int ax, int Q, int bw) {
 }
 
 // Heuristic choice: many cells per lane as long as >= 3/4 of a line group's
-// lanes work; as many columns per bundle as a 32 KB LDS tile holds.
+// lanes work; as many columns per bundle as a 32 KB LDS tile holds.  Lines
+// longer than 64 lanes of register-held cells: the fewest rounds through the
+// tile that put the line in one wavefront.
 bool heuristic_choice(const kds_problem* p, int ax, int* Qo, int* bwo) {
   const int Na = p->N[ax], S = p->S[ax];
   const int qmax = line_qmax((int)p->elem, p->nn);
@@ -223,6 +228,8 @@ bool heuristic_choice(const kds_problem* p, int ax, int* Qo, int* bwo) {
     if (util >= 0.74) { bestQ = Q; break; }
     if (util > bestU + 1e-12) { bestU = util; bestQ = Q; }
   }
+  for (int Q = qmax + 1; !bestQ && Q <= std::min(S, kMaxRoundQ); ++Q)
+    if (line_choice_ok(p, ax, Q, 1)) bestQ = Q;
   if (!bestQ) return false;
   const int col = line_col_lds(Na, p->nn) * (int)p->elem;
   int bw = std::max(1, 32 * 1024 / col);
@@ -276,7 +283,8 @@ bool plan_lines(kds_problem* p, std::string& why) {
   for (int k = 0; k < p->nv; ++k) {
     const int ax = axis_of(p, k);
     if (!heuristic_choice(p, ax, &p->line_Q[ax], &p->line_bw[ax])) {
-      why = "line schedule: no cells-per-lane count divides the subdomain width with the line in one wavefront";
+      why = "line schedule: no cells-per-lane count divides the subdomain width with the line in one "
+            "wavefront (at most " + std::to_string(kMaxRoundQ) + " cells per lane)";
       return false;
     }
   }
@@ -986,8 +994,10 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   // coordinate search: one axis at a time, over (cells per lane, bundle width)
   for (int ax = 0; ax < 3 && ok && line; ++ax) {
     if (!used[ax]) continue;
-    for (int Q = 1; Q <= kMaxQ && ok; ++Q)
+    for (int Q = 1; Q <= kMaxRoundQ && ok; ++Q)
       for (int bw : bws) {
+        // (beyond kMaxQ only the counts that need rounds to fit the line)
+        if (Q > kMaxQ && p->N[ax] / std::max(1, line_qmax((int)p->elem, p->nn)) <= 64) break;
         if (!line_choice_ok(p, ax, Q, bw)) continue;
         if (Q == p->line_Q[ax] && bw == p->line_bw[ax]) continue;
         int tq[3], tb[3];
@@ -1496,8 +1506,10 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    // plain, front and Dirichlet members keep their own kernel sequences
-    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0) {
+    // plain, front and Dirichlet members, and line members whose lanes
+    // stream their cells in rounds, keep their own kernel sequences
+    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0 ||
+        line_plan_rounds(p->geom, p->plan, (int)p->elem)) {
       b->others.push_back(p);
       continue;
     }

@@ -15,7 +15,9 @@ namespace kds {
 constexpr int kMaxVel = 8;   // kinetic velocities
 constexpr int kMaxP = 4;     // nodes per axis (degree <= 3)
 constexpr int kMaxM = 8;     // conserved components
-constexpr int kMaxQ = 8;     // cells per lane in the line schedule
+constexpr int kMaxQ = 8;     // cells per lane in the line schedule, in registers
+constexpr int kMaxRoundQ = 64;  // cells per lane streamed through the LDS tile in rounds
+                                // (lines longer than 64 lanes x the register budget)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X (own L2 each)
 
 // ---------------------------------------------------------------- host setup
@@ -124,7 +126,7 @@ __host__ __device__ constexpr int line_qmax(int elem_bytes, int nn) {
 
 // Line-schedule launch plan (per velocity).
 struct LinePlan {
-  int Q[kMaxVel];          // cells per lane
+  int Q[kMaxVel];          // cells per lane (above line_qmax: rounds through the tile)
   int lpl2[kMaxVel];       // lanes per line, power of two
   int bw[kMaxVel];         // columns of cells per bundle
   int64_t block_start[kMaxVel * kMaxM + 1];  // prefix over (k, c) of bundles
@@ -134,6 +136,15 @@ struct LinePlan {
   int threads;             // block size
   int xdirect;             // x lines may bypass the LDS tile (cells per lane = QMAX)
 };
+
+// Some velocity's lanes own more cells than the registers hold (their cells
+// go through the LDS tile in rounds; a kernel instantiation of its own).
+inline bool line_plan_rounds(const Geom& g, const LinePlan& pl, int elem_bytes) {
+  const int qmax = line_qmax(elem_bytes, g.nn);
+  for (int k = 0; k < g.nv; ++k)
+    if (pl.Q[k] > qmax) return true;
+  return false;
+}
 
 // Dirichlet inflow data of the faces of non-periodic axes: kinetic values
 // M_k(W_b) at the boundary nodes, [k][c][boundary node], at the start (old)

@@ -461,6 +461,212 @@ __device__ __forceinline__ void line_group(T (&d)[QMAX][NN], const LineLane& ln,
 #undef KDS_ND
 }
 
+// Lines longer than a wavefront holds in registers (64 lanes x QMAX cells):
+// the lane owns Q > QMAX consecutive cells and streams them from the LDS tile
+// in rounds of QMAX.  The arithmetic is line_group's: pass 1 runs the
+// zero-inflow recurrence over all the lane's cells, the lane scan and the
+// subdomain iteration are the same, pass 2 recomputes each cell's beta and
+// writes the new state into the tile in place (a lane's cells are its own;
+// different line groups touch different nodes).  Cell q of the lane, in
+// downwind order, is tile row `rowof(q)`; lanes without a line (act = false)
+// read row 0 and store nothing.
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, int O0, int PER,
+          bool DIR>
+__device__ __forceinline__ void line_group_rounds(T* tile, int cbase, int j0, int Na, bool act,
+                                                  const LineLane& ln, const T (&C)[P][P],
+                                                  const T (&e1)[P], const T (&eth)[P], T gg, T G,
+                                                  int K, const T* bo, const T* bn) {
+  const int Qn = ln.Q;
+  const bool dir = DIR && bo != nullptr;
+  auto rowof = [&](int q) { return act ? (SIGN > 0 ? j0 + q : Na - 1 - j0 - q) : 0; };
+#define KDS_NDR(o, b) node_of<P, DIM, AXIS>(O0 + (o), SIGN > 0 ? (b) : P - 1 - (b))
+  T last_old[PER], t_old0[PER], mB[PER];
+  {
+    const int rl = cbase + rowof(Qn - 1) * NN;
+#pragma unroll
+    for (int o = 0; o < PER; ++o) last_old[o] = tile[rl + KDS_NDR(o, P - 1)];
+  }
+#pragma unroll
+  for (int o = 0; o < PER; ++o) {
+    t_old0[o] = __shfl(last_old[o], ln.src_prev, 64);
+    if (dir && ln.first) t_old0[o] = bo[O0 + o];
+  }
+  // pass 1: zero-inflow recurrence over all my cells, QMAX at a time
+  {
+    T to[PER], x[PER];
+#pragma unroll
+    for (int o = 0; o < PER; ++o) { to[o] = t_old0[o]; x[o] = T(0); }
+    for (int q0 = 0; q0 < Qn; q0 += QMAX) {
+      T dq[QMAX][PER][P];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int r = cbase + rowof(q0 + q < Qn ? q0 + q : 0) * NN;
+#pragma unroll
+        for (int o = 0; o < PER; ++o)
+#pragma unroll
+          for (int b = 0; b < P; ++b) dq[q][o][b] = tile[r + KDS_NDR(o, b)];
+      }
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        if (q0 + q < Qn) {
+#pragma unroll
+          for (int o = 0; o < PER; ++o) {
+            T bq = e1[P - 1] * to[o];
+#pragma unroll
+            for (int c = 0; c < P; ++c) bq += C[P - 1][c] * dq[q][o][c];
+            x[o] = gg * x[o] + bq;
+            to[o] = dq[q][o][P - 1];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < PER; ++o) mB[o] = x[o];
+  }
+  // segmented inclusive scan over the lanes of each subdomain (as line_group)
+  {
+    T gw = powi(gg, Qn);
+    if (ln.dpp_ok) {
+#define KDS_SCAN_STEP(OFF)                                   \
+  if ((OFF) < ln.Ls) {                                       \
+    _Pragma("unroll") for (int o = 0; o < PER; ++o) {        \
+      const T pB = dpp_row_shr<T, (OFF)>(mB[o]);             \
+      if (ln.sl >= (OFF)) mB[o] = gw * pB + mB[o];           \
+    }                                                        \
+    gw = gw * gw;                                            \
+  }
+      KDS_SCAN_STEP(1)
+      KDS_SCAN_STEP(2)
+      KDS_SCAN_STEP(4)
+      KDS_SCAN_STEP(8)
+#undef KDS_SCAN_STEP
+    } else {
+      for (int off = 1; off < ln.Ls; off <<= 1) {
+#pragma unroll
+        for (int o = 0; o < PER; ++o) {
+          const T pB = __shfl_up(mB[o], off, 64);
+          if (ln.sl >= off) mB[o] = gw * pB + mB[o];
+        }
+        gw = gw * gw;
+      }
+    }
+  }
+  // subdomain iteration on the outflows (as line_group)
+  T t_in[PER];
+  T bnew[PER];
+#pragma unroll
+  for (int o = 0; o < PER; ++o) bnew[o] = (dir && ln.s_me == 0) ? bn[O0 + o] : T(0);
+  if (K > 0) {
+    T Tv[PER];
+#pragma unroll
+    for (int o = 0; o < PER; ++o) Tv[o] = last_old[o];
+    for (int it = 1; it < K; ++it) {
+#pragma unroll
+      for (int o = 0; o < PER; ++o) {
+        T up = __shfl(Tv[o], ln.end_up, 64);
+        if (dir && ln.s_me == 0) up = bnew[o];
+        Tv[o] = mB[o] + G * up;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < PER; ++o) {
+      t_in[o] = __shfl(Tv[o], ln.end_up, 64);
+      if (dir && ln.s_me == 0) t_in[o] = bnew[o];
+    }
+  } else {
+#pragma unroll
+    for (int o = 0; o < PER; ++o) t_in[o] = T(0);
+    T Gq = T(1);
+    for (int q = 0; q < ln.nseg; ++q) {
+      const int s_src = ((ln.s_me - 1 - q) % ln.nseg + ln.nseg) % ln.nseg;
+      const int src = ln.lbase + (s_src + 1) * ln.Ls - 1;
+#pragma unroll
+      for (int o = 0; o < PER; ++o) {
+        const T v = __shfl(mB[o], src, 64);
+        if (!dir || q < ln.s_me) t_in[o] += Gq * v;
+      }
+      Gq *= G;
+    }
+    if (dir) {
+      const T Gs = powi(G, ln.s_me);
+#pragma unroll
+      for (int o = 0; o < PER; ++o) t_in[o] += Gs * bn[O0 + o];
+    } else {
+      const T inv = T(1) / (T(1) - Gq);
+#pragma unroll
+      for (int o = 0; o < PER; ++o) t_in[o] *= inv;
+    }
+  }
+  // pass 2: the new state, QMAX cells at a time, into the tile
+  {
+    const T g0 = powi(gg, ln.sl * Qn);
+    T x[PER], gp[PER], to[PER];
+#pragma unroll
+    for (int o = 0; o < PER; ++o) {
+      T xv = ln.dpp_ok ? dpp_row_shr<T, 1>(mB[o]) : __shfl_up(mB[o], 1, 64);
+      x[o] = ln.sl == 0 ? T(0) : xv;
+      gp[o] = g0;
+      to[o] = t_old0[o];
+    }
+    for (int q0 = 0; q0 < Qn; q0 += QMAX) {
+      T dq[QMAX][PER][P];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int r = cbase + rowof(q0 + q < Qn ? q0 + q : 0) * NN;
+#pragma unroll
+        for (int o = 0; o < PER; ++o)
+#pragma unroll
+          for (int b = 0; b < P; ++b) dq[q][o][b] = tile[r + KDS_NDR(o, b)];
+      }
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        if (q0 + q < Qn) {
+          const int r = cbase + rowof(q0 + q) * NN;
+#pragma unroll
+          for (int o = 0; o < PER; ++o) {
+            const T tn = x[o] + gp[o] * t_in[o];
+            T fn[P];
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+              T acc = e1[b] * to[o] + eth[b] * tn;
+#pragma unroll
+              for (int c = 0; c < P; ++c) acc += C[b][c] * dq[q][o][c];
+              fn[b] = acc;
+            }
+            T bq = e1[P - 1] * to[o];
+#pragma unroll
+            for (int c = 0; c < P; ++c) bq += C[P - 1][c] * dq[q][o][c];
+            if (act) {
+#pragma unroll
+              for (int b = 0; b < P; ++b) tile[r + KDS_NDR(o, b)] = fn[b];
+            }
+            x[o] = bq + gg * x[o];
+            to[o] = dq[q][o][P - 1];
+            gp[o] *= gg;
+          }
+        }
+      }
+    }
+  }
+#undef KDS_NDR
+}
+
+template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, bool DIR, int O0 = 0>
+__device__ __forceinline__ void line_lanes_rounds(T* tile, int cbase, int j0, int Na, bool act,
+                                                  const LineLane& ln, const T (&C)[P][P],
+                                                  const T (&e1)[P], const T (&eth)[P], T gg, T G,
+                                                  int K, const T* bo, const T* bn) {
+  constexpr int ALL = ColShape<P, DIM>::PER;
+  constexpr int GS = ALL <= 4 ? ALL : (ALL % 3 == 0 ? 3 : 4);
+  if constexpr (O0 < ALL) {
+    constexpr int n = ALL - O0 < GS ? ALL - O0 : GS;
+    line_group_rounds<T, P, DIM, AXIS, SIGN, QMAX, NN, O0, n, DIR>(tile, cbase, j0, Na, act, ln, C,
+                                                                   e1, eth, gg, G, K, bo, bn);
+    line_lanes_rounds<T, P, DIM, AXIS, SIGN, QMAX, NN, DIR, O0 + n>(tile, cbase, j0, Na, act, ln, C,
+                                                                    e1, eth, gg, G, K, bo, bn);
+  }
+}
+
 template <typename T, int P, int DIM, int AXIS, int SIGN, int QMAX, int NN, bool DIR, int O0 = 0>
 __device__ __forceinline__ void line_lanes(T (&d)[QMAX][NN], const LineLane& ln,
                                            const T (&C)[P][P], const T (&e1)[P], const T (&eth)[P],
@@ -643,7 +849,10 @@ __device__ __forceinline__ int64_t xcd_order(int64_t nb) {
 
 // One bundle `bid` (numbered over all (velocity, component) pairs) of one
 // problem; the body of the single-problem and the batched line kernels.
-template <typename T, int P, int DIM, bool DIR>
+// RND: some velocity's lanes own more cells than the registers hold (rounds
+// through the tile; a separate instantiation keeps the other kernels'
+// registers unchanged).
+template <typename T, int P, int DIM, bool DIR, bool RND = false>
 __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
                                             const SweepTab<T>& tab, const LinePlan& pl,
                                             const BndRef<T>& bd, int64_t bid, T* tile) {
@@ -795,6 +1004,17 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
           }
         }
         continue;
+      } else if (RND && Q > QMAX) {
+        // more cells per lane than the registers hold: rounds through the tile
+        if constexpr (RND)
+        switch (a * 2 + (sg > 0 ? 1 : 0)) {
+          case 0: line_lanes_rounds<T, P, DIM, 0, -1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 1: line_lanes_rounds<T, P, DIM, 0, 1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 2: if constexpr (DIM > 1) line_lanes_rounds<T, P, DIM, 1, -1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 3: if constexpr (DIM > 1) line_lanes_rounds<T, P, DIM, 1, 1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          case 4: if constexpr (DIM > 2) line_lanes_rounds<T, P, DIM, 2, -1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+          default: if constexpr (DIM > 2) line_lanes_rounds<T, P, DIM, 2, 1, QMAX, NN, DIR>(tile, cbase, j0, Na, act, ln, C, e1, eth, gg, G, g.K, bo, bn); break;
+        }
       } else {
         T d[QMAX][NN];
         // direct: my block starts at cell j0 (downwind = physical order) or at
@@ -864,13 +1084,13 @@ __device__ __forceinline__ void line_bundle(T* __restrict__ f, const Geom& g,
 }
 
 // DIR: some axis has Dirichlet ends (a separate instantiation keeps the
-// periodic kernel's registers unchanged)
-template <typename T, int P, int DIM, bool DIR>
+// periodic kernel's registers unchanged); RND: lanes with cells in rounds
+template <typename T, int P, int DIM, bool DIR, bool RND = false>
 __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, SweepTab<T> tab,
                                                     LinePlan pl, BndRef<T> bd) {
   extern __shared__ unsigned char smem_raw[];
-  line_bundle<T, P, DIM, DIR>(f, g, tab, pl, bd, xcd_order(pl.block_start[g.nv * g.m]),
-                         reinterpret_cast<T*>(smem_raw));
+  line_bundle<T, P, DIM, DIR, RND>(f, g, tab, pl, bd, xcd_order(pl.block_start[g.nv * g.m]),
+                                   reinterpret_cast<T*>(smem_raw));
 }
 
 // Many problems of one (precision, degree, dimension) in one launch: the
@@ -897,15 +1117,24 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
   const int64_t nblocks = plan.block_start[g.nv * g.m];
   const size_t lds = (size_t)std::max(plan.lds_elems, plan.lds_alloc) * sizeof(T);
   const int key = g.P * 10 + g.dim;
+  const bool rnd = line_plan_rounds(g, plan, (int)sizeof(T));
   switch (key) {
 #define KDS_LINE(PP, DD)                                                                        \
   case PP * 10 + DD:                                                                            \
-    if (bd.old != nullptr)                                                                      \
+    if (rnd && !line_grouped(ColShape<PP, DD>::NN)) {                                           \
+      if (bd.old != nullptr)                                                                    \
+        hipLaunchKernelGGL((k_sweep_line<T, PP, DD, true, true>), dim3((unsigned)nblocks),      \
+                           dim3(plan.threads), lds, s, (T*)f, g, t, plan, bd);                  \
+      else                                                                                      \
+        hipLaunchKernelGGL((k_sweep_line<T, PP, DD, false, true>), dim3((unsigned)nblocks),     \
+                           dim3(plan.threads), lds, s, (T*)f, g, t, plan, bd);                  \
+    } else if (bd.old != nullptr) {                                                             \
       hipLaunchKernelGGL((k_sweep_line<T, PP, DD, true>), dim3((unsigned)nblocks),              \
                          dim3(plan.threads), lds, s, (T*)f, g, t, plan, bd);                    \
-    else                                                                                        \
+    } else {                                                                                    \
       hipLaunchKernelGGL((k_sweep_line<T, PP, DD, false>), dim3((unsigned)nblocks),             \
                          dim3(plan.threads), lds, s, (T*)f, g, t, plan, bd);                    \
+    }                                                                                           \
     break;
     KDS_LINE(1, 1) KDS_LINE(2, 1) KDS_LINE(3, 1) KDS_LINE(4, 1)
     KDS_LINE(1, 2) KDS_LINE(2, 2) KDS_LINE(3, 2) KDS_LINE(4, 2)
@@ -945,9 +1174,13 @@ hipError_t line_allow_lds_t(size_t bytes) {
     if (e == hipSuccess)
       e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   };
-#define KDS_ALLOW(PP, DD)                                              \
-  set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, false>)); \
-  set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, true>));  \
+#define KDS_ALLOW(PP, DD)                                                      \
+  set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, false>));         \
+  set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, true>));          \
+  if (!line_grouped(ColShape<PP, DD>::NN)) {                                   \
+    set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, false, true>)); \
+    set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, true, true>));  \
+  }                                                                            \
   set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD>));
   KDS_ALLOW(1, 1) KDS_ALLOW(2, 1) KDS_ALLOW(3, 1) KDS_ALLOW(4, 1)
   KDS_ALLOW(1, 2) KDS_ALLOW(2, 2) KDS_ALLOW(3, 2) KDS_ALLOW(4, 2)

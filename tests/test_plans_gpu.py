@@ -87,7 +87,7 @@ def run(spec, W0, B, prec, plan):
 def families(spec, prec):
     """The plans to force: per used axis, Q in {1, 2, Q_max} x bw in {1, the
     largest accepted}; Q_max on every axis with the direct x path on and off;
-    a larger LDS allocation."""
+    a larger LDS allocation; 2 Q_max cells per lane (rounds) per axis."""
     import torch  # noqa: F401
     from paper_2212_11010_amd import kds
     with kds.Problem(spec, precision=prec, schedule="line") as pb:
@@ -117,6 +117,14 @@ def families(spec, prec):
     p = copy.deepcopy(base)
     p["lds_bytes"] = max(tile, 1) + 16 * 1024
     out.append(("lds +16K", p))
+    # more cells per lane than the registers hold (rounds through the tile),
+    # where 2 Q_max divides the subdomain (refused for 64-node cells)
+    for a in used:
+        if S[a] % (2 * qmax) == 0:
+            p = copy.deepcopy(base)
+            p["Q"][a] = 2 * qmax
+            p["xdirect"] = 0
+            out.append(("axis%d Q%d rounds" % (a, 2 * qmax), p))
     return out, used, qmax
 
 
@@ -163,7 +171,7 @@ def test_set_plan_rejects_invalid_choices():
         base = pb.get_plan()
         qmax = pb.info()["line_qmax"]
         for bad in (dict(Q=[3, base["Q"][1], 0]),        # 3 does not divide the 8-cell subdomain
-                    dict(Q=[qmax * 2, base["Q"][1], 0]),  # beyond the register budget
+                    dict(Q=[16, base["Q"][1], 0]),        # more cells than the subdomain has
                     dict(bw=[0, base["bw"][1], 0]),
                     dict(xdirect=2), dict(step_eager=-1), dict(lds_bytes=-4),
                     dict(lds_bytes=1 << 30)):
@@ -179,6 +187,27 @@ def test_set_plan_rejects_invalid_choices():
         p["xdirect"] = 1
         with pytest.raises(kds.KdsError):
             pb.set_plan(p)
+        # more cells per lane than the registers hold is a valid plan (rounds
+        # through the tile) where it divides the subdomain, but not with xdirect
+        p = copy.deepcopy(base)
+        p["Q"][0] = 2 * qmax
+        p["xdirect"] = 0
+        pb.set_plan(p)
+        assert pb.get_plan()["Q"][0] == 2 * qmax
+        p["xdirect"] = 1
+        with pytest.raises(kds.KdsError):
+            pb.set_plan(p)
+    # cells of 64 nodes (grouped mode) keep their cells in registers only
+    spec, W0, _, _, _ = case("euler_p3_grouped")
+    with kds.Problem(spec, precision="fp32", schedule="line") as pb:
+        p = pb.get_plan()
+        qmax = pb.info()["line_qmax"]
+        a = [i for i in range(3) if p["Q"][i] > 0][0]
+        if spec["sub_cells"][a] % (2 * qmax) == 0:
+            p["Q"][a] = 2 * qmax
+            with pytest.raises(kds.KdsError) as e:
+                pb.set_plan(p)
+            assert e.value.status == kds.KDS_E_INVALID
 
 
 def test_tuned_plan_restored_reproduces_bitwise():
