@@ -1445,6 +1445,7 @@ const char* kds_last_error(const kds_problem* p) {
 struct kds_batch {
   struct Branch {
     int prec = 0, P = 0, dim = 0, threads = 0, law = 0, m = 0, nv = 0;
+    bool rounds = false;  // members whose lanes stream their cells in rounds
     size_t lds_elems = 0;
     std::vector<unsigned char> line_tasks, relax_tasks;  // packed records (host)
     std::vector<int64_t> line_start{0}, relax_start{0};  // block prefixes
@@ -1506,18 +1507,17 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    // plain, front and Dirichlet members, and line members whose lanes
-    // stream their cells in rounds, keep their own kernel sequences
-    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0 ||
-        line_plan_rounds(p->geom, p->plan, (int)p->elem)) {
+    // plain, front and Dirichlet members keep their own kernel sequences
+    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0) {
       b->others.push_back(p);
       continue;
     }
     const Geom& g = p->geom;
+    const bool rounds = line_plan_rounds(g, p->plan, (int)p->elem);
     kds_batch::Branch* br = nullptr;
     for (auto& x : b->branches)
       if (x.prec == p->prec && x.P == p->P && x.dim == p->dim && x.threads == p->plan.threads &&
-          x.law == p->law && x.m == p->m && x.nv == p->nv)
+          x.law == p->law && x.m == p->m && x.nv == p->nv && x.rounds == rounds)
         br = &x;
     if (!br) {
       b->branches.emplace_back();
@@ -1529,6 +1529,7 @@ kds_status batch_build(kds_batch* b) {
       br->law = p->law;
       br->m = p->m;
       br->nv = p->nv;
+      br->rounds = rounds;
     }
     const size_t lb = line_task_bytes(p->prec);
     const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
@@ -1579,8 +1580,8 @@ kds_status batch_build(kds_batch* b) {
 }
 
 hipError_t launch_branch_line(const kds_batch::Branch& br, hipStream_t s) {
-  return launch_sweep_line_batch(br.prec, br.P, br.dim, br.d_line, br.d_line_start, br.ntask(),
-                                 br.line_start.back(), br.threads, br.lds_elems, s);
+  return launch_sweep_line_batch(br.prec, br.P, br.dim, br.rounds, br.d_line, br.d_line_start,
+                                 br.ntask(), br.line_start.back(), br.threads, br.lds_elems, s);
 }
 
 hipError_t launch_branch_relax(const kds_batch::Branch& br, hipStream_t s) {

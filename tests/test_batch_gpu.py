@@ -191,3 +191,41 @@ def test_batch_with_degree3_members():
              np.ascontiguousarray(F.transpose(0, 2, 3, 1)), TOL["fp32"], label="degree-3 member")
     for pb in members + singles:
         pb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_with_long_line_members(prec):
+    """Members whose lines need rounds through the tile (512 cells along x at
+    p = 2) beside ordinary members of the same degree and dimension: the
+    batch puts them in a branch of their own, and every member still equals
+    the same problem stepped alone, bit for bit."""
+    import torch
+    from paper_2212_11010_amd import kds, workloads as wl
+    shapes = [([512, 4], [64, 4]), ([32, 24], [8, 6]), ([4, 512], [4, 128]), ([48, 16], [16, 8])]
+    specs = []
+    for i, (n, s) in enumerate(shapes):
+        spec, W0 = wl.make_workload(2, n_cells=n, sub_cells=s, steps=3, seed=100 + i)
+        specs.append((spec, W0))
+
+    def build():
+        out = []
+        for spec, W0 in specs:
+            pb = kds.Problem(spec, precision=prec)
+            pb.set_state(torch.from_numpy(W0).cuda())
+            out.append(pb)
+        return out
+
+    members, singles = build(), build()
+    qmax = members[0].info()["line_qmax"]
+    rounds = [max(pb.get_plan()["Q"]) > qmax for pb in members]
+    assert rounds == [True, False, True, False], rounds
+    with kds.Batch(members) as b:
+        b.step(3)
+        b.synchronize()
+    for pb in singles:
+        pb.step(3)
+    for i, (pm, ps) in enumerate(zip(members, singles)):
+        assert pm.info()["schedule"] == kds.KDS_SCHED_LINE
+        assert np.array_equal(pm.get_kinetic(), ps.get_kinetic()), i
+    for pb in members + singles:
+        pb.close()
