@@ -180,8 +180,9 @@ kds_status kds_step_timed(kds_problem* p, int32_t n_steps, double* kernel_ms);
  * then fewer workgroups per CU (larger LDS allocation), then the step launch
  * mode of kds_step (graph replay or enqueued kernels) and the access width of
  * the relaxation (periodic problems only; whole steps timed); restores the
- * state.  Needs a state.  For the plain and front schedules only the last two
- * choices are tuned (*sweep_ms = -1).  sweep_ms (nullable): best average
+ * state.  Needs a state.  For the front schedule the front kernel (where both
+ * apply) and the last two choices are tuned, for the plain schedule only the
+ * last two (*sweep_ms = -1).  sweep_ms (nullable): best average
  * sweep time.  Needs one state's worth of free device memory (else
  * KDS_E_NOMEM). */
 kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms);
@@ -237,6 +238,38 @@ kds_status kds_get_plan(const kds_problem* p, kds_plan_t* plan);
  * not apply to the problem; Q and bw entries of an axis without velocities
  * are ignored. */
 kds_status kds_set_plan(kds_problem* p, const kds_plan_t* plan);
+
+/* Autotuner of the subdomain width (sub_cells), which -- unlike the launch
+ * plan -- changes the answer (the Jacobi iteration of Sec. 5.1 couples the
+ * subdomains through lagged interface traces), so it is a separate call whose
+ * result the caller adopts: for each axis carrying a velocity component, the
+ * widths S that divide n_cells and satisfy the Proposition of Sec. 5.1
+ * (max_k |V_k^a| dt <= S h_a) are tried one axis at a time, the others kept
+ * at their best so far, starting from cfg->sub_cells (which must be valid).
+ * Each candidate is a temporary problem built from cfg with that width,
+ * started from W (FP64 host [cell][node][c]), tuned (kds_tune, reps) and timed
+ * over reps steps.  Out: sub_cells[3] the fastest widths, step_ms (nullable)
+ * its time per step.  Candidates that cannot be built or run (e.g. a width no
+ * schedule accepts, not enough memory) are skipped.  Periodic boxes only
+ * (KDS_E_UNSUPPORTED otherwise: the steps of a Dirichlet problem need its
+ * boundary data).  Errors: KDS_E_INVALID for NULL arguments, and those of
+ * kds_create / kds_set_state / kds_step for cfg itself. */
+kds_status kds_tune_subdomains(const kds_config* cfg, const double* W, int32_t reps,
+                               int32_t* sub_cells, double* step_ms);
+
+/* kds_tune through a plan cache: a text file of (key, plan) lines, so that
+ * later runs and other processes on the same kind of device take the plan
+ * that was tuned once instead of timing again -- their FP32 results then do
+ * not depend on timing noise.  The key holds everything a plan depends on:
+ * schedule, precision, degree, dimension, m, n_vel, n_cells, sub_cells, the
+ * axis and sign of every velocity, the Dirichlet axes and the device's
+ * architecture name.  If `path` holds the key its plan is applied
+ * (kds_set_plan) and *hit = 1; otherwise kds_tune runs, its plan is appended
+ * to the file and *hit = 0 (hit nullable).  A missing or unreadable file
+ * counts as empty.  Errors: those of kds_tune and kds_set_plan (a cached plan
+ * that no longer applies is re-tuned and appended), KDS_E_INVALID for a NULL
+ * path or a file that cannot be written (the tuned plan stays in place). */
+kds_status kds_tune_cached(kds_problem* p, int32_t reps, const char* path, int32_t* hit);
 
 /* Average duration of one launch of each kernel kind (sweep: the line kernel,
  * or one plain subdomain iteration; relax), from HIP events around reps

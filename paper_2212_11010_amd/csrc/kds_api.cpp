@@ -1245,6 +1245,192 @@ kds_status kds_set_plan(kds_problem* p, const kds_plan_t* pl) {
   return KDS_OK;
 }
 
+namespace {
+
+// The plan cache key of a problem (one line of text, no '|').
+std::string plan_key(const kds_problem* p) {
+  std::string k;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "sched=%d prec=%d P=%d dim=%d m=%d nv=%d N=%dx%dx%d S=%dx%dx%d",
+                p->sched, p->prec, p->P, p->dim, p->m, p->nv, p->N[0], p->N[1], p->N[2], p->S[0],
+                p->S[1], p->S[2]);
+  k += buf;
+  k += " vel=";
+  for (int i = 0; i < p->nv; ++i) {
+    for (int a = 0; a < p->dim; ++a) {
+      const double v = p->vel[i * p->dim + a];
+      k += v > 0 ? '+' : (v < 0 ? '-' : '0');
+    }
+    k += i + 1 < p->nv ? "," : "";
+  }
+  std::snprintf(buf, sizeof(buf), " dirichlet=%d%d%d", p->boff[0][0] >= 0, p->boff[1][0] >= 0,
+                p->boff[2][0] >= 0);
+  k += buf;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    k += " arch=";
+    for (const char* c = prop.gcnArchName; *c && *c != ':'; ++c) k += *c;
+  } else {
+    (void)hipGetLastError();
+    k += " arch=?";
+  }
+  return k;
+}
+
+constexpr int kPlanInts = 12;  // kds_plan_t as integers, in field order
+
+void plan_to_ints(const kds_plan_t& pl, int32_t* v) {
+  for (int a = 0; a < 3; ++a) { v[a] = pl.Q[a]; v[3 + a] = pl.bw[a]; }
+  v[6] = pl.xdirect;
+  v[7] = pl.lds_bytes;
+  v[8] = pl.step_eager;
+  v[9] = pl.relax_vec;
+  v[10] = pl.front_kernel;
+  v[11] = 0;
+}
+void plan_from_ints(const int32_t* v, kds_plan_t& pl) {
+  for (int a = 0; a < 3; ++a) { pl.Q[a] = v[a]; pl.bw[a] = v[3 + a]; }
+  pl.xdirect = v[6];
+  pl.lds_bytes = v[7];
+  pl.step_eager = v[8];
+  pl.relax_vec = v[9];
+  pl.front_kernel = v[10];
+}
+
+}  // namespace
+
+kds_status kds_tune_subdomains(const kds_config* cfg, const double* W, int32_t reps,
+                               int32_t* sub_cells, double* step_ms) {
+  if (!cfg || !W || !sub_cells) return fail(nullptr, KDS_E_INVALID, "NULL argument");
+  for (int a = 0; a < std::max(1, std::min(3, cfg->dim)); ++a)
+    if (!cfg->periodic[a])
+      return fail(nullptr, KDS_E_UNSUPPORTED,
+                  "kds_tune_subdomains: periodic boxes only (the steps of a Dirichlet problem "
+                  "need its boundary data)");
+  reps = std::max(1, std::min(reps, 100));
+  // one candidate: build, start from W, tune, time reps steps (ms per step,
+  // or a negative value if the candidate cannot run)
+  auto time_width = [&](const int32_t* S, double* ms) -> kds_status {
+    kds_config c = *cfg;
+    for (int a = 0; a < 3; ++a) c.sub_cells[a] = S[a];
+    kds_problem* p = nullptr;
+    kds_status st = kds_create(&c, nullptr, &p);
+    *ms = -1.0;
+    if (st != KDS_OK) return st;
+    st = kds_set_state(p, W, 0);
+    if (st == KDS_OK) {
+      const kds_status tst = kds_tune(p, reps, nullptr);
+      if (tst != KDS_OK && tst != KDS_E_NOMEM && tst != KDS_E_STATE) st = tst;
+    }
+    if (st == KDS_OK) st = kds_step(p, 1);  // warm-up (captures the step graphs)
+    if (st == KDS_OK) st = kds_synchronize(p);
+    if (st == KDS_OK) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      hipError_t he = hipEventCreate(&e0);
+      if (he == hipSuccess) he = hipEventCreate(&e1);
+      if (he == hipSuccess) he = hipEventRecord(e0, p->stream);
+      if (he == hipSuccess && (st = kds_step(p, reps)) == KDS_OK) {
+        he = hipEventRecord(e1, p->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&f, e0, e1);
+        if (he == hipSuccess) *ms = f / reps;
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (he != hipSuccess) {
+        (void)hipGetLastError();
+        st = KDS_E_DEVICE;
+      }
+    }
+    kds_destroy(p);
+    return st;
+  };
+  int32_t best[3] = {cfg->sub_cells[0], cfg->sub_cells[1], cfg->sub_cells[2]};
+  double best_ms = 0.0;
+  {
+    const kds_status st = time_width(best, &best_ms);
+    if (st != KDS_OK) return st;  // cfg itself must run
+  }
+  const int dim = std::max(1, std::min(3, cfg->dim));
+  for (int a = 0; a < dim; ++a) {
+    // the Proposition: max_k |V_k^a| dt <= S h_a
+    double vmax = 0.0;
+    for (int k = 0; k < cfg->n_vel; ++k) vmax = std::max(vmax, std::fabs(cfg->vel[k * cfg->dim + a]));
+    if (vmax == 0.0) continue;
+    const double h = (cfg->box_hi[a] - cfg->box_lo[a]) / cfg->n_cells[a];
+    const double nu = vmax * cfg->dt / h;
+    for (int S = 1; S <= cfg->n_cells[a]; ++S) {
+      if (cfg->n_cells[a] % S || S == best[a] || S < nu * (1.0 - 1e-12)) continue;
+      int32_t cand[3] = {best[0], best[1], best[2]};
+      cand[a] = S;
+      double ms = -1.0;
+      if (time_width(cand, &ms) != KDS_OK || ms < 0.0) continue;
+      if (ms < 0.97 * best_ms) {
+        best_ms = ms;
+        best[a] = S;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) sub_cells[a] = best[a];
+  if (step_ms) *step_ms = best_ms;
+  return KDS_OK;
+}
+
+kds_status kds_tune_cached(kds_problem* p, int32_t reps, const char* path, int32_t* hit) {
+  if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
+  if (!path) return fail(p, KDS_E_INVALID, "kds_tune_cached: path is NULL");
+  if (hit) *hit = 0;
+  const std::string key = plan_key(p);
+  // the last line with this key wins (a re-tuned plan is appended)
+  bool found = false;
+  kds_plan_t cached;
+  std::memset(&cached, 0, sizeof(cached));
+  if (FILE* fp = std::fopen(path, "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof(line), fp)) {
+      char* bar = std::strchr(line, '|');
+      if (!bar) continue;
+      std::string k(line, bar - line);
+      while (!k.empty() && k.back() == ' ') k.pop_back();
+      if (k != key) continue;
+      int32_t v[kPlanInts];
+      int n = 0;
+      char* q = bar + 1;
+      while (n < kPlanInts) {
+        char* end = nullptr;
+        const long x = std::strtol(q, &end, 10);
+        if (end == q) break;
+        v[n++] = (int32_t)x;
+        q = end;
+      }
+      if (n == kPlanInts) {
+        plan_from_ints(v, cached);
+        found = true;
+      }
+    }
+    std::fclose(fp);
+  }
+  if (found && kds_set_plan(p, &cached) == KDS_OK) {
+    if (hit) *hit = 1;
+    return KDS_OK;
+  }
+  kds_status st = kds_tune(p, reps, nullptr);
+  if (st != KDS_OK) return st;
+  kds_plan_t pl;
+  kds_get_plan(p, &pl);
+  int32_t v[kPlanInts];
+  plan_to_ints(pl, v);
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return fail(p, KDS_E_INVALID, std::string("kds_tune_cached: cannot write ") + path);
+  std::fprintf(fp, "%s |", key.c_str());
+  for (int i = 0; i < kPlanInts; ++i) std::fprintf(fp, " %d", v[i]);
+  std::fprintf(fp, "\n");
+  const bool ok = std::fclose(fp) == 0;
+  if (!ok) return fail(p, KDS_E_INVALID, std::string("kds_tune_cached: cannot write ") + path);
+  return KDS_OK;
+}
+
 kds_status kds_time_kernels(kds_problem* p, int32_t reps, double* kernel_ms) {
   if (!p) return fail(nullptr, KDS_E_INVALID, "problem is NULL");
   if (!kernel_ms || reps < 1) return fail(p, KDS_E_INVALID, "bad arguments");

@@ -27,7 +27,8 @@ SCHEDULES = {"auto": KDS_SCHED_AUTO, "plain": KDS_SCHED_PLAIN, "line": KDS_SCHED
              "front": KDS_SCHED_FRONT}
 N_KERNEL_KINDS = 2
 EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_step_timed",
-            "kds_tune", "kds_set_launch", "kds_get_plan", "kds_set_plan",
+            "kds_tune", "kds_tune_cached", "kds_tune_subdomains", "kds_set_launch",
+            "kds_get_plan", "kds_set_plan",
             "kds_time_kernels", "kds_moments", "kds_moments_static",
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
@@ -95,6 +96,8 @@ def lib():
         L.kds_step.argtypes = [vp, C.c_int32]
         L.kds_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_tune.argtypes = [vp, C.c_int32, dp]
+        L.kds_tune_cached.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]
+        L.kds_tune_subdomains.argtypes = [C.POINTER(kds_config), dp, C.c_int32, C.POINTER(C.c_int32), dp]
         L.kds_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
         L.kds_get_plan.argtypes = [vp, C.POINTER(kds_plan_t)]
         L.kds_set_plan.argtypes = [vp, C.POINTER(kds_plan_t)]
@@ -213,6 +216,18 @@ def kds_create(spec, precision="fp32", schedule="auto", stream=None):
     return h
 
 
+def kds_tune_subdomains(spec, W, precision="fp32", schedule="auto", reps=3):
+    """kds_tune_subdomains: (sub_cells [3], ms per step) for the problem
+    `spec` started from W (FP64 host [cell][node][c])."""
+    cfg, keep = make_config(spec, precision, schedule)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    out = (C.c_int32 * 3)()
+    ms = C.c_double(0.0)
+    _check(lib().kds_tune_subdomains(C.byref(cfg), W.ctypes.data_as(C.POINTER(C.c_double)),
+                                     int(reps), out, C.byref(ms)))
+    return list(out), ms.value
+
+
 def kds_set_state(h, W, nbytes):
     ptr, dev = _buf(W, nbytes)
     _check(lib().kds_set_state(h, ptr, dev), h)
@@ -237,6 +252,13 @@ def kds_tune(h, reps=3):
     best = C.c_double(0.0)
     _check(lib().kds_tune(h, int(reps), C.byref(best)), h)
     return best.value
+
+
+def kds_tune_cached(h, path, reps=3):
+    """kds_tune through the plan cache file `path`; True if the plan came from it."""
+    hit = C.c_int32(0)
+    _check(lib().kds_tune_cached(h, int(reps), os.fsencode(path), C.byref(hit)), h)
+    return bool(hit.value)
 
 
 def kds_set_launch(h, step_eager, relax_vec):
@@ -422,6 +444,9 @@ class Problem:
 
     def tune(self, reps=3):
         return kds_tune(self.h, reps)
+
+    def tune_cached(self, path, reps=3):
+        return kds_tune_cached(self.h, path, reps)
 
     def time_kernels(self, reps=10):
         return kds_time_kernels(self.h, reps)
