@@ -229,3 +229,63 @@ def test_fullsize_two_steps_both_legs(name):
             print("  %s %s step %d: rel err %.3e, per plane %.3e" % (prec, sched, s + 1, e_glob,
                                                                       e_plane), flush=True)
             assert e_glob <= TOL[prec] and e_plane <= TOL[prec], (prec, sched, s, e_glob, e_plane)
+
+
+def test_batch_recipe_members_two_steps():
+    """The many-problem workload's recipe at its own sizes (acoustics 64^2 ..
+    512^2 p = 1..3, Euler 32^3 .. 96^3 p = 1..2, subdomain widths drawn with
+    nu <= S), fourteen members (1.1e9 unknowns, among them 512^2 lines and a
+    96^3 Euler member) advanced TOGETHER by the batch step with the
+    tuned plans bench.py times, each compared with the FP64 oracle at two
+    sampled cells (a subdomain corner and a seeded cell) after one and after
+    two steps, at the FP32 tolerance."""
+    import torch
+    from paper_2212_11010_amd import kds, workloads as wl
+    specs = wl.make_batch_workload(n_problems=14, max_unknowns=1.2e9, seed=wl.SEED_BASE + 7)
+    rng = np.random.default_rng(11)
+    members, states, picks = [], [], []
+    try:
+        for s in specs:
+            W0 = wl.batch_member_state(s)
+            pb = kds.Problem(s, precision="fp32")
+            pb.set_state(torch.from_numpy(W0).cuda())
+            pb.tune(3)
+            assert pb.info()["schedule"] == kds.KDS_SCHED_LINE
+            d, N, S = s["dim"], s["n_cells"][0], s["sub_cells"][0]
+            # (S may equal N: the corner's other coordinates stay on the grid)
+            cells = [[S - 1] + [min(S, N - 1)] * (d - 1),
+                     [int(v) for v in rng.integers(0, N, size=d)]]
+            ncell = N ** d
+            assert all(0 <= cell_id(cc, N) < ncell for cc in cells), (s["name"], cells)
+            print("  member %s N %d S %d p %d plan Q %s" % (s["name"], N, S, s["degree"],
+                                                            pb.get_plan()["Q"][:s["n_vel"]]),
+                  flush=True)
+            members.append(pb)
+            states.append(W0)
+            picks.append(cells)
+        got = [[] for _ in members]
+        with kds.Batch(members) as b:
+            for _ in range(2):
+                b.step(1)
+                b.synchronize()
+                for i, (pb, s) in enumerate(zip(members, specs)):
+                    host_ids = [cell_id(cc, s["n_cells"][0]) for cc in picks[i]]
+                    assert max(host_ids) < pb.f_shape[1]     # checked before any device index
+                    ids = torch.tensor(host_ids, device="cuda")
+                    Fd = torch.empty(pb.f_shape, dtype=torch.float64, device="cuda")
+                    pb.get_kinetic(Fd)
+                    got[i].append((Fd[:, ids].cpu().numpy(), Fd.abs().amax(dim=(1, 2)).cpu().numpy()))
+                    del Fd
+        for i, s in enumerate(specs):
+            orc = TwoStepOracle(s, states[i])
+            refs = [orc.at(cc) for cc in picks[i]]
+            for st in range(2):
+                ref = np.stack([r[st] for r in refs])
+                e_glob, e_plane = errs(got[i][st], ref)
+                print("  %s step %d: rel err %.3e, per plane %.3e" % (s["name"], st + 1, e_glob,
+                                                                       e_plane), flush=True)
+                assert e_glob <= TOL["fp32"] and e_plane <= TOL["fp32"], (s["name"], st, e_glob,
+                                                                         e_plane)
+    finally:
+        for pb in members:
+            pb.close()
