@@ -996,8 +996,11 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
     if (!used[ax]) continue;
     for (int Q = 1; Q <= kMaxRoundQ && ok; ++Q)
       for (int bw : bws) {
-        // (beyond kMaxQ only the counts that need rounds to fit the line)
-        if (Q > kMaxQ && p->N[ax] / std::max(1, line_qmax((int)p->elem, p->nn)) <= 64) break;
+        // (counts beyond the register budget, whose cells stream through the
+        // tile in rounds, only where the line does not fit the registers:
+        // elsewhere they cost 2-5x the register plans)
+        const int qmax = std::max(1, line_qmax((int)p->elem, p->nn));
+        if (Q > qmax && p->N[ax] / qmax <= 64) break;
         if (!line_choice_ok(p, ax, Q, bw)) continue;
         if (Q == p->line_Q[ax] && bw == p->line_bw[ax]) continue;
         int tq[3], tb[3];
