@@ -1625,16 +1625,19 @@ const char* kds_last_error(const kds_problem* p) {
 
 // ================================================================ batches
 // Many problems advanced together.  The line-schedule members that share
-// (precision, degree, dimension, workgroup size, law, m, n_vel) form a branch:
-// ONE launch sweeps all of them (workgroups spread over the members), ONE
-// launch relaxes them.  Branches touch disjoint memory and run as parallel
-// branches of one captured HIP graph per step; the plain- and front-schedule
-// members add their own kernel sequences on one more branch.
+// (precision, degree, dimension, workgroup size, law, m, n_vel, periodic or
+// Dirichlet) form a branch: ONE launch sweeps all of them (workgroups spread
+// over the members), ONE launch relaxes them.  Branches touch disjoint memory
+// and run as parallel branches of one captured HIP graph per step; the
+// plain- and front-schedule members add their own kernel sequences on one
+// more branch.  (A Dirichlet member's records point at its two boundary
+// halves, which kds_set_boundary refills in place between steps.)
 
 struct kds_batch {
   struct Branch {
     int prec = 0, P = 0, dim = 0, threads = 0, law = 0, m = 0, nv = 0;
     bool rounds = false;  // members whose lanes stream their cells in rounds
+    bool dir = false;     // members with Dirichlet axes
     size_t lds_elems = 0;
     std::vector<unsigned char> line_tasks, relax_tasks;  // packed records (host)
     std::vector<int64_t> line_start{0}, relax_start{0};  // block prefixes
@@ -1696,17 +1699,18 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    // plain, front and Dirichlet members keep their own kernel sequences
-    if (p->sched != KDS_SCHED_LINE || p->nbnd > 0) {
+    // plain- and front-schedule members keep their own kernel sequences
+    if (p->sched != KDS_SCHED_LINE) {
       b->others.push_back(p);
       continue;
     }
     const Geom& g = p->geom;
     const bool rounds = line_plan_rounds(g, p->plan, (int)p->elem);
+    const bool dir = p->nbnd > 0;
     kds_batch::Branch* br = nullptr;
     for (auto& x : b->branches)
       if (x.prec == p->prec && x.P == p->P && x.dim == p->dim && x.threads == p->plan.threads &&
-          x.law == p->law && x.m == p->m && x.nv == p->nv && x.rounds == rounds)
+          x.law == p->law && x.m == p->m && x.nv == p->nv && x.rounds == rounds && x.dir == dir)
         br = &x;
     if (!br) {
       b->branches.emplace_back();
@@ -1719,6 +1723,7 @@ kds_status batch_build(kds_batch* b) {
       br->m = p->m;
       br->nv = p->nv;
       br->rounds = rounds;
+      br->dir = dir;
     }
     const size_t lb = line_task_bytes(p->prec);
     const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
@@ -1769,8 +1774,9 @@ kds_status batch_build(kds_batch* b) {
 }
 
 hipError_t launch_branch_line(const kds_batch::Branch& br, hipStream_t s) {
-  return launch_sweep_line_batch(br.prec, br.P, br.dim, br.rounds, br.d_line, br.d_line_start,
-                                 br.ntask(), br.line_start.back(), br.threads, br.lds_elems, s);
+  return launch_sweep_line_batch(br.prec, br.P, br.dim, br.rounds, br.dir, br.d_line,
+                                 br.d_line_start, br.ntask(), br.line_start.back(), br.threads,
+                                 br.lds_elems, s);
 }
 
 hipError_t launch_branch_relax(const kds_batch::Branch& br, hipStream_t s) {

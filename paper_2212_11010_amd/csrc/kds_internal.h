@@ -280,10 +280,12 @@ hipError_t sweep_line_f32(const Geom& g, const void* tab, const LinePlan& plan, 
                           const BndArgs& bnd, hipStream_t s);
 hipError_t sweep_line_f64(const Geom& g, const void* tab, const LinePlan& plan, void* f,
                           const BndArgs& bnd, hipStream_t s);
-hipError_t sweep_line_batch_f32(int P, int dim, bool rounds, const void* tasks, const int64_t* start, int ntask,
-                                int64_t nblocks, int threads, size_t lds_elems, hipStream_t s);
-hipError_t sweep_line_batch_f64(int P, int dim, bool rounds, const void* tasks, const int64_t* start, int ntask,
-                                int64_t nblocks, int threads, size_t lds_elems, hipStream_t s);
+hipError_t sweep_line_batch_f32(int P, int dim, bool rounds, bool dir, const void* tasks,
+                                const int64_t* start, int ntask, int64_t nblocks, int threads,
+                                size_t lds_elems, hipStream_t s);
+hipError_t sweep_line_batch_f64(int P, int dim, bool rounds, bool dir, const void* tasks,
+                                const int64_t* start, int ntask, int64_t nblocks, int threads,
+                                size_t lds_elems, hipStream_t s);
 hipError_t line_allow_lds_f32(size_t bytes);
 hipError_t line_allow_lds_f64(size_t bytes);
 size_t line_task_bytes_f32();
@@ -295,10 +297,11 @@ void pack_line_task_f64(void* f, const Geom& g, const void* tab, const LinePlan&
 size_t line_task_bytes(int prec);
 void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const LinePlan& pl,
                     const BndArgs& bnd, void* out);
-// rounds: some member's lanes stream their cells through the tile in rounds
-hipError_t launch_sweep_line_batch(int prec, int P, int dim, bool rounds, const void* tasks,
-                                   const int64_t* start, int ntask, int64_t nblocks, int threads,
-                                   size_t lds_elems, hipStream_t s);
+// rounds: some member's lanes stream their cells through the tile in rounds;
+// dir: the members have Dirichlet axes
+hipError_t launch_sweep_line_batch(int prec, int P, int dim, bool rounds, bool dir,
+                                   const void* tasks, const int64_t* start, int ntask,
+                                   int64_t nblocks, int threads, size_t lds_elems, hipStream_t s);
 
 // Equilibrium tables are built into a byte blob matching EqTab<D, M, NV> for
 // the (law, dim, m, nv) combination; returns false if the combination has no

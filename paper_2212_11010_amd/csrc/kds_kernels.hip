@@ -715,12 +715,13 @@ void pack_line_task(int prec, void* f, const Geom& g, const void* tab, const Lin
     pack_line_task_f32(f, g, tab, pl, bnd, out);
 }
 
-hipError_t launch_sweep_line_batch(int prec, int P, int dim, bool rounds, const void* tasks,
-                                   const int64_t* start, int ntask, int64_t nblocks, int threads,
-                                   size_t lds_elems, hipStream_t s) {
-  return prec == KDS_FP64
-             ? sweep_line_batch_f64(P, dim, rounds, tasks, start, ntask, nblocks, threads, lds_elems, s)
-             : sweep_line_batch_f32(P, dim, rounds, tasks, start, ntask, nblocks, threads, lds_elems, s);
+hipError_t launch_sweep_line_batch(int prec, int P, int dim, bool rounds, bool dir,
+                                   const void* tasks, const int64_t* start, int ntask,
+                                   int64_t nblocks, int threads, size_t lds_elems, hipStream_t s) {
+  return prec == KDS_FP64 ? sweep_line_batch_f64(P, dim, rounds, dir, tasks, start, ntask,
+                                                 nblocks, threads, lds_elems, s)
+                          : sweep_line_batch_f32(P, dim, rounds, dir, tasks, start, ntask,
+                                                 nblocks, threads, lds_elems, s);
 }
 
 // Allow the line kernels (single and batched) dynamic LDS up to `bytes`

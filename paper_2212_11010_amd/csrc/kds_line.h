@@ -1095,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_sweep_line(T* __restrict__ f, Geom g, S
 
 // Many problems of one (precision, degree, dimension) in one launch: the
 // bundles of all problems are numbered consecutively (start[] prefix).
-template <typename T, int P, int DIM, bool RND = false>
+template <typename T, int P, int DIM, bool RND = false, bool DIR = false>
 __global__ __launch_bounds__(256) void k_sweep_line_batch(const LineTask<T>* __restrict__ tasks,
                                                           const int64_t* __restrict__ start,
                                                           int ntask) {
@@ -1104,9 +1104,9 @@ __global__ __launch_bounds__(256) void k_sweep_line_batch(const LineTask<T>* __r
   int pid = 0;
   while (gbid >= start[pid + 1]) ++pid;
   const LineTask<T>& t = tasks[pid];
-  // (batches hold periodic line-schedule members only)
-  line_bundle<T, P, DIM, false, RND>(t.f, t.g, t.tab, t.pl, t.bd, gbid - start[pid],
-                                     reinterpret_cast<T*>(smem_raw));
+  // (DIR: members with Dirichlet axes, whose boundary data the records point to)
+  line_bundle<T, P, DIM, DIR, RND>(t.f, t.g, t.tab, t.pl, t.bd, gbid - start[pid],
+                                   reinterpret_cast<T*>(smem_raw));
 }
 
 template <typename T>
@@ -1148,19 +1148,28 @@ hipError_t sweep_line_t(const Geom& g, const void* tab, const LinePlan& plan, vo
 
 
 template <typename T>
-hipError_t sweep_line_batch_t(int P, int dim, bool rounds, const void* tasks, const int64_t* start,
-                              int ntask, int64_t nblocks, int threads, size_t lds_elems,
-                              hipStream_t s) {
+hipError_t sweep_line_batch_t(int P, int dim, bool rounds, bool dir, const void* tasks,
+                              const int64_t* start, int ntask, int64_t nblocks, int threads,
+                              size_t lds_elems, hipStream_t s) {
   const size_t lds = lds_elems * sizeof(T);
+  const LineTask<T>* tk = (const LineTask<T>*)tasks;
   switch (P * 10 + dim) {
 #define KDS_LB(PP, DD)                                                                          \
   case PP * 10 + DD:                                                                            \
-    if (rounds && !line_grouped(ColShape<PP, DD>::NN))                                          \
-      hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD, true>), dim3((unsigned)nblocks),        \
-                         dim3(threads), lds, s, (const LineTask<T>*)tasks, start, ntask);       \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD>), dim3((unsigned)nblocks), dim3(threads), \
-                         lds, s, (const LineTask<T>*)tasks, start, ntask);                     \
+    if (rounds && !line_grouped(ColShape<PP, DD>::NN)) {                                        \
+      if (dir)                                                                                  \
+        hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD, true, true>), dim3((unsigned)nblocks),  \
+                           dim3(threads), lds, s, tk, start, ntask);                            \
+      else                                                                                      \
+        hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD, true>), dim3((unsigned)nblocks),      \
+                           dim3(threads), lds, s, tk, start, ntask);                            \
+    } else if (dir) {                                                                           \
+      hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD, false, true>), dim3((unsigned)nblocks), \
+                         dim3(threads), lds, s, tk, start, ntask);                              \
+    } else {                                                                                    \
+      hipLaunchKernelGGL((k_sweep_line_batch<T, PP, DD>), dim3((unsigned)nblocks),              \
+                         dim3(threads), lds, s, tk, start, ntask);                              \
+    }                                                                                           \
     break;
     KDS_LB(1, 1) KDS_LB(2, 1) KDS_LB(3, 1) KDS_LB(4, 1)
     KDS_LB(1, 2) KDS_LB(2, 2) KDS_LB(3, 2) KDS_LB(4, 2)
@@ -1186,8 +1195,10 @@ hipError_t line_allow_lds_t(size_t bytes) {
     set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, false, true>)); \
     set(reinterpret_cast<const void*>(&k_sweep_line<T, PP, DD, true, true>));  \
     set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD, true>));  \
-  }                                                                            \
-  set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD>));
+    set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD, true, true>));   \
+  }                                                                                  \
+  set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD>));                \
+  set(reinterpret_cast<const void*>(&k_sweep_line_batch<T, PP, DD, false, true>));
   KDS_ALLOW(1, 1) KDS_ALLOW(2, 1) KDS_ALLOW(3, 1) KDS_ALLOW(4, 1)
   KDS_ALLOW(1, 2) KDS_ALLOW(2, 2) KDS_ALLOW(3, 2) KDS_ALLOW(4, 2)
   KDS_ALLOW(1, 3) KDS_ALLOW(2, 3) KDS_ALLOW(3, 3) KDS_ALLOW(4, 3)
@@ -1214,10 +1225,10 @@ void pack_line_task_t(void* f, const Geom& g, const void* tab, const LinePlan& p
                               const BndArgs& bnd, hipStream_t s) {                             \
     return sweep_line_t<T>(g, tab, plan, f, bnd, s);                                           \
   }                                                                                            \
-  hipError_t sweep_line_batch_##SFX(int P, int dim, bool rounds, const void* tasks,            \
+  hipError_t sweep_line_batch_##SFX(int P, int dim, bool rounds, bool dir, const void* tasks,  \
                                     const int64_t* start, int ntask, int64_t nblocks,          \
                                     int threads, size_t lds_elems, hipStream_t s) {            \
-    return sweep_line_batch_t<T>(P, dim, rounds, tasks, start, ntask, nblocks, threads,        \
+    return sweep_line_batch_t<T>(P, dim, rounds, dir, tasks, start, ntask, nblocks, threads,   \
                                  lds_elems, s);                                                \
   }                                                                                            \
   hipError_t line_allow_lds_##SFX(size_t bytes) { return line_allow_lds_t<T>(bytes); }         \

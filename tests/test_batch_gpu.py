@@ -132,31 +132,49 @@ def test_batch_member_without_state_rejected():
 
 
 def test_batch_with_dirichlet_member():
-    """A member with Dirichlet axes keeps its own kernel sequence inside the
-    batch (its boundary data held constant over the batched steps) and ends
-    bitwise equal to the same problem stepped on its own."""
+    """Members with Dirichlet axes (along x, and along y with a second velocity
+    set) join the grouped line launch of their kind; with boundary data that
+    change between the batched steps they end bitwise equal to the same
+    problems stepped on their own with the same data."""
     import torch
     from paper_2212_11010_amd import kds
     from paper_2212_11010_amd import workloads as wl
     specs = small_batch(seed=13, n=3)
-    dspec, dW0 = wl.make_workload(2, n_cells=[24, 16], sub_cells=[8, 8], periodic=[0, 1], steps=3)
-    Wb = wl.boundary_state(dspec, dW0)
+    dspecs = [wl.make_workload(2, n_cells=[24, 16], sub_cells=[8, 8], periodic=[0, 1], steps=3),
+              wl.make_workload(2, n_cells=[16, 32], sub_cells=[8, 16], periodic=[1, 0], steps=3),
+              wl.make_workload(3, n_cells=[8, 6, 4], sub_cells=[4, 6, 4], periodic=[1, 1, 0],
+                               steps=3)]
+    rng = np.random.default_rng(3)
+    data = []
+    for dspec, dW0 in dspecs:
+        Wb = wl.boundary_state(dspec, dW0)
+        data.append([Wb * (1.0 + 0.01 * rng.standard_normal((Wb.shape[0], 1))) for _ in range(4)])
     members = make_members(specs, "fp32", ["auto"] * len(specs))
     singles = make_members(specs, "fp32", ["auto"] * len(specs))
-    dm = kds.Problem(dspec, precision="fp32")
-    ds = kds.Problem(dspec, precision="fp32")
-    for pb in (dm, ds):
-        pb.set_state(torch.from_numpy(dW0).cuda())
-        pb.set_boundary(Wb)
-    with kds.Batch(members + [dm]) as b:
-        b.step(3)
+    dm, ds = [], []
+    for (dspec, dW0), B in zip(dspecs, data):
+        for lst in (dm, ds):
+            pb = kds.Problem(dspec, precision="fp32")
+            pb.set_state(torch.from_numpy(dW0).cuda())
+            pb.set_boundary(B[0])
+            assert pb.info()["schedule"] == kds.KDS_SCHED_LINE
+            lst.append(pb)
+    with kds.Batch(members + dm) as b:
+        for s in range(3):
+            for pb, B in zip(dm, data):
+                pb.set_boundary(B[s + 1])
+            b.step(1)
         b.synchronize()
-    for pb in singles + [ds]:
+    for pb in singles:
         pb.step(3)
-    for pm, ps in zip(members + [dm], singles + [ds]):
+    for s in range(3):
+        for pb, B in zip(ds, data):
+            pb.set_boundary(B[s + 1])
+            pb.step(1)
+    for pm, ps in zip(members + dm, singles + ds):
         assert pm.info()["steps_done"] == 3
         assert np.array_equal(pm.get_kinetic(), ps.get_kinetic())
-    for pb in members + singles + [dm, ds]:
+    for pb in members + singles + dm + ds:
         pb.close()
 
 
