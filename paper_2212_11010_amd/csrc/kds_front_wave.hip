@@ -286,17 +286,31 @@ __device__ __forceinline__ void front_wave_task(
       isfr[a] = valid && sg[a] != 0 && ((pk >> (10 * a)) & 1023) > 0;
     }
     // ---- the GEMM input: cell slots, then face slots (frontier, or the
-    // theta-combined traces loaded with the cell values)
+    // theta-combined traces loaded with the cell values).  Every lane reads
+    // its frontier slots (in range for any record) and both candidates are
+    // formed before the selects: the reads go out together, and no lane
+    // branches on its face kind.
     float bx[KS];
 #pragma unroll
     for (int e = 0; e < CS; ++e) bx[e] = pc[e];
+    float frv[DIM * FS], trv[DIM * FS];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int j = 0; j < FS; ++j) frv[a * FS + j] = FR[frb[a] + fst + j];
+#pragma unroll
+    for (int s = 0; s < DIM * FS; ++s) {
+      trv[s] = th1 * pvo[s] + th * pvn[s];
+      // (keeps each candidate a computed value, so the select below stays a
+      // select rather than becoming a branch around a load)
+      __asm__ volatile("" ::"v"(frv[s]), "v"(trv[s]));
+    }
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
       for (int j = 0; j < FS; ++j) {
         const int s = a * FS + j;
-        const float fr = FR[frb[a] + fst + j];
-        bx[CS + s] = isfr[a] ? fr : th1 * pvo[s] + th * pvn[s];
+        bx[CS + s] = isfr[a] ? frv[s] : trv[s];
       }
 #pragma unroll
     for (int e = CS + DIM * FS; e < KS; ++e) bx[e] = 0.0f;
@@ -390,13 +404,17 @@ __device__ __forceinline__ void front_wave_task(
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) TB[16 * t + 4 * lk + v] = th * acc[t][v] + th1 * xo[t][v];
+    // (all trace reads before the frontier writes: one LDS round trip)
+    float zv[DIM * FS];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
-      for (int j = 0; j < FS; ++j) {
-        const float z = TB[nbn4[a][j] >> 2];
-        FR[(valid && sg[a] != 0) ? frb[a] + fst + j : frn] = z;
-      }
+      for (int j = 0; j < FS; ++j) zv[a * FS + j] = TB[nbn4[a][j] >> 2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int j = 0; j < FS; ++j)
+        FR[(valid && sg[a] != 0) ? frb[a] + fst + j : frn] = zv[a * FS + j];
 
     cb = ncb;
     ce = nce;
