@@ -1638,6 +1638,7 @@ struct kds_batch {
     int prec = 0, P = 0, dim = 0, threads = 0, law = 0, m = 0, nv = 0;
     bool rounds = false;  // members whose lanes stream their cells in rounds
     bool dir = false;     // members with Dirichlet axes
+    std::vector<kds_problem*> members;
     size_t lds_elems = 0;
     std::vector<unsigned char> line_tasks, relax_tasks;  // packed records (host)
     std::vector<int64_t> line_start{0}, relax_start{0};  // block prefixes
@@ -1728,6 +1729,7 @@ kds_status batch_build(kds_batch* b) {
     const size_t lb = line_task_bytes(p->prec);
     const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
     if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
+    br->members.push_back(p);
     size_t off = br->line_tasks.size();
     br->line_tasks.resize(off + lb);
     pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, p->bnd(),
@@ -1797,8 +1799,16 @@ kds_status batch_enqueue(kds_batch* b) {
     for (size_t i = 1; i < nstreams; ++i) KDS_BHIP(b, hipStreamWaitEvent(bs[i], b->ev_fork, 0));
   }
   for (size_t i = 0; i < nb; ++i) {
-    KDS_BHIP(b, launch_branch_line(b->branches[i], bs[i]));
-    KDS_BHIP(b, launch_branch_relax(b->branches[i], bs[i]));
+    const kds_batch::Branch& br = b->branches[i];
+    KDS_BHIP(b, launch_branch_line(br, bs[i]));
+    KDS_BHIP(b, launch_branch_relax(br, bs[i]));
+    // the boundary data at the end of the step are the start data of the
+    // next, as in a member's own step
+    if (br.dir)
+      for (kds_problem* p : br.members) {
+        const BndArgs bd = p->bnd();
+        KDS_BHIP(b, launch_copy(p->prec, bd.neu, p->fb, p->bnd_half(), bs[i]));
+      }
   }
   if (!b->others.empty()) {
     hipStream_t s = bs[nstreams - 1];

@@ -132,10 +132,11 @@ def test_batch_member_without_state_rejected():
 
 
 def test_batch_with_dirichlet_member():
-    """Members with Dirichlet axes (along x, and along y with a second velocity
-    set) join the grouped line launch of their kind; with boundary data that
-    change between the batched steps they end bitwise equal to the same
-    problems stepped on their own with the same data."""
+    """Members with Dirichlet axes (2-D along x and along y, 3-D along z) join
+    the grouped line launch of their kind; with boundary data that change
+    between the batched steps, and over two batched steps in one call, they
+    end bitwise equal to the same problems stepped on their own with the same
+    data."""
     import torch
     from paper_2212_11010_amd import kds
     from paper_2212_11010_amd import workloads as wl
@@ -164,15 +165,25 @@ def test_batch_with_dirichlet_member():
             for pb, B in zip(dm, data):
                 pb.set_boundary(B[s + 1])
             b.step(1)
+        # two batched steps in one call: the second starts from the data at
+        # the end of the first
+        for pb, B in zip(dm, data):
+            pb.set_boundary(B[0])
+            pb.set_boundary(B[2])
+        b.step(2)
         b.synchronize()
     for pb in singles:
-        pb.step(3)
+        pb.step(5)
     for s in range(3):
         for pb, B in zip(ds, data):
             pb.set_boundary(B[s + 1])
             pb.step(1)
+    for pb, B in zip(ds, data):
+        pb.set_boundary(B[0])
+        pb.set_boundary(B[2])
+        pb.step(2)
     for pm, ps in zip(members + dm, singles + ds):
-        assert pm.info()["steps_done"] == 3
+        assert pm.info()["steps_done"] == 5
         assert np.array_equal(pm.get_kinetic(), ps.get_kinetic())
     for pb in members + singles + dm + ds:
         pb.close()
