@@ -1160,7 +1160,8 @@ kds_status kds_tune(kds_problem* p, int32_t reps, double* sweep_ms) {
   }
   drop_graphs(p);
   p->tuned = line;
-  if (line) ++p->plan_version;
+  // (a batch regroups its members when a line plan or a front kernel changed)
+  if (line || p->front_wave != wave0) ++p->plan_version;
   if (sweep_ms) *sweep_ms = (line || best > 0.0f) ? best : -1.0;
   return KDS_OK;
 }
@@ -1234,6 +1235,7 @@ kds_status kds_set_plan(kds_problem* p, const kds_plan_t* pl) {
     ++p->plan_version;
   }
   if (p->sched == KDS_SCHED_FRONT && pl->front_kernel != 0) {
+    const bool wave_before = p->front_wave;
     if (pl->front_kernel == 2 && front_wave_ok(p)) p->front_wave = true;
     else if (pl->front_kernel == 1 && front_wg_ok(p)) p->front_wave = false;
     else
@@ -1241,6 +1243,7 @@ kds_status kds_set_plan(kds_problem* p, const kds_plan_t* pl) {
                   std::string("kds_set_plan: front_kernel ") + std::to_string(pl->front_kernel) +
                       " does not apply (1: workgroup kernel" + (front_wg_ok(p) ? "" : ", not here") +
                       "; 2: wave kernel" + (front_wave_ok(p) ? "" : ", not here") + ")");
+    if (p->front_wave != wave_before) ++p->plan_version;
   }
   p->eager_steps = pl->step_eager == 1;
   p->relax_vec = pl->relax_vec == 1;
@@ -1648,9 +1651,27 @@ struct kds_batch {
     int64_t* d_relax_start = nullptr;
     int ntask() const { return (int)line_start.size() - 1; }
   };
+  // front-schedule members on the wave kernel that share (form, dimension,
+  // degree, subdomain iterations, law, m, n_vel): one launch per iteration,
+  // one relaxation launch
+  struct FrontBranch {
+    int mode = 0, dim = 0, P = 0, K = 0, law = 0, m = 0, nv = 0;
+    Geom g{};             // the first member's (the kernel shape)
+    size_t lds = 0;       // largest LDS of the members
+    std::vector<kds_problem*> members;
+    std::vector<std::vector<unsigned char>> it_tasks;  // per iteration 1..K (host)
+    std::vector<unsigned char> relax_tasks;
+    std::vector<int64_t> start{0}, relax_start{0};
+    std::vector<void*> d_it;
+    void* d_relax = nullptr;
+    int64_t* d_start = nullptr;
+    int64_t* d_relax_start = nullptr;
+    int ntask() const { return (int)start.size() - 1; }
+  };
   std::vector<kds_problem*> probs;
   std::vector<int> versions;
   std::vector<Branch> branches;
+  std::vector<FrontBranch> fronts;
   std::vector<kds_problem*> others;  // members on the extra branch
   int device = 0;
   hipStream_t stream = nullptr;      // the batch's stream (branch 0 when captured)
@@ -1686,7 +1707,15 @@ void batch_free_branches(kds_batch* b) {
     for (void* x : bufs)
       if (x) (void)hipFree(x);
   }
+  for (auto& fb : b->fronts) {
+    for (void* x : fb.d_it)
+      if (x) (void)hipFree(x);
+    void* bufs[] = {fb.d_relax, fb.d_start, fb.d_relax_start};
+    for (void* x : bufs)
+      if (x) (void)hipFree(x);
+  }
   b->branches.clear();
+  b->fronts.clear();
   b->others.clear();
 }
 
@@ -1700,7 +1729,49 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    // plain- and front-schedule members keep their own kernel sequences
+    if (p->sched == KDS_SCHED_FRONT && p->front_wave && front_wave_ok(p)) {
+      // front members on the wave kernel: grouped by their kernel and step
+      const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
+      if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
+      kds_batch::FrontBranch* fb = nullptr;
+      for (auto& x : b->fronts)
+        if (x.mode == p->front_mode && x.dim == p->dim && x.P == p->P && x.K == p->K &&
+            x.law == p->law && x.m == p->m && x.nv == p->nv)
+          fb = &x;
+      if (!fb) {
+        b->fronts.emplace_back();
+        fb = &b->fronts.back();
+        fb->mode = p->front_mode;
+        fb->dim = p->dim;
+        fb->P = p->P;
+        fb->K = p->K;
+        fb->law = p->law;
+        fb->m = p->m;
+        fb->nv = p->nv;
+        fb->g = p->geom;
+        fb->it_tasks.resize(p->K);
+      }
+      fb->members.push_back(p);
+      const size_t tb = front_wave_task_bytes();
+      for (int it = 1; it <= p->K; ++it) {
+        const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
+        auto& t = fb->it_tasks[it - 1];
+        const size_t off = t.size();
+        t.resize(off + tb);
+        pack_front_wave_task(p->geom, p->front, p->front_W, p->front_lvl_start, p->front_desc,
+                             p->front_ndesc, p->f, f_prev, p->fit[it & 1], p->bnd(), t.data() + off);
+      }
+      fb->start.push_back(fb->start.back() + front_wave_blocks(p->geom, p->front));
+      fb->lds = std::max(fb->lds, front_wave_lds_bytes(p->geom, p->front));
+      const size_t off = fb->relax_tasks.size();
+      fb->relax_tasks.resize(off + rb);
+      pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->fit[p->K & 1], p->f,
+                      p->plane(), fb->relax_tasks.data() + off);
+      fb->relax_start.push_back(fb->relax_start.back() + (p->plane() + 255) / 256);
+      continue;
+    }
+    // plain-schedule members, and front members on the workgroup kernel,
+    // keep their own kernel sequences
     if (p->sched != KDS_SCHED_LINE) {
       b->others.push_back(p);
       continue;
@@ -1761,8 +1832,26 @@ kds_status batch_build(kds_batch* b) {
                    std::string("batch task tables: ") + hipGetErrorString(e));
     }
   }
+  for (auto& fb : b->fronts) {
+    if (fb.start.back() > 0x7fffffffLL || fb.relax_start.back() > 0x7fffffffLL)
+      return bfail(b, KDS_E_UNSUPPORTED, "batched launch exceeds the grid limit");
+    hipError_t e = hipSuccess;
+    fb.d_it.assign(fb.K, nullptr);
+    for (int it = 0; it < fb.K && e == hipSuccess; ++it)
+      e = upload(&fb.d_it[it], fb.it_tasks[it].data(), fb.it_tasks[it].size());
+    if (e == hipSuccess) e = upload((void**)&fb.d_start, fb.start.data(), fb.start.size() * 8);
+    if (e == hipSuccess) e = upload(&fb.d_relax, fb.relax_tasks.data(), fb.relax_tasks.size());
+    if (e == hipSuccess)
+      e = upload((void**)&fb.d_relax_start, fb.relax_start.data(), fb.relax_start.size() * 8);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, e == hipErrorOutOfMemory ? KDS_E_NOMEM : KDS_E_DEVICE,
+                   std::string("batch task tables: ") + hipGetErrorString(e));
+    }
+  }
   // capture streams for the branches beyond the first
-  const size_t nside = b->branches.size() - (b->branches.empty() ? 0 : 1) + (b->others.empty() ? 0 : 1);
+  const size_t ngrouped = b->branches.size() + b->fronts.size();
+  const size_t nside = ngrouped - (ngrouped ? 1 : 0) + (b->others.empty() ? 0 : 1);
   while (b->sides.size() < nside) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
@@ -1781,6 +1870,16 @@ hipError_t launch_branch_line(const kds_batch::Branch& br, hipStream_t s) {
                                  br.lds_elems, s);
 }
 
+hipError_t launch_front_branch_iter(const kds_batch::FrontBranch& fb, int it, hipStream_t s) {
+  return launch_sweep_front_wave_batch(fb.mode, fb.g, fb.d_it[it], fb.d_start, fb.ntask(),
+                                       fb.start.back(), fb.lds, s);
+}
+
+hipError_t launch_front_branch_relax(const kds_batch::FrontBranch& fb, hipStream_t s) {
+  return launch_relax_batch(KDS_FP32, fb.law, fb.dim, fb.m, fb.nv, fb.d_relax, fb.d_relax_start,
+                            fb.ntask(), fb.relax_start.back(), s);
+}
+
 hipError_t launch_branch_relax(const kds_batch::Branch& br, hipStream_t s) {
   return launch_relax_batch(br.prec, br.law, br.dim, br.m, br.nv, br.d_relax, br.d_relax_start,
                             br.ntask(), br.relax_start.back(), s);
@@ -1789,11 +1888,11 @@ hipError_t launch_branch_relax(const kds_batch::Branch& br, hipStream_t s) {
 // One batched step, under stream capture: fork every side stream from the
 // batch stream, enqueue each branch on its stream, join them back.
 kds_status batch_enqueue(kds_batch* b) {
-  const size_t nb = b->branches.size();
+  const size_t nb = b->branches.size(), nf = b->fronts.size();
   std::vector<hipStream_t> bs;
   bs.push_back(b->stream);
   for (hipStream_t s : b->sides) bs.push_back(s);
-  const size_t nstreams = (nb ? nb : 1) + (b->others.empty() ? 0 : 1);
+  const size_t nstreams = (nb + nf ? nb + nf : 1) + (b->others.empty() ? 0 : 1);
   if (nstreams > 1) {
     KDS_BHIP(b, hipEventRecord(b->ev_fork, b->stream));
     for (size_t i = 1; i < nstreams; ++i) KDS_BHIP(b, hipStreamWaitEvent(bs[i], b->ev_fork, 0));
@@ -1808,6 +1907,18 @@ kds_status batch_enqueue(kds_batch* b) {
       for (kds_problem* p : br.members) {
         const BndArgs bd = p->bnd();
         KDS_BHIP(b, launch_copy(p->prec, bd.neu, p->fb, p->bnd_half(), bs[i]));
+      }
+  }
+  for (size_t j = 0; j < nf; ++j) {
+    const kds_batch::FrontBranch& fb = b->fronts[j];
+    hipStream_t s = bs[nb + j];
+    for (int it = 0; it < fb.K; ++it)
+      KDS_BHIP(b, launch_front_branch_iter(fb, it, s));
+    KDS_BHIP(b, launch_front_branch_relax(fb, s));
+    for (kds_problem* p : fb.members)
+      if (p->nbnd > 0) {
+        const BndArgs bd = p->bnd();
+        KDS_BHIP(b, launch_copy(p->prec, bd.neu, p->fb, p->bnd_half(), s));
       }
   }
   if (!b->others.empty()) {
@@ -1830,7 +1941,7 @@ kds_status batch_prepare(kds_batch* b) {
     if (p->nbnd > 0 && !p->bnd_set)
       return bfail(b, KDS_E_STATE, "a batch member has Dirichlet axes but no boundary data");
   }
-  bool stale = b->branches.empty() && b->others.empty();
+  bool stale = b->branches.empty() && b->fronts.empty() && b->others.empty();
   for (size_t i = 0; i < b->probs.size(); ++i)
     if (b->versions[i] != b->probs[i]->plan_version) stale = true;
   if (stale) {
@@ -1948,10 +2059,12 @@ kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms)
   kds_status st = batch_prepare(b);
   if (st != KDS_OK) return st;
   if ((st = batch_join_in(b)) != KDS_OK) return st;
-  // the grouped kernels update the line-schedule members in place: save them
+  // the grouped kernels update their members' states in place: save them
+  std::vector<kds_problem*> grouped;
+  for (auto& br : b->branches) grouped.insert(grouped.end(), br.members.begin(), br.members.end());
+  for (auto& fb : b->fronts) grouped.insert(grouped.end(), fb.members.begin(), fb.members.end());
   size_t total = 0;
-  for (kds_problem* p : b->probs)
-    if (p->sched == KDS_SCHED_LINE) total += (size_t)p->n_unknowns() * p->elem;
+  for (kds_problem* p : grouped) total += (size_t)p->n_unknowns() * p->elem;
   unsigned char* save = nullptr;
   if (total && hipMalloc((void**)&save, total) != hipSuccess) {
     (void)hipGetLastError();
@@ -1959,18 +2072,28 @@ kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms)
   }
   hipError_t e = hipSuccess;
   size_t off = 0;
-  for (kds_problem* p : b->probs)
-    if (p->sched == KDS_SCHED_LINE && e == hipSuccess) {
+  for (kds_problem* p : grouped)
+    if (e == hipSuccess) {
       const size_t n = (size_t)p->n_unknowns() * p->elem;
       e = hipMemcpyAsync(save + off, p->f, n, hipMemcpyDeviceToDevice, b->stream);
       off += n;
     }
   float ms[2] = {0, 0};
+  const size_t nb = b->branches.size(), ng = nb + b->fronts.size();
   for (int kind = 0; kind < 2 && e == hipSuccess; ++kind)
-    for (auto& br : b->branches) {
+    for (size_t i = 0; i < ng; ++i) {
       if (e != hipSuccess) break;
+      // (a front group: all its subdomain iterations per repetition)
       auto launch = [&]() -> hipError_t {
-        return kind == 0 ? launch_branch_line(br, b->stream) : launch_branch_relax(br, b->stream);
+        if (i < nb)
+          return kind == 0 ? launch_branch_line(b->branches[i], b->stream)
+                           : launch_branch_relax(b->branches[i], b->stream);
+        const kds_batch::FrontBranch& fb = b->fronts[i - nb];
+        if (kind == 1) return launch_front_branch_relax(fb, b->stream);
+        hipError_t r = hipSuccess;
+        for (int it = 0; it < fb.K && r == hipSuccess; ++it)
+          r = launch_front_branch_iter(fb, it, b->stream);
+        return r;
       };
       e = launch();  // warm-up
       if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
@@ -1983,8 +2106,8 @@ kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms)
     }
   off = 0;
   hipError_t e2 = hipSuccess;
-  for (kds_problem* p : b->probs)
-    if (p->sched == KDS_SCHED_LINE && e2 == hipSuccess) {
+  for (kds_problem* p : grouped)
+    if (e2 == hipSuccess) {
       const size_t n = (size_t)p->n_unknowns() * p->elem;
       e2 = hipMemcpyAsync(p->f, save + off, n, hipMemcpyDeviceToDevice, b->stream);
       off += n;

@@ -113,6 +113,20 @@ struct WaveShape {
   static constexpr int XOS = 16 * MT + 1;       // cell values of a tile, per column
 };
 
+// One problem of a batched launch (one subdomain iteration).
+struct FrontWaveTask {
+  const float* f_old;
+  const float* f_prev;
+  float* f_cur;
+  Geom g;
+  FrontParams fp;
+  const float* Wop;
+  const int* lvl_start;
+  const int4* desc;
+  int n_desc;
+  BndRef<float> bd;
+};
+
 template <int MODE, int KS0>
 struct WaveK {
   // slots per lane: the 16x16x16 products take four per step
@@ -435,17 +449,17 @@ constexpr int wave_occupancy() {
   return (WaveShape<DIM, P>::NN > 16 && MODE != kFrontMfma) ? 3 : 4;
 }
 
+// One task (velocity, subdomain, component) of one problem: the body of the
+// single-problem and the batched kernels.
 template <int MODE, int DIM, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
-void k_sweep_front_wave(
+__device__ __forceinline__ void front_wave_block(
     const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
-    Geom g, FrontParams fp, const float* __restrict__ Wop, const int* __restrict__ lvl_start,
-    const int4* __restrict__ desc, int n_desc, BndRef<float> bd) {
-  extern __shared__ float wave_lds[];
+    const Geom& g, const FrontParams& fp, const float* __restrict__ Wop,
+    const int* __restrict__ lvl_start, const int4* __restrict__ desc, int n_desc,
+    const BndRef<float>& bd, int task, float* wave_lds) {
   using S = WaveShape<DIM, P>;
   const int m = g.m, nn = S::NN;
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
-  const int task = blockIdx.x;
   const int c = task % m;
   const int sd = (task / m) % nsd;
   const int k = task / (m * nsd);
@@ -499,6 +513,33 @@ void k_sweep_front_wave(
     front_wave_task<MODE, DIM, P, false>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel,
                                          isb, boff, sdb, rfo, rfp, rfc, rfo, rfp, FR, XO);
   }
+}
+
+template <int MODE, int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
+void k_sweep_front_wave(
+    const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
+    Geom g, FrontParams fp, const float* __restrict__ Wop, const int* __restrict__ lvl_start,
+    const int4* __restrict__ desc, int n_desc, BndRef<float> bd) {
+  extern __shared__ float wave_lds[];
+  front_wave_block<MODE, DIM, P>(f_old, f_prev, f_cur, g, fp, Wop, lvl_start, desc, n_desc, bd,
+                                 (int)blockIdx.x, wave_lds);
+}
+
+// Many problems of one (form, dimension, degree) in one launch, one
+// subdomain iteration each: the tasks of all problems are numbered
+// consecutively (start[] prefix over the problems).
+template <int MODE, int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
+void k_sweep_front_wave_batch(const FrontWaveTask* __restrict__ tasks,
+                              const int64_t* __restrict__ start, int ntask) {
+  extern __shared__ float wave_lds[];
+  const int64_t gb = blockIdx.x;
+  int pid = 0;
+  while (pid + 1 < ntask && gb >= start[pid + 1]) ++pid;
+  const FrontWaveTask& t = tasks[pid];
+  front_wave_block<MODE, DIM, P>(t.f_old, t.f_prev, t.f_cur, t.g, t.fp, t.Wop, t.lvl_start,
+                                 t.desc, t.n_desc, t.bd, (int)(gb - start[pid]), wave_lds);
 }
 
 // the (dim, nodes per axis) shapes the kernel is built for: 0..4, or -1
@@ -577,6 +618,66 @@ hipError_t launch_sweep_front_wave(int mode, const Geom& g, const FrontParams& f
   }
 #undef KDS_WAVE
 #undef KDS_WAVE_LAUNCH
+  return hipGetLastError();
+}
+
+size_t front_wave_task_bytes() { return sizeof(FrontWaveTask); }
+
+void pack_front_wave_task(const Geom& g, const FrontParams& fp, const void* Wop,
+                          const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
+                          const void* f_prev, void* f_cur, const BndArgs& bnd, void* out) {
+  FrontWaveTask t;
+  t.f_old = (const float*)f_old;
+  t.f_prev = (const float*)f_prev;
+  t.f_cur = (float*)f_cur;
+  t.g = g;
+  t.fp = fp;
+  t.Wop = (const float*)Wop;
+  t.lvl_start = lvl_start;
+  t.desc = desc;
+  t.n_desc = n_desc;
+  t.bd = bnd_ref<float>(bnd);
+  std::memcpy(out, &t, sizeof(t));
+}
+
+int64_t front_wave_blocks(const Geom& g, const FrontParams& fp) {
+  return (int64_t)fp.nsub[0] * fp.nsub[1] * fp.nsub[2] * g.nv * g.m;
+}
+
+hipError_t launch_sweep_front_wave_batch(int mode, const Geom& g, const void* tasks,
+                                         const int64_t* start, int ntask, int64_t nblocks,
+                                         size_t lds_bytes, hipStream_t s) {
+  const int shape = front_wave_shape(g);
+  if (shape < 0 || ntask <= 0 || nblocks <= 0 || nblocks > 0x7fffffffLL || lds_bytes > 64 * 1024)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblocks), block(64);
+  const FrontWaveTask* tk = (const FrontWaveTask*)tasks;
+#define KDS_WAVEB_LAUNCH(MODE, DIM, P)                                                            \
+  hipLaunchKernelGGL((k_sweep_front_wave_batch<MODE, DIM, P>), grid, block, lds_bytes, s, tk, start, \
+                     ntask)
+#define KDS_WAVEB(MODE)                             \
+  switch (shape) {                                  \
+    case 0: KDS_WAVEB_LAUNCH(MODE, 3, 2); break;    \
+    case 1: KDS_WAVEB_LAUNCH(MODE, 3, 3); break;    \
+    case 2: KDS_WAVEB_LAUNCH(MODE, 2, 2); break;    \
+    case 3: KDS_WAVEB_LAUNCH(MODE, 2, 3); break;    \
+    default: KDS_WAVEB_LAUNCH(MODE, 2, 4); break;   \
+  }
+  switch (mode) {
+    case kFrontMfma:
+      KDS_WAVEB(kFrontMfma)
+      break;
+    case kFrontSplitF16:
+      KDS_WAVEB(kFrontSplitF16)
+      break;
+    case kFrontSplitBf16:
+      KDS_WAVEB(kFrontSplitBf16)
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef KDS_WAVEB
+#undef KDS_WAVEB_LAUNCH
   return hipGetLastError();
 }
 

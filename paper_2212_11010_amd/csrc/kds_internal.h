@@ -265,6 +265,18 @@ hipError_t launch_sweep_front_wave(int mode, const Geom& g, const FrontParams& f
                                    const int* lvl_start, const int4* desc, int n_desc,
                                    const void* f_old, const void* f_prev, void* f_cur,
                                    const BndArgs& bnd, hipStream_t s);
+// The same for many problems of one (form, dimension, degree) and one
+// subdomain iteration each: a task record per problem (the arguments above),
+// start[] the prefix over the problems of front_wave_blocks, lds_bytes the
+// largest front_wave_lds_bytes of the problems.
+size_t front_wave_task_bytes();
+void pack_front_wave_task(const Geom& g, const FrontParams& fp, const void* Wop,
+                          const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
+                          const void* f_prev, void* f_cur, const BndArgs& bnd, void* out);
+int64_t front_wave_blocks(const Geom& g, const FrontParams& fp);
+hipError_t launch_sweep_front_wave_batch(int mode, const Geom& g, const void* tasks,
+                                         const int64_t* start, int ntask, int64_t nblocks,
+                                         size_t lds_bytes, hipStream_t s);
 
 // Batched launches (many problems per kernel): task records are packed on the
 // host, copied to device memory, and the kernels find their problem from the

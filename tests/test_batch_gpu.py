@@ -115,6 +115,54 @@ def test_batch_with_front_member_and_retune():
         pb.close()
 
 
+def test_batch_front_members_grouped():
+    """Front-schedule members on the wave kernel share one launch per
+    subdomain iteration and one relaxation launch (two D3Q4 members of
+    different sizes, one with Dirichlet faces and data changing between the
+    steps); a member forced to the workgroup kernel keeps its own sequence.
+    All end bitwise equal to the same problems stepped on their own."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    cases = [dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=3),
+             dict(n_cells=[12, 8, 4], sub_cells=[4, 4, 4], steps=3),
+             dict(n_cells=[8, 8, 8], sub_cells=[4, 4, 4], steps=3, periodic=[0, 1, 1]),
+             dict(n_cells=[8, 4, 4], sub_cells=[4, 4, 4], steps=3)]
+    kernels = [2, 2, 2, 1]        # wave, wave, wave (Dirichlet), workgroup
+    specs = [wl.make_workload(6, **c) for c in cases]
+    bm, bs = [], []
+    for (spec, W0), kern in zip(specs, kernels):
+        for lst in (bm, bs):
+            pb = kds.Problem(spec, precision="fp32", schedule="front")
+            pb.set_state(torch.from_numpy(W0).cuda())
+            plan = pb.get_plan()
+            plan["front_kernel"] = kern
+            pb.set_plan(plan)
+            assert pb.get_plan()["front_kernel"] == kern
+            lst.append(pb)
+    dspec = specs[2][0]
+    data = [wl.boundary_state(dspec, t=0.1 * s) for s in range(4)]
+    for lst in (bm, bs):
+        lst[2].set_boundary(data[0])
+    with kds.Batch(bm) as b:
+        for s in range(3):
+            bm[2].set_boundary(data[s + 1])
+            b.step(1)
+        kms = b.time_kernels(reps=2)
+        assert kms[0] > 0 and kms[1] > 0
+        b.synchronize()
+    for s in range(3):
+        bs[2].set_boundary(data[s + 1])
+        for pb in bs:
+            pb.step(1)
+    for i, (pm, ps) in enumerate(zip(bm, bs)):
+        assert pm.info()["steps_done"] == 3
+        Fm, Fs = pm.get_kinetic(), ps.get_kinetic()
+        assert np.array_equal(Fm, Fs), (i, relerr(Fm, Fs))
+    for pb in bm + bs:
+        pb.close()
+
+
 def test_batch_member_without_state_rejected():
     import torch
     from paper_2212_11010_amd import kds
