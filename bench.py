@@ -343,6 +343,8 @@ def bench_batch(args):
     scheds = [{1: "plain", 2: "line", 3: "front"}[pb.info()["schedule"]] for pb in members]
     log("schedules: %s" % {k: scheds.count(k) for k in set(scheds)})
     b = kds.Batch(members)
+    # the batch's own launch shape (bundle widths of its line members)
+    tune_ms = b.tune(3) if not args.no_tune else None
     b.step(args.warmup)
     b.synchronize()
     torch.cuda.synchronize()
@@ -380,6 +382,7 @@ def bench_batch(args):
     for pb in members:
         pb.close()
     extra = {"schedules": {k: scheds.count(k) for k in set(scheds)},
+             "batch_tune_ms_per_step": tune_ms,
              "grouped_kernel_ms": {"sweep": kms[0], "relax": kms[1]},
              "one_by_one_ms_per_step": ms_single,
              "serial_ms_per_step": ms_serial,

@@ -364,10 +364,14 @@ const char* kds_last_error(const kds_problem* p);
  * together by one time step each per kds_batch_step.  The members keep their
  * own states; a batch step gives exactly the results of kds_step on every
  * member (the same kernels' arithmetic), but the line-schedule members that
- * share (precision, degree, dimension, workgroup size, law, m, n_vel) are
- * swept by ONE launch whose workgroups are spread over the members and
- * relaxed by ONE more launch; plain- and front-schedule members add their own
- * kernel sequences.  A whole batched step is one captured HIP graph whose
+ * share (precision, degree, dimension, workgroup size, law, m, n_vel,
+ * periodic or Dirichlet) are swept by ONE launch whose workgroups are spread
+ * over the members and relaxed by ONE more launch; front-schedule members on
+ * the wave kernel that share (form, dimension, degree, subdomain iterations,
+ * law, m, n_vel) take ONE launch per subdomain iteration and ONE relaxation;
+ * plain-schedule members and front members on the workgroup kernel add their
+ * own kernel sequences.  Dirichlet members advance their boundary data at
+ * the end of each step as in kds_step.  A whole batched step is one captured HIP graph whose
  * groups are parallel branches (they touch disjoint memory), launched on the
  * batch's own stream, ordered after the work already queued on every member's
  * stream; the members' streams are ordered after it.
@@ -396,6 +400,19 @@ kds_status kds_batch_step_timed(kds_batch* b, int32_t n_steps, double* ms);
  * batch stream); line-schedule member states are saved and restored (needs
  * their size in free device memory).  For measurement. */
 kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms);
+
+/* Launch-shape search for the batch (Sec. 5 subdomain parallelism over many
+ * problems): the batched step is timed (reps steps after one untimed, HIP
+ * events on the batch stream) with the line-schedule members' bundles widened
+ * 1, 2 and 4 times (columns of cells per workgroup, where the member's cells
+ * per lane allow it: the same lines and lane arithmetic, so results are
+ * unchanged; the members' own plans are untouched), and the fastest is kept.
+ * Every member's state and boundary data are saved before and restored after
+ * (needs their size in free device memory); step counts do not move.
+ * *best_ms (may be NULL) = ms per step of the kept choice.  Errors:
+ * KDS_E_INVALID, KDS_E_STATE (a member without state), KDS_E_NOMEM,
+ * KDS_E_DEVICE. */
+kds_status kds_batch_tune(kds_batch* b, int32_t reps, double* best_ms);
 
 /* Wait for the batch stream. */
 kds_status kds_batch_synchronize(kds_batch* b);

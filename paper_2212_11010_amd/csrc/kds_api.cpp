@@ -1672,6 +1672,7 @@ struct kds_batch {
   std::vector<int> versions;
   std::vector<Branch> branches;
   std::vector<FrontBranch> fronts;
+  int bw_mul = 1;  // line members' bundles widened this much in the batch (kds_batch_tune)
   std::vector<kds_problem*> others;  // members on the extra branch
   int device = 0;
   hipStream_t stream = nullptr;      // the batch's stream (branch 0 when captured)
@@ -1777,11 +1778,33 @@ kds_status batch_build(kds_batch* b) {
       continue;
     }
     const Geom& g = p->geom;
-    const bool rounds = line_plan_rounds(g, p->plan, (int)p->elem);
+    // the member's plan, with its bundles widened by bw_mul where the cells
+    // per lane allow it (the same lines and lane arithmetic, fewer and
+    // larger workgroups)
+    LinePlan pl = p->plan;
+    if (b->bw_mul > 1) {
+      int tq[3], tb[3];
+      for (int a = 0; a < 3; ++a) {
+        tq[a] = p->line_Q[a];
+        tb[a] = p->line_bw[a];
+        if (tq[a] <= 0) continue;
+        for (int w = tb[a] * b->bw_mul; w > tb[a]; --w)
+          if (line_choice_ok(p, a, tq[a], w)) {
+            tb[a] = w;
+            break;
+          }
+      }
+      LinePlan np;
+      if (finalize_plan(p, tq, tb, np)) {
+        np.xdirect = p->plan.xdirect;
+        pl = np;
+      }
+    }
+    const bool rounds = line_plan_rounds(g, pl, (int)p->elem);
     const bool dir = p->nbnd > 0;
     kds_batch::Branch* br = nullptr;
     for (auto& x : b->branches)
-      if (x.prec == p->prec && x.P == p->P && x.dim == p->dim && x.threads == p->plan.threads &&
+      if (x.prec == p->prec && x.P == p->P && x.dim == p->dim && x.threads == pl.threads &&
           x.law == p->law && x.m == p->m && x.nv == p->nv && x.rounds == rounds && x.dir == dir)
         br = &x;
     if (!br) {
@@ -1790,7 +1813,7 @@ kds_status batch_build(kds_batch* b) {
       br->prec = p->prec;
       br->P = p->P;
       br->dim = p->dim;
-      br->threads = p->plan.threads;
+      br->threads = pl.threads;
       br->law = p->law;
       br->m = p->m;
       br->nv = p->nv;
@@ -1803,10 +1826,10 @@ kds_status batch_build(kds_batch* b) {
     br->members.push_back(p);
     size_t off = br->line_tasks.size();
     br->line_tasks.resize(off + lb);
-    pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), p->plan, p->bnd(),
+    pack_line_task(p->prec, p->f, g, p->sweep_blob.data(), pl, p->bnd(),
                    br->line_tasks.data() + off);
-    br->line_start.push_back(br->line_start.back() + p->plan.block_start[g.nv * g.m]);
-    br->lds_elems = std::max(br->lds_elems, (size_t)std::max(p->plan.lds_elems, p->plan.lds_alloc));
+    br->line_start.push_back(br->line_start.back() + pl.block_start[g.nv * g.m]);
+    br->lds_elems = std::max(br->lds_elems, (size_t)std::max(pl.lds_elems, pl.lds_alloc));
     off = br->relax_tasks.size();
     br->relax_tasks.resize(off + rb);
     pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->f, p->f, p->plane(),
@@ -2118,6 +2141,74 @@ kds_status kds_batch_time_kernels(kds_batch* b, int32_t reps, double* kernel_ms)
   if (e2 != hipSuccess) return bfail(b, KDS_E_DEVICE, std::string("kds_batch_time_kernels restore: ") + hipGetErrorString(e2));
   kernel_ms[0] = ms[0];
   kernel_ms[1] = ms[1];
+  return batch_join_out(b, 0);
+}
+
+kds_status kds_batch_tune(kds_batch* b, int32_t reps, double* best_ms) {
+  if (!b) return bfail(nullptr, KDS_E_INVALID, "batch is NULL");
+  if (reps < 1) return bfail(b, KDS_E_INVALID, "reps must be >= 1");
+  reps = std::min(reps, 100);
+  kds_status st = batch_prepare(b);
+  if (st != KDS_OK) return st;
+  if ((st = batch_join_in(b)) != KDS_OK) return st;
+  // every member's state (and boundary data, which a step advances) is
+  // saved: the timed steps run the whole batch
+  size_t total = 0;
+  for (kds_problem* p : b->probs)
+    total += ((size_t)p->n_unknowns() + (p->nbnd > 0 ? 2 * (size_t)p->bnd_half() : 0)) * p->elem;
+  unsigned char* save = nullptr;
+  if (hipMalloc((void**)&save, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, KDS_E_NOMEM, "kds_batch_tune: no device memory to save the states");
+  }
+  auto copy_states = [&](bool to_save) -> hipError_t {
+    size_t off = 0;
+    hipError_t e = hipSuccess;
+    auto one = [&](void* buf, size_t n) {
+      if (e == hipSuccess)
+        e = to_save ? hipMemcpyAsync(save + off, buf, n, hipMemcpyDeviceToDevice, b->stream)
+                    : hipMemcpyAsync(buf, save + off, n, hipMemcpyDeviceToDevice, b->stream);
+      off += n;
+    };
+    for (kds_problem* p : b->probs) {
+      one(p->f, (size_t)p->n_unknowns() * p->elem);
+      if (p->nbnd > 0) one(p->fb, 2 * (size_t)p->bnd_half() * p->elem);
+    }
+    return e;
+  };
+  hipError_t e = copy_states(true);
+  const int mul0 = b->bw_mul;
+  int best_mul = mul0;
+  double best = -1.0;
+  for (int mul : {1, 2, 4}) {
+    if (e != hipSuccess) break;
+    b->bw_mul = mul;
+    if ((st = batch_build(b)) != KDS_OK || (st = batch_prepare(b)) != KDS_OK) break;
+    e = copy_states(false);
+    // one untimed step, then reps (the members' step counts do not move)
+    if (e == hipSuccess) e = hipGraphLaunch(b->graph_exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->graph_exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b->ev[1]);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, b->ev[0], b->ev[1]);
+    if (e == hipSuccess && (best < 0.0 || t / reps < 0.97 * best)) {
+      best = t / reps;
+      best_mul = mul;
+    }
+  }
+  hipError_t e2 = copy_states(false);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
+  (void)hipFree(save);
+  // keep the fastest choice (the one before the search if the search failed)
+  b->bw_mul = (st == KDS_OK && e == hipSuccess) ? best_mul : mul0;
+  const kds_status st2 = batch_build(b);
+  if (st != KDS_OK) return st;
+  if (e != hipSuccess) return bfail(b, KDS_E_DEVICE, std::string("kds_batch_tune: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return bfail(b, KDS_E_DEVICE, std::string("kds_batch_tune restore: ") + hipGetErrorString(e2));
+  if (st2 != KDS_OK) return st2;
+  if (best_ms) *best_ms = best;
   return batch_join_out(b, 0);
 }
 

@@ -33,7 +33,8 @@ EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_
             "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
             "kds_batch_create", "kds_batch_step", "kds_batch_step_timed",
-            "kds_batch_time_kernels", "kds_batch_synchronize", "kds_batch_destroy",
+            "kds_batch_time_kernels", "kds_batch_tune", "kds_batch_synchronize",
+            "kds_batch_destroy",
             "kds_batch_last_error"]
 _NO_STATUS = ("kds_destroy", "kds_last_error", "kds_batch_destroy", "kds_batch_last_error")
 
@@ -117,6 +118,7 @@ def lib():
         L.kds_batch_step.argtypes = [vp, C.c_int32]
         L.kds_batch_step_timed.argtypes = [vp, C.c_int32, dp]
         L.kds_batch_time_kernels.argtypes = [vp, C.c_int32, dp]
+        L.kds_batch_tune.argtypes = [vp, C.c_int32, dp]
         L.kds_batch_synchronize.argtypes = [vp]
         L.kds_batch_destroy.argtypes = [vp]
         L.kds_batch_destroy.restype = None
@@ -380,6 +382,12 @@ def kds_batch_time_kernels(b, reps=10):
     return list(out)
 
 
+def kds_batch_tune(b, reps=3):
+    ms = C.c_double(0.0)
+    _bcheck(lib().kds_batch_tune(b, int(reps), C.byref(ms)), b)
+    return ms.value
+
+
 def kds_batch_synchronize(b):
     _bcheck(lib().kds_batch_synchronize(b), b)
 
@@ -515,6 +523,9 @@ class Batch:
 
     def time_kernels(self, reps=10):
         return kds_batch_time_kernels(self.h, reps)
+
+    def tune(self, reps=3):
+        return kds_batch_tune(self.h, reps)
 
     def synchronize(self):
         kds_batch_synchronize(self.h)

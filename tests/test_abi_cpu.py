@@ -183,5 +183,6 @@ def test_batch_calls_reject_null_and_empty():
     assert L.kds_batch_create(arr, 2, C.byref(out)) == kds.KDS_E_INVALID
     assert not out.value
     assert L.kds_batch_step(None, 1) == kds.KDS_E_INVALID
+    assert L.kds_batch_tune(None, 3, None) == kds.KDS_E_INVALID
     assert L.kds_batch_synchronize(None) == kds.KDS_E_INVALID
     L.kds_batch_destroy(None)

@@ -163,6 +163,44 @@ def test_batch_front_members_grouped():
         pb.close()
 
 
+def test_batch_tune_keeps_results_and_state():
+    """kds_batch_tune times widened bundles for the line members; the states,
+    boundary data and step counts are restored, and the batch with the kept
+    choice still gives the single-problem results bitwise (a Dirichlet
+    member included)."""
+    import torch
+    from paper_2212_11010_amd import kds
+    from paper_2212_11010_amd import workloads as wl
+    specs = small_batch(seed=17, n=6)
+    members = make_members(specs, "fp32", ["auto"] * len(specs))
+    singles = make_members(specs, "fp32", ["auto"] * len(specs))
+    dspec, dW0 = wl.make_workload(2, n_cells=[24, 16], sub_cells=[8, 8], periodic=[0, 1], steps=2)
+    Wb = wl.boundary_state(dspec, dW0)
+    dm, ds = [], []
+    for lst in (dm, ds):
+        pb = kds.Problem(dspec, precision="fp32")
+        pb.set_state(torch.from_numpy(dW0).cuda())
+        pb.set_boundary(0.99 * Wb)
+        pb.set_boundary(Wb)
+        lst.append(pb)
+    before = [pb.get_kinetic() for pb in members + dm]
+    with kds.Batch(members + dm) as b:
+        ms = b.tune(reps=2)
+        assert ms > 0
+        for pb, F in zip(members + dm, before):
+            assert pb.info()["steps_done"] == 0
+            assert np.array_equal(pb.get_kinetic(), F)
+        b.step(2)
+        b.synchronize()
+    for pb in singles + ds:
+        pb.step(2)
+    for i, (pm, ps) in enumerate(zip(members + dm, singles + ds)):
+        Fm, Fs = pm.get_kinetic(), ps.get_kinetic()
+        assert np.array_equal(Fm, Fs), (i, relerr(Fm, Fs))
+    for pb in members + singles + dm + ds:
+        pb.close()
+
+
 def test_batch_member_without_state_rejected():
     import torch
     from paper_2212_11010_amd import kds
