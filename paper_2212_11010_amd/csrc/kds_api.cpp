@@ -1631,10 +1631,13 @@ const char* kds_last_error(const kds_problem* p) {
 // (precision, degree, dimension, workgroup size, law, m, n_vel, periodic or
 // Dirichlet) form a branch: ONE launch sweeps all of them (workgroups spread
 // over the members), ONE launch relaxes them.  Branches touch disjoint memory
-// and run as parallel branches of one captured HIP graph per step; the
-// plain- and front-schedule members add their own kernel sequences on one
-// more branch.  (A Dirichlet member's records point at its two boundary
-// halves, which kds_set_boundary refills in place between steps.)
+// and run as parallel branches of one captured HIP graph per step.  Front-
+// schedule members on the wave kernel form branches of their own (one launch
+// per subdomain iteration, one relaxation).  Plain-schedule members and front
+// members on the workgroup kernel add their own kernel sequences on one more
+// branch.  (A Dirichlet member's records point at its two boundary halves,
+// which kds_set_boundary refills in place between steps; the batch step
+// advances them as a member's own step does.)
 
 struct kds_batch {
   struct Branch {
