@@ -308,6 +308,23 @@ kds_status kds_set_kinetic(kds_problem* p, const double* F, int32_t on_device);
 /* Scan the kinetic state for NaN/Inf: KDS_OK or KDS_E_NONFINITE. */
 kds_status kds_check_finite(kds_problem* p);
 
+/* Residual of the subdomain iteration (Sec. 5.1, eq:ibvp): for the step that
+ * would start from the current state (and boundary data), the outflow traces
+ * of every subdomain (every velocity, component and node line through the
+ * subdomain's downwind face) after the last iterate K and after iterate K-1
+ * (iterate 0 = the state itself), and
+ *   out[0] = max |tr^(K) - tr^(K-1)|,  out[1] = max |tr^(K)|.
+ * With lagged interface data, what leaves a subdomain through its downwind
+ * face (iterate K) and what enters the next one (iterate K-1) differ by this
+ * difference, weighted by theta |V_k| dt and the face quadrature, so out[0]
+ * measures the conservation defect of a step; it goes to 0 as the iteration
+ * converges (n_iter = 0: out = {0, -1}).  The state is not changed; runs the
+ * literal sweep's kernels (one launch per iterate) on the problem's stream and
+ * waits.  Axis-aligned velocity sets only (else KDS_E_UNSUPPORTED); errors
+ * KDS_E_INVALID, KDS_E_STATE (no state, or Dirichlet data missing),
+ * KDS_E_NOMEM (two trace sets of device memory), KDS_E_DEVICE. */
+kds_status kds_trace_residual(kds_problem* p, double* out);
+
 /* Wait for all work of the problem's stream. */
 kds_status kds_synchronize(kds_problem* p);
 

@@ -12,7 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libkds.so")
 SOURCES = ["csrc/kds_setup.cpp", "csrc/kds_api.cpp", "csrc/kds_kernels.hip",
-           "csrc/kds_front.hip", "csrc/kds_front_wave.hip", "csrc/kds_line_f32.hip", "csrc/kds_line_f64.hip"]
+           "csrc/kds_front.hip", "csrc/kds_front_wave.hip", "csrc/kds_line_f32.hip", "csrc/kds_line_f64.hip",
+           "csrc/kds_metrics.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

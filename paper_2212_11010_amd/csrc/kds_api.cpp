@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kds_internal.h"
+#include "kds_metrics.h"
 
 using namespace kds;
 
@@ -1574,6 +1575,52 @@ kds_status kds_check_finite(kds_problem* p) {
   KDS_HIP(p, hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   KDS_HIP(p, hipStreamSynchronize(p->stream));
   if (flag) return fail(p, KDS_E_NONFINITE, "kinetic state holds NaN or Inf");
+  return KDS_OK;
+}
+
+kds_status kds_trace_residual(kds_problem* p, double* out) {
+  if (!p || !out) return fail(p, KDS_E_INVALID, "NULL argument");
+  if (!p->state_set) return fail(p, KDS_E_STATE, "kds_trace_residual before kds_set_state");
+  if (p->nbnd > 0 && !p->bnd_set)
+    return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary before kds_trace_residual");
+  if (p->sweep_blob.empty())
+    return fail(p, KDS_E_UNSUPPORTED,
+                "kds_trace_residual: oblique velocities (the traces of axis-aligned sweeps only)");
+  const Geom& g = p->geom;
+  if (p->K == 0) {  // the converged iteration: no residual
+    out[0] = 0.0;
+    out[1] = -1.0;
+    return KDS_OK;
+  }
+  // two trace sets, zeroed (entries no velocity uses stay 0 in both), and the
+  // two reduction words
+  const int64_t n = g.tr_stride * (int64_t)p->nv * p->m;
+  const size_t bytes = (size_t)n * p->elem;
+  unsigned char* buf = nullptr;
+  if (hipMalloc((void**)&buf, 2 * bytes + 16) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, KDS_E_NOMEM, "kds_trace_residual: no device memory for the traces");
+  }
+  void* tr[2] = {buf, buf + bytes};
+  unsigned long long* red = (unsigned long long*)(buf + 2 * bytes);
+  hipError_t e = hipMemsetAsync(buf, 0, 2 * bytes + 16, p->stream);
+  // iterates 1 .. K of the sweep from the current state (the state itself
+  // is not changed); with K = 1 the other set is iterate 0, the state's own
+  // traces
+  if (e == hipSuccess && p->K == 1)
+    e = launch_trace_iterate0(p->prec, g, p->sweep_blob.data(), p->f, tr[0], p->stream);
+  for (int it = 1; it <= p->K && e == hipSuccess; ++it)
+    e = launch_sweep_plain(p->prec, g, p->sweep_blob.data(), p->f, nullptr,
+                           it == 1 ? nullptr : tr[(it - 1) & 1], tr[it & 1], p->bnd(), p->stream);
+  if (e == hipSuccess)
+    e = launch_max_absdiff(p->prec, tr[p->K & 1], tr[(p->K - 1) & 1], n, red, p->stream);
+  unsigned long long bits[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(bits, red, 16, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(p, e, "kds_trace_residual");
+  std::memcpy(&out[0], &bits[0], 8);
+  std::memcpy(&out[1], &bits[1], 8);
   return KDS_OK;
 }
 

@@ -30,7 +30,8 @@ EXPORTED = ["kds_create", "kds_set_state", "kds_set_boundary", "kds_step", "kds_
             "kds_tune", "kds_tune_cached", "kds_tune_subdomains", "kds_set_launch",
             "kds_get_plan", "kds_set_plan",
             "kds_time_kernels", "kds_moments", "kds_moments_static",
-            "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_synchronize",
+            "kds_get_kinetic", "kds_set_kinetic", "kds_check_finite", "kds_trace_residual",
+            "kds_synchronize",
             "kds_info", "kds_destroy", "kds_last_error",
             "kds_batch_create", "kds_batch_step", "kds_batch_step_timed",
             "kds_batch_time_kernels", "kds_batch_tune", "kds_batch_synchronize",
@@ -108,6 +109,7 @@ def lib():
         L.kds_get_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_set_kinetic.argtypes = [vp, vp, C.c_int32]
         L.kds_check_finite.argtypes = [vp]
+        L.kds_trace_residual.argtypes = [vp, dp]
         L.kds_synchronize.argtypes = [vp]
         L.kds_info.argtypes = [vp, C.POINTER(kds_info_t)]
         L.kds_destroy.argtypes = [vp]
@@ -334,6 +336,12 @@ def kds_check_finite(h):
     return True
 
 
+def kds_trace_residual(h):
+    out = (C.c_double * 2)()
+    _check(lib().kds_trace_residual(h, out), h)
+    return out[0], out[1]
+
+
 def kds_synchronize(h):
     _check(lib().kds_synchronize(h), h)
 
@@ -483,6 +491,11 @@ class Problem:
 
     def check_finite(self):
         return kds_check_finite(self.h)
+
+    def trace_residual(self):
+        """(max |tr^(K) - tr^(K-1)|, max |tr^(K)|) of the step that would
+        start from the current state."""
+        return kds_trace_residual(self.h)
 
     def synchronize(self):
         kds_synchronize(self.h)

@@ -163,6 +163,7 @@ def test_null_arguments_are_rejected():
     assert L.kds_get_plan(None, None) == kds.KDS_E_INVALID
     assert L.kds_set_plan(None, None) == kds.KDS_E_INVALID
     assert L.kds_tune_cached(None, 1, b"plans.txt", None) == kds.KDS_E_INVALID
+    assert L.kds_trace_residual(None, None) == kds.KDS_E_INVALID
     L.kds_destroy(None)
 
 
