@@ -118,6 +118,15 @@ def time_problem(spec, W0, prec, sched, steps, warmup, tune=False, plan=None):
     # around `steps` back-to-back launches of each kernel (state restored)
     kms = pb.time_kernels(steps)
     ok = pb.check_finite()
+    # the subdomain iteration's residual at the state reached (Sec. 5.1):
+    # change of the outflow traces between the last two iterates
+    try:
+        d, v = pb.trace_residual()
+        info["trace_residual"] = {"max_abs_change": d, "max_abs_trace": v,
+                                  "relative": d / v if v > 0 else 0.0, "n_iter": spec["n_iter"]}
+    except kds.KdsError as e:
+        if e.status != kds.KDS_E_UNSUPPORTED:
+            raise
     pb.close()
     return ms_graph, kms, info, ok, plan
 
@@ -506,6 +515,8 @@ def main():
                            "lds_bytes_per_workgroup": info32["line_lds_bytes"],
                            "step_launch": "enqueued" if info32["step_eager"] else "graph",
                            "relax_16byte_access": bool(info32["relax_vec"])}}
+    if "trace_residual" in info32:
+        extra["trace_residual"] = info32["trace_residual"]
     if sched == "line":
         # the line kernel resolves all n_iter subdomain iterations in one launch
         extra["fp32_sweep_ms_per_iteration_equivalent"] = k32[0] / max(1, spec["n_iter"])
