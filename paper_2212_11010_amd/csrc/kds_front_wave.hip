@@ -283,10 +283,23 @@ __device__ __forceinline__ void front_wave_task(
   int ncb, nce, nlev2;
   advance(cb, ce, lev, ncb, nce, nlev2);
   int4 dc = desc[min(cb + li, n_desc - 1)];
-  int4 dn = desc[min(ncb + li, n_desc - 1)];
-  float pc[CS], pvo[DIM * FS], pvn[DIM * FS];
-  issue(dc, cb + li < ce, pc, pvo, pvn);
-  while (lev < nlev) {
+  // Two sets of registers for the prefetched records and cell values, used
+  // in turn: a tile reads the set the tile before it loaded and loads the
+  // other one, so no load in flight is copied between registers (a copy at
+  // the end of the loop would wait for the load there, a tile early).  The
+  // face values are consumed before the next ones are loaded: one set.
+  int4 dA = desc[min(ncb + li, n_desc - 1)], dB = dA;
+  float pcA[CS], pcB[CS], pvo[DIM * FS], pvn[DIM * FS];
+  issue(dc, cb + li < ce, pcA, pvo, pvn);
+  // (the first tile needs these at once; waiting here also leaves nothing
+  // in flight on the way into the loop, so the waits inside it count only
+  // the loads a tile ahead, not the stores issued after them)
+  __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+  // one tile: the current record dc, cell values pc and face values (pvo,
+  // pvn); dn: the next tile's record (loaded a tile ago); dnn_out, pcN: where
+  // the record after it and the next tile's cell values are loaded
+  auto tile = [&](const int4& dn, int4& dnn_out, const float(&pc)[CS], float(&pcN)[CS])
+                  __attribute__((always_inline)) {
     // ---- this tile's columns: lane j's cell (its loads were issued a tile ago)
     const bool valid = cb + li < ce;
     const unsigned off = sdb + (unsigned)dc.x;
@@ -335,8 +348,8 @@ __device__ __forceinline__ void front_wave_task(
     // ---- the next tile's loads, and the records of the one after
     int nncb, nnce, nlev3;
     advance(ncb, nce, nlev2, nncb, nnce, nlev3);
-    const int4 dnn = desc[min(nncb + li, n_desc - 1)];
-    issue(dn, nlev2 < nlev && ncb + li < nce, pc, pvo, pvn);
+    dnn_out = desc[min(nncb + li, n_desc - 1)];
+    issue(dn, nlev2 < nlev && ncb + li < nce, pcN, pvo, pvn);
 
     // ---- Y = W X
     wf32x4 acc[MT];
@@ -437,16 +450,21 @@ __device__ __forceinline__ void front_wave_task(
     nce = nnce;
     nlev2 = nlev3;
     dc = dn;
-    dn = dnn;
+  };
+  while (lev < nlev) {
+    tile(dA, dB, pcA, pcB);
+    if (lev >= nlev) break;
+    tile(dB, dA, pcB, pcA);
   }
 }
 
-// waves per SIMD the register budget aims at: with the 27-node cell, the
-// split forms (operator slice as hi / lo halves) need more than a quarter of
-// the register file
+// waves per SIMD the register budget aims at: with the 27-node cell every
+// form needs more than a quarter of the register file (the operator slice,
+// two sets of prefetched cell values; the split forms hold hi / lo halves):
+// three waves without spills measured as fast as four with them
 template <int MODE, int DIM, int P>
 constexpr int wave_occupancy() {
-  return (WaveShape<DIM, P>::NN > 16 && MODE != kFrontMfma) ? 3 : 4;
+  return WaveShape<DIM, P>::NN > 16 ? 3 : 4;
 }
 
 // One task (velocity, subdomain, component) of one problem: the body of the
