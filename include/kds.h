@@ -211,9 +211,10 @@ kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec)
  * ignored (kds_set_plan).  step_eager and relax_vec as in kds_set_launch.
  * front_kernel (front schedule; 0 elsewhere): 1 = one workgroup per
  * (velocity, subdomain), any cell size and precision; 2 = one wave per
- * (velocity, subdomain, component), the FP32 matrix-core forms with cells of
- * at most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D) and frontiers that fit the
- * LDS; kds_set_plan with front_kernel = 0 keeps the current kernel.
+ * (velocity, subdomain, component), the FP32 matrix-core forms and FP64 (on
+ * the FP64 matrix cores) with cells of at most 32 nodes (p <= 2 in 3-D,
+ * p <= 3 in 2-D) and frontiers that fit the LDS; kds_set_plan with
+ * front_kernel = 0 keeps the current kernel.
  * The FP64 results of every valid plan agree to rounding; FP32 results depend
  * on Q (the association of the line scan) and on the front kernel (the order
  * of the products' sums), so a plan saved with kds_get_plan and restored with
@@ -384,10 +385,10 @@ const char* kds_last_error(const kds_problem* p);
  * share (precision, degree, dimension, workgroup size, law, m, n_vel,
  * periodic or Dirichlet) are swept by ONE launch whose workgroups are spread
  * over the members and relaxed by ONE more launch; front-schedule members on
- * the wave kernel that share (form, dimension, degree, subdomain iterations,
- * law, m, n_vel) take ONE launch per subdomain iteration and ONE relaxation;
- * plain-schedule members and front members on the workgroup kernel add their
- * own kernel sequences.  Dirichlet members advance their boundary data at
+ * the wave kernel in FP32 forms that share (form, dimension, degree,
+ * subdomain iterations, law, m, n_vel) take ONE launch per subdomain
+ * iteration and ONE relaxation; plain-schedule members, FP64 front members
+ * and front members on the workgroup kernel add their own kernel sequences.  Dirichlet members advance their boundary data at
  * the end of each step as in kds_step.  A whole batched step is one captured HIP graph whose
  * groups are parallel branches (they touch disjoint memory), launched on the
  * batch's own stream, ordered after the work already queued on every member's

@@ -449,8 +449,9 @@ void free_device(kds_problem* p) {
 // One subdomain iteration of the front schedule, with the problem's kernel choice.
 hipError_t launch_front_iter(kds_problem* p, const void* f_prev, void* f_cur, hipStream_t s) {
   if (p->front_wave)
-    return launch_sweep_front_wave(p->front_mode, p->geom, p->front, p->front_W, p->front_lvl_start,
-                                   p->front_desc, p->front_ndesc, p->f, f_prev, f_cur, p->bnd(), s);
+    return launch_sweep_front_wave(p->prec, p->front_mode, p->geom, p->front, p->front_W,
+                                   p->front_lvl_start, p->front_desc, p->front_ndesc, p->f, f_prev,
+                                   f_cur, p->bnd(), s);
   return launch_sweep_front(p->prec, p->front_mode, p->geom, p->front, p->front_W,
                             p->front_lvl_start, p->front_lvl_cells, p->f, f_prev, f_cur, p->bnd(), s);
 }
@@ -701,7 +702,8 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
     p->sched = KDS_SCHED_FRONT;
     p->front_ndesc = (int)front_desc.size();
     // the wave-per-task kernel where it applies (its records fit, FP32
-    // matrix-core modes, p <= 2 in 3-D), else one workgroup per subdomain
+    // matrix-core modes or FP64, p <= 2 in 3-D), else one workgroup per
+    // subdomain
     p->front_wave = front_wave_ok(p);
     if (!p->front_wave && !front_wg_ok(p)) {
       delete p;
@@ -1780,8 +1782,8 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    if (p->sched == KDS_SCHED_FRONT && p->front_wave && front_wave_ok(p)) {
-      // front members on the wave kernel: grouped by their kernel and step
+    if (p->sched == KDS_SCHED_FRONT && p->front_wave && front_wave_ok(p) && p->prec == KDS_FP32) {
+      // FP32 front members on the wave kernel: grouped by their kernel and step
       const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
       if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
       kds_batch::FrontBranch* fb = nullptr;

@@ -1,6 +1,7 @@
 // kds_front_wave.hip -- the front schedule with one wave per
-// (velocity, subdomain, component): the FP32 matrix-core forms for cells of
-// at most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D).
+// (velocity, subdomain, component): the FP32 matrix-core forms, and FP64 on
+// the FP64 matrix cores, for cells of at most 32 nodes (p <= 2 in 3-D,
+// p <= 3 in 2-D).
 //
 // The same computation as k_sweep_front (the solves of one anti-diagonal
 // front of the V-oriented cell graph as one GEMM Y = W X per front, Sec. 3.2,
@@ -37,6 +38,7 @@ namespace {
 constexpr unsigned kOob = 0x80000000u;  // byte offset past every buffer of the kernel
 
 typedef float wf32x4 __attribute__((ext_vector_type(4)));
+typedef double wf64x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 wf16x4 __attribute__((ext_vector_type(4)));
 typedef short wi16x4 __attribute__((ext_vector_type(4)));
 
@@ -92,6 +94,42 @@ __device__ __forceinline__ void bstore_run(__amdgpu_buffer_rsrc_t r, unsigned o,
   }
 }
 
+// the same for FP64 values (8-byte elements: pairs with 16-byte accesses)
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  const u2 x = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  return __builtin_bit_cast(double, x);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float) {
+  return bload(r, byte_off);
+}
+template <int N>
+__device__ __forceinline__ void bload_run(__amdgpu_buffer_rsrc_t r, unsigned o, double* v) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if constexpr (N >= 2) {
+    const u4 x = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
+    v[0] = __builtin_bit_cast(double, u2{x[0], x[1]});
+    v[1] = __builtin_bit_cast(double, u2{x[2], x[3]});
+    bload_run<N - 2>(r, o + 16u, v + 2);
+  } else if constexpr (N == 1) {
+    v[0] = bload(r, o, 0.0);
+  }
+}
+template <int N>
+__device__ __forceinline__ void bstore_run(__amdgpu_buffer_rsrc_t r, unsigned o, const double* v) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if constexpr (N >= 2) {
+    const u2 a = __builtin_bit_cast(u2, v[0]), b = __builtin_bit_cast(u2, v[1]);
+    const u4 x = {a[0], a[1], b[0], b[1]};
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, o, 0, 0);
+    bstore_run<N - 2>(r, o + 16u, v + 2);
+  } else if constexpr (N == 1) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v[0]), r, o, 0, 0);
+  }
+}
+
 __device__ __forceinline__ unsigned short wbf16_rne(float x) {
   const unsigned int b = __float_as_uint(x);
   return (unsigned short)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
@@ -136,14 +174,14 @@ struct WaveK {
 // The tasks' work: levels of one subdomain, tiles of 16 cells of a level.
 // BND: Dirichlet box faces on the subdomain's inflow side (boundary traces
 // are a second pair of buffers).
-template <int MODE, int DIM, int P, bool BND>
+template <typename T, int MODE, int DIM, int P, bool BND>
 __device__ __forceinline__ void front_wave_task(
-    const Geom& g, const FrontParams& fp, const float* __restrict__ Wk,
+    const Geom& g, const FrontParams& fp, const T* __restrict__ Wk,
     const int* __restrict__ lvl_start, const int4* __restrict__ desc, int n_desc, int k,
     const int (&sg)[3], const int (&sdc)[3], const int (&nbrel)[3], const int (&isb)[3],
     const int (&boff)[3], unsigned sdb, __amdgpu_buffer_rsrc_t rfo, __amdgpu_buffer_rsrc_t rfp,
-    __amdgpu_buffer_rsrc_t rfc, __amdgpu_buffer_rsrc_t rbo, __amdgpu_buffer_rsrc_t rbn, float* FR,
-    float* XO) {
+    __amdgpu_buffer_rsrc_t rfc, __amdgpu_buffer_rsrc_t rbo, __amdgpu_buffer_rsrc_t rbn, T* FR,
+    T* XO) {
   using S = WaveShape<DIM, P>;
   constexpr int NN = S::NN, NF = S::NF, CS = S::CS, FS = S::FS, FSTR = S::FSTR, MT = S::MT,
                 XOS = S::XOS;
@@ -152,7 +190,8 @@ __device__ __forceinline__ void front_wave_task(
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
   const int Kd = fp.Kd;
-  const float th = (float)fp.theta, th1 = 1.0f - th;
+  constexpr unsigned ES = sizeof(T);  // bytes per value (offsets below are in bytes)
+  const T th = (T)fp.theta, th1 = T(1) - th;
   const int frn = 3 * fp.fr_pos * FSTR;  // frontier values; FR[frn] is a write sink
   // Slots of lane group lk: cell nodes cst .. cst + CS - 1 and face nodes
   // fst .. fst + FS - 1, runs inside the cell and the face (the last group's
@@ -163,7 +202,7 @@ __device__ __forceinline__ void front_wave_task(
   // ---- the operator slice: lane (i, g) of row tile t holds operator row
   // 16 t + i at the K positions of slots e (e = st in the 16x16x4 products,
   // 4 st + u in the 16x16x16 ones)
-  float afr[MODE == kFrontMfma ? MT : 1][MODE == kFrontMfma ? KS : 1];
+  T afr[MODE == kFrontMfma ? MT : 1][MODE == kFrontMfma ? KS : 1];
   wf16x4 ah16[MODE == kFrontSplitF16 ? MT : 1][KB], al16[MODE == kFrontSplitF16 ? MT : 1][KB];
   wi16x4 ahb[MODE == kFrontSplitBf16 ? MT : 1][KB], alb[MODE == kFrontSplitBf16 ? MT : 1][KB];
 #pragma unroll
@@ -181,7 +220,7 @@ __device__ __forceinline__ void front_wave_task(
         const int a = (e - CS) / FS, q = fst + (e - CS) % FS;
         col = q >= lk * FS ? NN + a * NF + q : -1;
       }
-      const float w = (i < NN && col >= 0) ? Wk[i * Kd + col] : 0.0f;
+      const T w = (i < NN && col >= 0) ? Wk[i * Kd + col] : T(0);
       if constexpr (MODE == kFrontMfma) {
         afr[t][e] = w;
       } else if constexpr (MODE == kFrontSplitF16) {
@@ -203,36 +242,36 @@ __device__ __forceinline__ void front_wave_task(
 #pragma unroll
   for (int j = 0; j < FS; ++j) {
     const int q = fst + j;
-    bq4[j] = 4u * q;
+    bq4[j] = ES * q;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int side = sg[a] > 0 ? P - 1 : 0;
       const int node = a == 0 ? side + P * q
                               : (a == 1 ? (q % P) + P * side + P * P * (q / P) : q + P * P * side);
-      nbn4[a][j] = a < DIM ? 4u * node : kOob;
+      nbn4[a][j] = a < DIM ? ES * node : kOob;
     }
   }
   // the frontier starts at zero (a read it serves before the upwind cell wrote
   // it is discarded, but stays a finite number)
-  for (int x = lane; x <= frn; x += 64) FR[x] = 0.0f;
+  for (int x = lane; x <= frn; x += 64) FR[x] = T(0);
 
   // ---- the global loads of a tile (records d; columns with `ok`): the cell
   // values at t^{n-1}, and on inflow faces across an interface or a Dirichlet
   // box face the old and new traces.  None of them depends on the sweep, so
   // a tile's loads are issued while the tile before it computes.
-  auto issue = [&](const int4 d, bool ok, float (&pc)[CS], float (&pvo)[DIM * FS],
-                   float (&pvn)[DIM * FS]) {
+  auto issue = [&](const int4 d, bool ok, T (&pc)[CS], T (&pvo)[DIM * FS],
+                   T (&pvn)[DIM * FS]) {
     const unsigned off = sdb + (unsigned)d.x;  // node 0 of the cell in its plane
     const int pk = d.y;
     // nodes cst .. cst + CS - 1: consecutive, read with wide loads
-    bload_run<CS>(rfo, ok ? (off + (unsigned)cst) * 4u : kOob, pc);
+    bload_run<CS>(rfo, ok ? (off + (unsigned)cst) * ES : kOob, pc);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       // the first cell of the subdomain along a reads across the interface
       // (iterate p-1, periodic wrap included) or the boundary data
       const int la = (pk >> (10 * a)) & 1023;
       const bool first = ok && sg[a] != 0 && la == 0;
-      const unsigned nb4 = (first && !isb[a]) ? ((unsigned)((int)off + nbrel[a])) * 4u : kOob;
+      const unsigned nb4 = (first && !isb[a]) ? ((unsigned)((int)off + nbrel[a])) * ES : kOob;
       unsigned bb4 = kOob;
       if constexpr (BND) {
         // the boundary node block of the cell's face: cells over the other axes
@@ -245,22 +284,22 @@ __device__ __forceinline__ void front_wave_task(
             fcell += (sdc[o] * g.S[o] + pl) * mul;
             mul *= g.N[o];
           }
-        if (first && isb[a]) bb4 = (unsigned)(boff[a] + fcell * NF) * 4u;
+        if (first && isb[a]) bb4 = (unsigned)(boff[a] + fcell * NF) * ES;
       }
 #pragma unroll
-      for (int j = 0; j < FS; ++j) pvo[a * FS + j] = pvn[a * FS + j] = 0.0f;
+      for (int j = 0; j < FS; ++j) pvo[a * FS + j] = pvn[a * FS + j] = T(0);
       // (the host puts a front's first cells first: most tiles have none)
       if (__any(first)) {
 #pragma unroll
         for (int j = 0; j < FS; ++j) {
           const int s = a * FS + j;
-          pvo[s] = bload(rfo, nb4 + nbn4[a][j]);
-          pvn[s] = bload(rfp, nb4 + nbn4[a][j]);
+          pvo[s] = bload(rfo, nb4 + nbn4[a][j], T(0));
+          pvn[s] = bload(rfp, nb4 + nbn4[a][j], T(0));
           if constexpr (BND) {
             // a row reads the state or the boundary data, never both: the
             // other load is out of range and adds an exact 0
-            pvo[s] += bload(rbo, bb4 + bq4[j]);
-            pvn[s] += bload(rbn, bb4 + bq4[j]);
+            pvo[s] += bload(rbo, bb4 + bq4[j], T(0));
+            pvn[s] += bload(rbn, bb4 + bq4[j], T(0));
           }
         }
       }
@@ -289,7 +328,7 @@ __device__ __forceinline__ void front_wave_task(
   // the end of the loop would wait for the load there, a tile early).  The
   // face values are consumed before the next ones are loaded: one set.
   int4 dA = desc[min(ncb + li, n_desc - 1)], dB = dA;
-  float pcA[CS], pcB[CS], pvo[DIM * FS], pvn[DIM * FS];
+  T pcA[CS], pcB[CS], pvo[DIM * FS], pvn[DIM * FS];
   issue(dc, cb + li < ce, pcA, pvo, pvn);
   // (the first tile needs these at once; waiting here also leaves nothing
   // in flight on the way into the loop, so the waits inside it count only
@@ -298,7 +337,7 @@ __device__ __forceinline__ void front_wave_task(
   // one tile: the current record dc, cell values pc and face values (pvo,
   // pvn); dn: the next tile's record (loaded a tile ago); dnn_out, pcN: where
   // the record after it and the next tile's cell values are loaded
-  auto tile = [&](const int4& dn, int4& dnn_out, const float(&pc)[CS], float(&pcN)[CS])
+  auto tile = [&](const int4& dn, int4& dnn_out, const T(&pc)[CS], T(&pcN)[CS])
                   __attribute__((always_inline)) {
     // ---- this tile's columns: lane j's cell (its loads were issued a tile ago)
     const bool valid = cb + li < ce;
@@ -317,10 +356,10 @@ __device__ __forceinline__ void front_wave_task(
     // its frontier slots (in range for any record) and both candidates are
     // formed before the selects: the reads go out together, and no lane
     // branches on its face kind.
-    float bx[KS];
+    T bx[KS];
 #pragma unroll
     for (int e = 0; e < CS; ++e) bx[e] = pc[e];
-    float frv[DIM * FS], trv[DIM * FS];
+    T frv[DIM * FS], trv[DIM * FS];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
@@ -340,7 +379,7 @@ __device__ __forceinline__ void front_wave_task(
         bx[CS + s] = isfr[a] ? frv[s] : trv[s];
       }
 #pragma unroll
-    for (int e = CS + DIM * FS; e < KS; ++e) bx[e] = 0.0f;
+    for (int e = CS + DIM * FS; e < KS; ++e) bx[e] = T(0);
     // the cell's own values, for the outflow traces of the epilogue
 #pragma unroll
     for (int e = 0; e < CS; ++e) XO[li * XOS + cst + e] = bx[e];
@@ -352,15 +391,20 @@ __device__ __forceinline__ void front_wave_task(
     issue(dn, nlev2 < nlev && ncb + li < nce, pcN, pvo, pvn);
 
     // ---- Y = W X
-    wf32x4 acc[MT];
+    using AccV = typename std::conditional<sizeof(T) == 8, wf64x4, wf32x4>::type;
+    AccV acc[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) acc[t] = wf32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MT; ++t) acc[t] = AccV{T(0), T(0), T(0), T(0)};
     if constexpr (MODE == kFrontMfma) {
 #pragma unroll
       for (int e = 0; e < KS; ++e)
 #pragma unroll
-        for (int t = 0; t < MT; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[t][e], bx[e], acc[t], 0, 0, 0);
+        for (int t = 0; t < MT; ++t) {
+          if constexpr (sizeof(T) == 8)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[t][e], bx[e], acc[t], 0, 0, 0);
+          else
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[t][e], bx[e], acc[t], 0, 0, 0);
+        }
     } else {
       wf32x4 cor[MT];
 #pragma unroll
@@ -413,30 +457,35 @@ __device__ __forceinline__ void front_wave_task(
     // theta y + (1 - theta) f^{n-1}, which each lane copies into the frontier
     // for its face-node runs (a cell's outflow node with face index q on axis
     // a is the node its downwind neighbour reads as the upwind one)
-    float* TB = XO + li * XOS;
-    float xo[MT][4];
+    T* TB = XO + li * XOS;
+    // product row of item v of row tile t in this lane: FP32 products give
+    // a lane four consecutive rows, FP64 products every fourth row
+    auto orow = [&](int t, int v) {
+      return sizeof(T) == 8 ? 16 * t + 4 * v + lk : 16 * t + 4 * lk + v;
+    };
+    T xo[MT][4];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xo[t][v] = TB[16 * t + 4 * lk + v];
+      for (int v = 0; v < 4; ++v) xo[t][v] = TB[orow(t, v)];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) TB[16 * t + 4 * lk + v] = acc[t][v];
-    float yr[CS];
+      for (int v = 0; v < 4; ++v) TB[orow(t, v)] = acc[t][v];
+    T yr[CS];
 #pragma unroll
     for (int e = 0; e < CS; ++e) yr[e] = TB[cst + e];
-    bstore_run<CS>(rfc, valid ? (off + (unsigned)cst) * 4u : kOob, yr);
+    bstore_run<CS>(rfc, valid ? (off + (unsigned)cst) * ES : kOob, yr);
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) TB[16 * t + 4 * lk + v] = th * acc[t][v] + th1 * xo[t][v];
+      for (int v = 0; v < 4; ++v) TB[orow(t, v)] = th * acc[t][v] + th1 * xo[t][v];
     // (all trace reads before the frontier writes: one LDS round trip)
-    float zv[DIM * FS];
+    T zv[DIM * FS];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
-      for (int j = 0; j < FS; ++j) zv[a * FS + j] = TB[nbn4[a][j] >> 2];
+      for (int j = 0; j < FS; ++j) zv[a * FS + j] = TB[nbn4[a][j] / ES];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
@@ -461,28 +510,29 @@ __device__ __forceinline__ void front_wave_task(
 // waves per SIMD the register budget aims at: with the 27-node cell every
 // form needs more than a quarter of the register file (the operator slice,
 // two sets of prefetched cell values; the split forms hold hi / lo halves):
-// three waves without spills measured as fast as four with them
-template <int MODE, int DIM, int P>
+// three waves without spills measured as fast as four with them.  FP64
+// takes two registers per value: two waves
+template <typename T, int MODE, int DIM, int P>
 constexpr int wave_occupancy() {
-  return WaveShape<DIM, P>::NN > 16 ? 3 : 4;
+  return sizeof(T) == 8 ? 2 : (WaveShape<DIM, P>::NN > 16 ? 3 : 4);
 }
 
 // One task (velocity, subdomain, component) of one problem: the body of the
 // single-problem and the batched kernels.
-template <int MODE, int DIM, int P>
+template <typename T, int MODE, int DIM, int P>
 __device__ __forceinline__ void front_wave_block(
-    const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
-    const Geom& g, const FrontParams& fp, const float* __restrict__ Wop,
+    const T* __restrict__ f_old, const T* __restrict__ f_prev, T* __restrict__ f_cur,
+    const Geom& g, const FrontParams& fp, const T* __restrict__ Wop,
     const int* __restrict__ lvl_start, const int4* __restrict__ desc, int n_desc,
-    const BndRef<float>& bd, int task, float* wave_lds) {
+    const BndRef<T>& bd, int task, T* wave_lds) {
   using S = WaveShape<DIM, P>;
   const int m = g.m, nn = S::NN;
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const int c = task % m;
   const int sd = (task / m) % nsd;
   const int k = task / (m * nsd);
-  float* FR = wave_lds;                                // [3][fr_pos][FSTR], then the sink
-  float* XO = FR + 3 * fp.fr_pos * S::FSTR + 4;        // [16][XOS]
+  T* FR = wave_lds;                                    // [3][fr_pos][FSTR], then the sink
+  T* XO = FR + 3 * fp.fr_pos * S::FSTR + 4;            // [16][XOS]
 
   int sg[3], sdc[3], nbrel[3], isb[3], boff[3];
   sdc[0] = sd % fp.nsub[0];
@@ -518,37 +568,37 @@ __device__ __forceinline__ void front_wave_block(
   const unsigned sdb = (unsigned)((sdc[0] * g.S[0] +
                                    (int64_t)g.N[0] * (sdc[1] * g.S[1] + (int64_t)g.N[1] * sdc[2] * g.S[2])) *
                                   nn);
-  const __amdgpu_buffer_rsrc_t rfo = wave_rsrc(f_old + pc * plane, plane * 4);
-  const __amdgpu_buffer_rsrc_t rfp = wave_rsrc(f_prev + pc * plane, plane * 4);
-  const __amdgpu_buffer_rsrc_t rfc = wave_rsrc(f_cur + pc * plane, plane * 4);
-  const float* Wk = Wop + (int64_t)k * nn * fp.Kd;
+  const __amdgpu_buffer_rsrc_t rfo = wave_rsrc(f_old + pc * plane, plane * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t rfp = wave_rsrc(f_prev + pc * plane, plane * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t rfc = wave_rsrc(f_cur + pc * plane, plane * (int64_t)sizeof(T));
+  const T* Wk = Wop + (int64_t)k * nn * fp.Kd;
   if (any_bnd) {
-    const __amdgpu_buffer_rsrc_t rbo = wave_rsrc(bd.old + pc * bd.nb, bd.nb * 4);
-    const __amdgpu_buffer_rsrc_t rbn = wave_rsrc(bd.neu + pc * bd.nb, bd.nb * 4);
-    front_wave_task<MODE, DIM, P, true>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel, isb,
+    const __amdgpu_buffer_rsrc_t rbo = wave_rsrc(bd.old + pc * bd.nb, bd.nb * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rbn = wave_rsrc(bd.neu + pc * bd.nb, bd.nb * (int64_t)sizeof(T));
+    front_wave_task<T, MODE, DIM, P, true>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel, isb,
                                         boff, sdb, rfo, rfp, rfc, rbo, rbn, FR, XO);
   } else {
-    front_wave_task<MODE, DIM, P, false>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel,
+    front_wave_task<T, MODE, DIM, P, false>(g, fp, Wk, lvl_start, desc, n_desc, k, sg, sdc, nbrel,
                                          isb, boff, sdb, rfo, rfp, rfc, rfo, rfp, FR, XO);
   }
 }
 
-template <int MODE, int DIM, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
+template <typename T, int MODE, int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<T, MODE, DIM, P>())))
 void k_sweep_front_wave(
-    const float* __restrict__ f_old, const float* __restrict__ f_prev, float* __restrict__ f_cur,
-    Geom g, FrontParams fp, const float* __restrict__ Wop, const int* __restrict__ lvl_start,
-    const int4* __restrict__ desc, int n_desc, BndRef<float> bd) {
-  extern __shared__ float wave_lds[];
-  front_wave_block<MODE, DIM, P>(f_old, f_prev, f_cur, g, fp, Wop, lvl_start, desc, n_desc, bd,
-                                 (int)blockIdx.x, wave_lds);
+    const T* __restrict__ f_old, const T* __restrict__ f_prev, T* __restrict__ f_cur,
+    Geom g, FrontParams fp, const T* __restrict__ Wop, const int* __restrict__ lvl_start,
+    const int4* __restrict__ desc, int n_desc, BndRef<T> bd) {
+  extern __shared__ double wave_lds_d[];  // (8-byte aligned; FP32 values use it as floats)
+  front_wave_block<T, MODE, DIM, P>(f_old, f_prev, f_cur, g, fp, Wop, lvl_start, desc, n_desc, bd,
+                                    (int)blockIdx.x, reinterpret_cast<T*>(wave_lds_d));
 }
 
 // Many problems of one (form, dimension, degree) in one launch, one
 // subdomain iteration each: the tasks of all problems are numbered
 // consecutively (start[] prefix over the problems).
 template <int MODE, int DIM, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<MODE, DIM, P>())))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<float, MODE, DIM, P>())))
 void k_sweep_front_wave_batch(const FrontWaveTask* __restrict__ tasks,
                               const int64_t* __restrict__ start, int ntask) {
   extern __shared__ float wave_lds[];
@@ -556,7 +606,7 @@ void k_sweep_front_wave_batch(const FrontWaveTask* __restrict__ tasks,
   int pid = 0;
   while (pid + 1 < ntask && gb >= start[pid + 1]) ++pid;
   const FrontWaveTask& t = tasks[pid];
-  front_wave_block<MODE, DIM, P>(t.f_old, t.f_prev, t.f_cur, t.g, t.fp, t.Wop, t.lvl_start,
+  front_wave_block<float, MODE, DIM, P>(t.f_old, t.f_prev, t.f_cur, t.g, t.fp, t.Wop, t.lvl_start,
                                  t.desc, t.n_desc, t.bd, (int)(gb - start[pid]), wave_lds);
 }
 
@@ -578,40 +628,63 @@ size_t wave_lds_size(const FrontParams& fp) {
 
 }  // namespace
 
-size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp) {
+size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp, int prec) {
+  const size_t es = prec == KDS_FP64 ? 2 : 1;  // the sizes below count FP32 values
   switch (front_wave_shape(g)) {
-    case 0: return wave_lds_size<3, 2>(fp);
-    case 1: return wave_lds_size<3, 3>(fp);
-    case 2: return wave_lds_size<2, 2>(fp);
-    case 3: return wave_lds_size<2, 3>(fp);
-    case 4: return wave_lds_size<2, 4>(fp);
+    case 0: return es * wave_lds_size<3, 2>(fp);
+    case 1: return es * wave_lds_size<3, 3>(fp);
+    case 2: return es * wave_lds_size<2, 2>(fp);
+    case 3: return es * wave_lds_size<2, 3>(fp);
+    case 4: return es * wave_lds_size<2, 4>(fp);
     default: return 0;
   }
 }
 
 bool front_wave_fits(int prec, int mode, const Geom& g, const FrontParams& fp, int64_t nb) {
-  const int64_t plane = g.ncell * g.nn;
-  return prec == KDS_FP32 && mode != kFrontFma && front_wave_shape(g) >= 0 &&
-         fp.Kd == g.nn + 3 * fp.nf && plane * 4 < ((int64_t)1 << 31) &&
-         nb * 4 < ((int64_t)1 << 31) && fp.fr_pos > 0 && front_wave_lds_bytes(g, fp) <= 64 * 1024;
+  // FP32: the matrix-core forms; FP64: the FP64 matrix cores, for the FMA mode
+  const bool f32 = prec == KDS_FP32 && mode != kFrontFma;
+  const bool f64 = prec == KDS_FP64 && mode == kFrontFma;
+  const int64_t plane = g.ncell * g.nn, es = f64 ? 8 : 4;
+  return (f32 || f64) && front_wave_shape(g) >= 0 && fp.Kd == g.nn + 3 * fp.nf &&
+         plane * es < ((int64_t)1 << 31) && nb * es < ((int64_t)1 << 31) && fp.fr_pos > 0 &&
+         front_wave_lds_bytes(g, fp, prec) <= 64 * 1024;
 }
 
-hipError_t launch_sweep_front_wave(int mode, const Geom& g, const FrontParams& fp, const void* Wop,
-                                   const int* lvl_start, const int4* desc, int n_desc,
-                                   const void* f_old, const void* f_prev, void* f_cur,
+hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const FrontParams& fp,
+                                   const void* Wop, const int* lvl_start, const int4* desc,
+                                   int n_desc, const void* f_old, const void* f_prev, void* f_cur,
                                    const BndArgs& bnd, hipStream_t s) {
-  if (!front_wave_fits(KDS_FP32, mode, g, fp, bnd.nb) || n_desc <= 0) return hipErrorInvalidValue;
+  if (!front_wave_fits(prec, mode, g, fp, bnd.nb) || n_desc <= 0) return hipErrorInvalidValue;
   const int nsd = fp.nsub[0] * fp.nsub[1] * fp.nsub[2];
   const dim3 grid((unsigned)(nsd * g.nv * g.m)), block(64);
-  const size_t lds = front_wave_lds_bytes(g, fp);
+  const size_t lds = front_wave_lds_bytes(g, fp, prec);
   const int shape = front_wave_shape(g);
+  if (prec == KDS_FP64) {
+    const double* dfo = (const double*)f_old;
+    const double* dfp = (const double*)f_prev;
+    double* dfc = (double*)f_cur;
+    const double* dW = (const double*)Wop;
+    const BndRef<double> dbd = bnd_ref<double>(bnd);
+#define KDS_WAVE64(DIM, P)                                                                    \
+  hipLaunchKernelGGL((k_sweep_front_wave<double, kFrontMfma, DIM, P>), grid, block, lds, s, dfo, \
+                     dfp, dfc, g, fp, dW, lvl_start, desc, n_desc, dbd)
+    switch (shape) {
+      case 0: KDS_WAVE64(3, 2); break;
+      case 1: KDS_WAVE64(3, 3); break;
+      case 2: KDS_WAVE64(2, 2); break;
+      case 3: KDS_WAVE64(2, 3); break;
+      default: KDS_WAVE64(2, 4); break;
+    }
+#undef KDS_WAVE64
+    return hipGetLastError();
+  }
   const float* fo = (const float*)f_old;
   const float* fpv = (const float*)f_prev;
   float* fc = (float*)f_cur;
   const float* W = (const float*)Wop;
   const BndRef<float> bd = bnd_ref<float>(bnd);
 #define KDS_WAVE_LAUNCH(MODE, DIM, P)                                                            \
-  hipLaunchKernelGGL((k_sweep_front_wave<MODE, DIM, P>), grid, block, lds, s, fo, fpv, fc, g, fp, \
+  hipLaunchKernelGGL((k_sweep_front_wave<float, MODE, DIM, P>), grid, block, lds, s, fo, fpv, fc, g, fp, \
                      W, lvl_start, desc, n_desc, bd)
 #define KDS_WAVE(MODE)                              \
   switch (shape) {                                  \

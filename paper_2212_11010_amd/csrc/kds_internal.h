@@ -254,16 +254,17 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
                               const void* f_old, const void* f_prev, void* f_cur,
                               const BndArgs& bnd, hipStream_t s);
 size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp);
-// The wave-per-task form of the same sweep (FP32 matrix-core modes, operators
-// of at most 64 columns and 32 rows).  desc: per cell in front order (the
+// The wave-per-task form of the same sweep (FP32 matrix-core modes, and the
+// FMA mode in FP64 on the FP64 matrix cores; operators of at most 64 columns
+// and 32 rows).  desc: per cell in front order (the
 // order of lvl_cells) {element offset of the cell inside its subdomain,
 // downwind local coordinates lx | ly << 10 | lz << 20, frontier position on
 // axis 0 | on axis 1 << 16, on axis 2}; n_desc entries.  nb: boundary nodes.
 bool front_wave_fits(int prec, int mode, const Geom& g, const FrontParams& fp, int64_t nb);
-size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp);
-hipError_t launch_sweep_front_wave(int mode, const Geom& g, const FrontParams& fp, const void* Wop,
-                                   const int* lvl_start, const int4* desc, int n_desc,
-                                   const void* f_old, const void* f_prev, void* f_cur,
+size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp, int prec = KDS_FP32);
+hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const FrontParams& fp,
+                                   const void* Wop, const int* lvl_start, const int4* desc,
+                                   int n_desc, const void* f_old, const void* f_prev, void* f_cur,
                                    const BndArgs& bnd, hipStream_t s);
 // The same for many problems of one (form, dimension, degree) and one
 // subdomain iteration each: a task record per problem (the arguments above),

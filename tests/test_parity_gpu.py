@@ -299,8 +299,9 @@ def front_case(name):
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_front_schedule_parity(name, prec, kernel):
     """Both front kernels, forced through the plan (1: workgroup per
-    (velocity, subdomain); 2: wave per (velocity, subdomain, component), FP32
-    matrix-core forms and cells of at most 32 nodes only)."""
+    (velocity, subdomain); 2: wave per (velocity, subdomain, component), the
+    FP32 matrix-core forms and FP64 on the FP64 matrix cores, cells of at most
+    32 nodes only)."""
     import torch
     from paper_2212_11010_amd import kds
     spec, W0, Fref, Wref = front_case(name)
@@ -314,9 +315,9 @@ def test_front_schedule_parity(name, prec, kernel):
         except kds.KdsError as e:
             assert e.status == kds.KDS_E_INVALID, e
             nodes = (spec["degree"] + 1) ** len(spec["n_cells"])
-            wave_ok = prec != "fp64" and nodes <= 32
+            wave_ok = nodes <= 32
             assert kernel == 2 and not wave_ok, "front kernel %d refused" % kernel
-            pytest.skip("the wave kernel does not apply (%s, degree %d)" % (prec, spec["degree"]))
+            pytest.skip("the wave kernel does not apply (degree %d)" % spec["degree"])
         assert pb.get_plan()["front_kernel"] == kernel
         pb.set_state(torch.from_numpy(W0).cuda())
         pb.step(spec["steps"])
@@ -334,4 +335,7 @@ def test_auto_picks_front_for_oblique_velocities():
     with kds.Problem(spec, precision="fp32_split_bf16") as pb:
         assert pb.get_plan()["front_kernel"] == 2
     with kds.Problem(spec, precision="fp64") as pb:
+        assert pb.get_plan()["front_kernel"] == 2
+    spec3, _, _, _ = front_case("maxwell_q3")       # 64-node cells: workgroup kernel
+    with kds.Problem(spec3, precision="fp64") as pb:
         assert pb.get_plan()["front_kernel"] == 1
