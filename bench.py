@@ -84,7 +84,7 @@ def device_copy_gbs(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def time_problem(spec, W0, prec, sched, steps, warmup, tune=False, plan=None):
+def time_problem(spec, W0, prec, sched, steps, warmup, tune=False, plan=None, front_kernel=0):
     """Returns (ms per step, [sweep, relax] ms per launch, info, state finite,
     launch plan)."""
     import torch
@@ -103,6 +103,11 @@ def time_problem(spec, W0, prec, sched, steps, warmup, tune=False, plan=None):
                 raise
             print("  (no device memory for the tuner's state copy: default launch plan)",
                   file=sys.stderr, flush=True)
+    if front_kernel:
+        # a forced front kernel (1: workgroup per subdomain, 2: wave per task)
+        fp = pb.get_plan()
+        fp["front_kernel"] = front_kernel
+        pb.set_plan(fp)
     info = pb.info()
     plan = pb.get_plan()
     pb.step(warmup)
@@ -461,6 +466,9 @@ def main():
     ap.add_argument("--precision", default="fp32", help="fp32 | fp32_split_f16 | fp32_split_bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fp64-front-kernel", type=int, default=0, choices=(0, 1, 2),
+                    help="front schedule, FP64 leg: 1 workgroup kernel, 2 wave kernel "
+                         "(default: the library's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-plan autotuner")
     ap.add_argument("--no-extra-legs", action="store_true",
                     help="skip the K = 1 and matrix-core front timings")
@@ -526,7 +534,8 @@ def main():
         # (its step launch mode tuned too, so that both sides launch their best way)
         ms64, k64, info64, ok64, plan64 = time_problem(spec, W0, "fp64", base,
                                                        max(5, args.steps // 5), 2,
-                                                       tune=not args.no_tune)
+                                                       tune=not args.no_tune,
+                                                       front_kernel=args.fp64_front_kernel)
         log("fp64 %s: %.4f ms/step, kernels %s ms" % (base, ms64, k64))
         extra.update({"fp64_plain_value": U / (ms64 * 1e-3), "fp64_plain_ms_per_step": ms64,
                       "fp64_plain_kernel_ms": {"sweep_per_iteration": k64[0], "relax": k64[1]},
@@ -534,6 +543,7 @@ def main():
                           "step_launch": "enqueued" if info64["step_eager"] else "graph",
                           "relax_16byte_access": bool(info64["relax_vec"])},
                       "fp64_plain_state_finite": ok64,
+                      "fp64_front_kernel": plan64.get("front_kernel", 0),
                       "speedup_fp32_vs_fp64_plain": ms64 / ms32})
     if sched == "line" and not args.no_extra_legs:
         # one subdomain iteration per step (K = 1): the step time the lag of
