@@ -385,10 +385,10 @@ const char* kds_last_error(const kds_problem* p);
  * share (precision, degree, dimension, workgroup size, law, m, n_vel,
  * periodic or Dirichlet) are swept by ONE launch whose workgroups are spread
  * over the members and relaxed by ONE more launch; front-schedule members on
- * the wave kernel in FP32 forms that share (form, dimension, degree,
- * subdomain iterations, law, m, n_vel) take ONE launch per subdomain
- * iteration and ONE relaxation; plain-schedule members, FP64 front members
- * and front members on the workgroup kernel add their own kernel sequences.  Dirichlet members advance their boundary data at
+ * the wave kernel that share (precision, form, dimension, degree, subdomain
+ * iterations, law, m, n_vel) take ONE launch per subdomain iteration and ONE
+ * relaxation; plain-schedule members and front members on the workgroup
+ * kernel add their own kernel sequences.  Dirichlet members advance their boundary data at
  * the end of each step as in kds_step.  A whole batched step is one captured HIP graph whose
  * groups are parallel branches (they touch disjoint memory), launched on the
  * batch's own stream, ordered after the work already queued on every member's

@@ -1707,7 +1707,7 @@ struct kds_batch {
   // degree, subdomain iterations, law, m, n_vel): one launch per iteration,
   // one relaxation launch
   struct FrontBranch {
-    int mode = 0, dim = 0, P = 0, K = 0, law = 0, m = 0, nv = 0;
+    int prec = 0, mode = 0, dim = 0, P = 0, K = 0, law = 0, m = 0, nv = 0;
     Geom g{};             // the first member's (the kernel shape)
     size_t lds = 0;       // largest LDS of the members
     std::vector<kds_problem*> members;
@@ -1782,18 +1782,19 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 kds_status batch_build(kds_batch* b) {
   batch_free_branches(b);
   for (kds_problem* p : b->probs) {
-    if (p->sched == KDS_SCHED_FRONT && p->front_wave && front_wave_ok(p) && p->prec == KDS_FP32) {
-      // FP32 front members on the wave kernel: grouped by their kernel and step
+    if (p->sched == KDS_SCHED_FRONT && p->front_wave && front_wave_ok(p)) {
+      // front members on the wave kernel: grouped by their kernel and step
       const size_t rb = relax_task_bytes(p->law, p->dim, p->m, p->nv);
       if (rb == 0) return bfail(b, KDS_E_UNSUPPORTED, "no batched relaxation for a member's law");
       kds_batch::FrontBranch* fb = nullptr;
       for (auto& x : b->fronts)
-        if (x.mode == p->front_mode && x.dim == p->dim && x.P == p->P && x.K == p->K &&
-            x.law == p->law && x.m == p->m && x.nv == p->nv)
+        if (x.prec == p->prec && x.mode == p->front_mode && x.dim == p->dim && x.P == p->P &&
+            x.K == p->K && x.law == p->law && x.m == p->m && x.nv == p->nv)
           fb = &x;
       if (!fb) {
         b->fronts.emplace_back();
         fb = &b->fronts.back();
+        fb->prec = p->prec;
         fb->mode = p->front_mode;
         fb->dim = p->dim;
         fb->P = p->P;
@@ -1805,17 +1806,18 @@ kds_status batch_build(kds_batch* b) {
         fb->it_tasks.resize(p->K);
       }
       fb->members.push_back(p);
-      const size_t tb = front_wave_task_bytes();
+      const size_t tb = front_wave_task_bytes(p->prec);
       for (int it = 1; it <= p->K; ++it) {
         const void* f_prev = it == 1 ? p->f : p->fit[(it - 1) & 1];
         auto& t = fb->it_tasks[it - 1];
         const size_t off = t.size();
         t.resize(off + tb);
-        pack_front_wave_task(p->geom, p->front, p->front_W, p->front_lvl_start, p->front_desc,
-                             p->front_ndesc, p->f, f_prev, p->fit[it & 1], p->bnd(), t.data() + off);
+        pack_front_wave_task(p->prec, p->geom, p->front, p->front_W, p->front_lvl_start,
+                             p->front_desc, p->front_ndesc, p->f, f_prev, p->fit[it & 1], p->bnd(),
+                             t.data() + off);
       }
       fb->start.push_back(fb->start.back() + front_wave_blocks(p->geom, p->front));
-      fb->lds = std::max(fb->lds, front_wave_lds_bytes(p->geom, p->front));
+      fb->lds = std::max(fb->lds, front_wave_lds_bytes(p->geom, p->front, p->prec));
       const size_t off = fb->relax_tasks.size();
       fb->relax_tasks.resize(off + rb);
       pack_relax_task(p->law, p->dim, p->m, p->nv, p->eq_blob.data(), p->fit[p->K & 1], p->f,
@@ -1946,12 +1948,12 @@ hipError_t launch_branch_line(const kds_batch::Branch& br, hipStream_t s) {
 }
 
 hipError_t launch_front_branch_iter(const kds_batch::FrontBranch& fb, int it, hipStream_t s) {
-  return launch_sweep_front_wave_batch(fb.mode, fb.g, fb.d_it[it], fb.d_start, fb.ntask(),
-                                       fb.start.back(), fb.lds, s);
+  return launch_sweep_front_wave_batch(fb.prec, fb.mode, fb.g, fb.d_it[it], fb.d_start,
+                                       fb.ntask(), fb.start.back(), fb.lds, s);
 }
 
 hipError_t launch_front_branch_relax(const kds_batch::FrontBranch& fb, hipStream_t s) {
-  return launch_relax_batch(KDS_FP32, fb.law, fb.dim, fb.m, fb.nv, fb.d_relax, fb.d_relax_start,
+  return launch_relax_batch(fb.prec, fb.law, fb.dim, fb.m, fb.nv, fb.d_relax, fb.d_relax_start,
                             fb.ntask(), fb.relax_start.back(), s);
 }
 

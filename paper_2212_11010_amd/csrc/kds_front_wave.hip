@@ -152,17 +152,18 @@ struct WaveShape {
 };
 
 // One problem of a batched launch (one subdomain iteration).
+template <typename T>
 struct FrontWaveTask {
-  const float* f_old;
-  const float* f_prev;
-  float* f_cur;
+  const T* f_old;
+  const T* f_prev;
+  T* f_cur;
   Geom g;
   FrontParams fp;
-  const float* Wop;
+  const T* Wop;
   const int* lvl_start;
   const int4* desc;
   int n_desc;
-  BndRef<float> bd;
+  BndRef<T> bd;
 };
 
 template <int MODE, int KS0>
@@ -597,17 +598,18 @@ void k_sweep_front_wave(
 // Many problems of one (form, dimension, degree) in one launch, one
 // subdomain iteration each: the tasks of all problems are numbered
 // consecutively (start[] prefix over the problems).
-template <int MODE, int DIM, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<float, MODE, DIM, P>())))
-void k_sweep_front_wave_batch(const FrontWaveTask* __restrict__ tasks,
+template <typename T, int MODE, int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<T, MODE, DIM, P>())))
+void k_sweep_front_wave_batch(const FrontWaveTask<T>* __restrict__ tasks,
                               const int64_t* __restrict__ start, int ntask) {
-  extern __shared__ float wave_lds[];
+  extern __shared__ double wave_lds_b[];  // (8-byte aligned; FP32 values use it as floats)
   const int64_t gb = blockIdx.x;
   int pid = 0;
   while (pid + 1 < ntask && gb >= start[pid + 1]) ++pid;
-  const FrontWaveTask& t = tasks[pid];
-  front_wave_block<float, MODE, DIM, P>(t.f_old, t.f_prev, t.f_cur, t.g, t.fp, t.Wop, t.lvl_start,
-                                 t.desc, t.n_desc, t.bd, (int)(gb - start[pid]), wave_lds);
+  const FrontWaveTask<T>& t = tasks[pid];
+  front_wave_block<T, MODE, DIM, P>(t.f_old, t.f_prev, t.f_cur, t.g, t.fp, t.Wop, t.lvl_start,
+                                    t.desc, t.n_desc, t.bd, (int)(gb - start[pid]),
+                                    reinterpret_cast<T*>(wave_lds_b));
 }
 
 // the (dim, nodes per axis) shapes the kernel is built for: 0..4, or -1
@@ -712,40 +714,72 @@ hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const Fron
   return hipGetLastError();
 }
 
-size_t front_wave_task_bytes() { return sizeof(FrontWaveTask); }
+size_t front_wave_task_bytes(int prec) {
+  return prec == KDS_FP64 ? sizeof(FrontWaveTask<double>) : sizeof(FrontWaveTask<float>);
+}
 
-void pack_front_wave_task(const Geom& g, const FrontParams& fp, const void* Wop,
-                          const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
-                          const void* f_prev, void* f_cur, const BndArgs& bnd, void* out) {
-  FrontWaveTask t;
-  t.f_old = (const float*)f_old;
-  t.f_prev = (const float*)f_prev;
-  t.f_cur = (float*)f_cur;
+namespace {
+template <typename T>
+void pack_front_wave_task_t(const Geom& g, const FrontParams& fp, const void* Wop,
+                            const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
+                            const void* f_prev, void* f_cur, const BndArgs& bnd, void* out) {
+  FrontWaveTask<T> t;
+  t.f_old = (const T*)f_old;
+  t.f_prev = (const T*)f_prev;
+  t.f_cur = (T*)f_cur;
   t.g = g;
   t.fp = fp;
-  t.Wop = (const float*)Wop;
+  t.Wop = (const T*)Wop;
   t.lvl_start = lvl_start;
   t.desc = desc;
   t.n_desc = n_desc;
-  t.bd = bnd_ref<float>(bnd);
+  t.bd = bnd_ref<T>(bnd);
   std::memcpy(out, &t, sizeof(t));
+}
+}  // namespace
+
+void pack_front_wave_task(int prec, const Geom& g, const FrontParams& fp, const void* Wop,
+                          const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
+                          const void* f_prev, void* f_cur, const BndArgs& bnd, void* out) {
+  if (prec == KDS_FP64)
+    pack_front_wave_task_t<double>(g, fp, Wop, lvl_start, desc, n_desc, f_old, f_prev, f_cur, bnd,
+                                   out);
+  else
+    pack_front_wave_task_t<float>(g, fp, Wop, lvl_start, desc, n_desc, f_old, f_prev, f_cur, bnd,
+                                  out);
 }
 
 int64_t front_wave_blocks(const Geom& g, const FrontParams& fp) {
   return (int64_t)fp.nsub[0] * fp.nsub[1] * fp.nsub[2] * g.nv * g.m;
 }
 
-hipError_t launch_sweep_front_wave_batch(int mode, const Geom& g, const void* tasks,
+hipError_t launch_sweep_front_wave_batch(int prec, int mode, const Geom& g, const void* tasks,
                                          const int64_t* start, int ntask, int64_t nblocks,
                                          size_t lds_bytes, hipStream_t s) {
   const int shape = front_wave_shape(g);
   if (shape < 0 || ntask <= 0 || nblocks <= 0 || nblocks > 0x7fffffffLL || lds_bytes > 64 * 1024)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks), block(64);
-  const FrontWaveTask* tk = (const FrontWaveTask*)tasks;
+  if (prec == KDS_FP64) {
+    if (mode != kFrontFma) return hipErrorInvalidValue;
+    const FrontWaveTask<double>* tk = (const FrontWaveTask<double>*)tasks;
+#define KDS_WAVEB64(DIM, P)                                                                   \
+  hipLaunchKernelGGL((k_sweep_front_wave_batch<double, kFrontMfma, DIM, P>), grid, block,       \
+                     lds_bytes, s, tk, start, ntask)
+    switch (shape) {
+      case 0: KDS_WAVEB64(3, 2); break;
+      case 1: KDS_WAVEB64(3, 3); break;
+      case 2: KDS_WAVEB64(2, 2); break;
+      case 3: KDS_WAVEB64(2, 3); break;
+      default: KDS_WAVEB64(2, 4); break;
+    }
+#undef KDS_WAVEB64
+    return hipGetLastError();
+  }
+  const FrontWaveTask<float>* tk = (const FrontWaveTask<float>*)tasks;
 #define KDS_WAVEB_LAUNCH(MODE, DIM, P)                                                            \
-  hipLaunchKernelGGL((k_sweep_front_wave_batch<MODE, DIM, P>), grid, block, lds_bytes, s, tk, start, \
-                     ntask)
+  hipLaunchKernelGGL((k_sweep_front_wave_batch<float, MODE, DIM, P>), grid, block, lds_bytes, s, tk, \
+                     start, ntask)
 #define KDS_WAVEB(MODE)                             \
   switch (shape) {                                  \
     case 0: KDS_WAVEB_LAUNCH(MODE, 3, 2); break;    \

@@ -266,16 +266,16 @@ hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const Fron
                                    const void* Wop, const int* lvl_start, const int4* desc,
                                    int n_desc, const void* f_old, const void* f_prev, void* f_cur,
                                    const BndArgs& bnd, hipStream_t s);
-// The same for many problems of one (form, dimension, degree) and one
-// subdomain iteration each: a task record per problem (the arguments above),
-// start[] the prefix over the problems of front_wave_blocks, lds_bytes the
-// largest front_wave_lds_bytes of the problems.
-size_t front_wave_task_bytes();
-void pack_front_wave_task(const Geom& g, const FrontParams& fp, const void* Wop,
+// The same for many problems of one (precision, form, dimension, degree)
+// and one subdomain iteration each: a task record per problem (the arguments
+// above), start[] the prefix over the problems of front_wave_blocks,
+// lds_bytes the largest front_wave_lds_bytes of the problems.
+size_t front_wave_task_bytes(int prec);
+void pack_front_wave_task(int prec, const Geom& g, const FrontParams& fp, const void* Wop,
                           const int* lvl_start, const int4* desc, int n_desc, const void* f_old,
                           const void* f_prev, void* f_cur, const BndArgs& bnd, void* out);
 int64_t front_wave_blocks(const Geom& g, const FrontParams& fp);
-hipError_t launch_sweep_front_wave_batch(int mode, const Geom& g, const void* tasks,
+hipError_t launch_sweep_front_wave_batch(int prec, int mode, const Geom& g, const void* tasks,
                                          const int64_t* start, int ntask, int64_t nblocks,
                                          size_t lds_bytes, hipStream_t s);
 

@@ -115,12 +115,14 @@ def test_batch_with_front_member_and_retune():
         pb.close()
 
 
-def test_batch_front_members_grouped():
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_front_members_grouped(prec):
     """Front-schedule members on the wave kernel share one launch per
     subdomain iteration and one relaxation launch (two D3Q4 members of
     different sizes, one with Dirichlet faces and data changing between the
-    steps); a member forced to the workgroup kernel keeps its own sequence.
-    All end bitwise equal to the same problems stepped on their own."""
+    steps), in FP32 and in FP64 (FP64 matrix cores); a member forced to the
+    workgroup kernel keeps its own sequence.  All end bitwise equal to the
+    same problems stepped on their own."""
     import torch
     from paper_2212_11010_amd import kds
     from paper_2212_11010_amd import workloads as wl
@@ -133,7 +135,7 @@ def test_batch_front_members_grouped():
     bm, bs = [], []
     for (spec, W0), kern in zip(specs, kernels):
         for lst in (bm, bs):
-            pb = kds.Problem(spec, precision="fp32", schedule="front")
+            pb = kds.Problem(spec, precision=prec, schedule="front")
             pb.set_state(torch.from_numpy(W0).cuda())
             plan = pb.get_plan()
             plan["front_kernel"] = kern
