@@ -311,19 +311,21 @@ kds_status kds_check_finite(kds_problem* p);
 
 /* Residual of the subdomain iteration (Sec. 5.1, eq:ibvp): for the step that
  * would start from the current state (and boundary data), the outflow traces
- * of every subdomain (every velocity, component and node line through the
- * subdomain's downwind face) after the last iterate K and after iterate K-1
- * (iterate 0 = the state itself), and
+ * of every subdomain (every velocity and component, at every node on the
+ * subdomain's downwind faces: for velocity k the faces across which V_k
+ * leaves it) after the last iterate K and after iterate K-1 (iterate 0 = the
+ * state itself), and
  *   out[0] = max |tr^(K) - tr^(K-1)|,  out[1] = max |tr^(K)|.
  * With lagged interface data, what leaves a subdomain through its downwind
  * face (iterate K) and what enters the next one (iterate K-1) differ by this
  * difference, weighted by theta |V_k| dt and the face quadrature, so out[0]
  * measures the conservation defect of a step; it goes to 0 as the iteration
- * converges (n_iter = 0: out = {0, -1}).  The state is not changed; runs the
- * literal sweep's kernels (one launch per iterate) on the problem's stream and
- * waits.  Axis-aligned velocity sets only (else KDS_E_UNSUPPORTED); errors
+ * converges (n_iter = 0: out = {0, -1}).  The state is not changed.  Runs,
+ * on the problem's stream, and waits: on the front schedule (any velocity
+ * set) its own K iterates into its iterate buffers; otherwise the literal
+ * sweep's kernels (one launch per iterate, two trace sets allocated).  Errors
  * KDS_E_INVALID, KDS_E_STATE (no state, or Dirichlet data missing),
- * KDS_E_NOMEM (two trace sets of device memory), KDS_E_DEVICE. */
+ * KDS_E_NOMEM, KDS_E_DEVICE. */
 kds_status kds_trace_residual(kds_problem* p, double* out);
 
 /* Wait for all work of the problem's stream. */

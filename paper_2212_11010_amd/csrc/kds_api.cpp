@@ -1585,15 +1585,39 @@ kds_status kds_trace_residual(kds_problem* p, double* out) {
   if (!p->state_set) return fail(p, KDS_E_STATE, "kds_trace_residual before kds_set_state");
   if (p->nbnd > 0 && !p->bnd_set)
     return fail(p, KDS_E_STATE, "Dirichlet axes: kds_set_boundary before kds_trace_residual");
-  if (p->sweep_blob.empty())
-    return fail(p, KDS_E_UNSUPPORTED,
-                "kds_trace_residual: oblique velocities (the traces of axis-aligned sweeps only)");
   const Geom& g = p->geom;
   if (p->K == 0) {  // the converged iteration: no residual
     out[0] = 0.0;
     out[1] = -1.0;
     return KDS_OK;
   }
+  if (p->sched == KDS_SCHED_FRONT) {
+    // the front schedule's own iterates 1 .. K into its iterate buffers (the
+    // state is not changed), then the change between the last two over the
+    // subdomains' outflow faces
+    unsigned long long* red = nullptr;
+    if (hipMalloc((void**)&red, 16) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(p, KDS_E_NOMEM, "kds_trace_residual: no device memory");
+    }
+    hipError_t e = hipMemsetAsync(red, 0, 16, p->stream);
+    for (int it = 1; it <= p->K && e == hipSuccess; ++it)
+      e = launch_front_iter(p, it == 1 ? p->f : p->fit[(it - 1) & 1], p->fit[it & 1], p->stream);
+    if (e == hipSuccess)
+      e = launch_max_absdiff_outflow(p->prec, p->fit[p->K & 1],
+                                     p->K == 1 ? p->f : p->fit[(p->K - 1) & 1], g, p->front, red,
+                                     p->stream);
+    unsigned long long bits[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(bits, red, 16, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(red);
+    if (e != hipSuccess) return hip_fail(p, e, "kds_trace_residual");
+    std::memcpy(&out[0], &bits[0], 8);
+    std::memcpy(&out[1], &bits[1], 8);
+    return KDS_OK;
+  }
+  if (p->sweep_blob.empty())
+    return fail(p, KDS_E_UNSUPPORTED, "kds_trace_residual: no sweep table for this problem");
   // two trace sets, zeroed (entries no velocity uses stay 0 in both), and the
   // two reduction words
   const int64_t n = g.tr_stride * (int64_t)p->nv * p->m;

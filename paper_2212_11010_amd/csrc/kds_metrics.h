@@ -19,4 +19,11 @@ hipError_t launch_trace_iterate0(int prec, const Geom& g, const void* tab, const
 hipError_t launch_max_absdiff(int prec, const void* x, const void* y, int64_t n,
                               unsigned long long* out, hipStream_t s);
 
+// The same over the nodes on the outflow faces of every subdomain (for
+// velocity k the downwind faces along each axis with fp.sg[k][a] != 0), x and
+// y full states [k m + c][cell][node]: any velocity set.
+hipError_t launch_max_absdiff_outflow(int prec, const void* x, const void* y, const Geom& g,
+                                      const FrontParams& fp, unsigned long long* out,
+                                      hipStream_t s);
+
 }  // namespace kds

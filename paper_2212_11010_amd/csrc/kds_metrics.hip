@@ -77,6 +77,50 @@ __global__ __launch_bounds__(256) void k_max_absdiff(const T* __restrict__ x,
   }
 }
 
+// The same maximum over the nodes on the outflow faces of every subdomain:
+// for velocity k, the faces on the downwind side along each axis where
+// V^a != 0 (sg: the signs of V^a); x and y full states laid out
+// [k m + c][cell][node], cells and nodes with axis 0 fastest.
+template <typename T>
+__global__ __launch_bounds__(256) void k_max_absdiff_outflow(const T* __restrict__ x,
+                                                             const T* __restrict__ y, Geom g,
+                                                             FrontParams fp,
+                                                             unsigned long long* __restrict__ out) {
+  const int64_t n = (int64_t)g.nv * g.m * g.ncell * g.nn;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double d = 0.0, v = 0.0;
+  for (; i < n; i += stride) {
+    int64_t r = i / g.nn;
+    int nd = (int)(i - r * g.nn);
+    int64_t cell = r % g.ncell;
+    const int k = (int)(r / g.ncell) / g.m;
+    bool on = false;
+    for (int a = 0; a < g.dim; ++a) {
+      const int ca = (int)(cell % g.N[a]);
+      cell /= g.N[a];
+      const int ba = nd % g.P;
+      nd /= g.P;
+      const int sa = fp.sg[k][a];
+      if (sa > 0) on = on || (ca % g.S[a] == g.S[a] - 1 && ba == g.P - 1);
+      if (sa < 0) on = on || (ca % g.S[a] == 0 && ba == 0);
+    }
+    if (!on) continue;
+    const double xi = (double)x[i], yi = (double)y[i];
+    const double di = fabs(xi - yi), vi = fabs(xi);
+    d = di == di ? fmax(d, di) : INFINITY;
+    v = vi == vi ? fmax(v, vi) : INFINITY;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d = fmax(d, __shfl_xor(d, o));
+    v = fmax(v, __shfl_xor(v, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(d));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(v));
+  }
+}
+
 template <typename T>
 hipError_t trace_iterate0_t(const Geom& g, const void* tab, const void* f, void* tr,
                             hipStream_t s) {
@@ -121,6 +165,20 @@ hipError_t launch_max_absdiff(int prec, const void* x, const void* y, int64_t n,
   else
     hipLaunchKernelGGL(k_max_absdiff<float>, dim3(nb), dim3(256), 0, s, (const float*)x,
                        (const float*)y, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_absdiff_outflow(int prec, const void* x, const void* y, const Geom& g,
+                                      const FrontParams& fp, unsigned long long* out,
+                                      hipStream_t s) {
+  const int64_t n = (int64_t)g.nv * g.m * g.ncell * g.nn;
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n), 4096));
+  if (prec == KDS_FP64)
+    hipLaunchKernelGGL(k_max_absdiff_outflow<double>, dim3(nb), dim3(256), 0, s, (const double*)x,
+                       (const double*)y, g, fp, out);
+  else
+    hipLaunchKernelGGL(k_max_absdiff_outflow<float>, dim3(nb), dim3(256), 0, s, (const float*)x,
+                       (const float*)y, g, fp, out);
   return hipGetLastError();
 }
 

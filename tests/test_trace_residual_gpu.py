@@ -2,8 +2,11 @@
 between the last two Jacobi iterates of Sec. 5.1 (eq:ibvp), for the step
 that would start from the current state.  The expected values come from the
 FP64 oracle: its transport run with n_iter = K and with n_iter = K - 1 (or,
-for K = 1, the state itself: iterate 0), read at the downwind face node of
-every subdomain's last cell along each velocity's axis."""
+for K = 1, the state itself: iterate 0), read at every node on the
+subdomains' outflow faces (for each axis along which the velocity has a
+component, the downwind face of the subdomain's last cell on that axis):
+axis-aligned sets (plain, line and front schedules) and the D3Q4 set of
+the paper (front schedule)."""
 import numpy as np
 import pytest
 
@@ -18,26 +21,33 @@ CASES = {
     "advection2d_K4": (1, dict(n_cells=[32, 16], sub_cells=[8, 4], n_iter=4), 2),
     "euler3d_K2": (3, dict(n_cells=[6, 4, 4], sub_cells=[3, 2, 2], n_iter=2), 1),
 }
+# D3Q4 Maxwell (oblique velocities: front schedule only)
+OBLIQUE = {
+    "maxwell_q2_K3": (6, dict(n_cells=[8, 8, 4], sub_cells=[4, 4, 2], n_iter=3), 1),
+    "maxwell_q1_K1": (6, dict(n_cells=[6, 4, 4], sub_cells=[3, 2, 4], n_iter=1, degree=1), 0),
+}
 
 
 def outflow_nodes(c, k, T):
-    """T[cell, node] of velocity k -> its values at the downwind face node of
-    each subdomain's last cell along the velocity's axis."""
+    """T[cell, node] of velocity k -> its values at the nodes on the
+    subdomains' outflow faces: for each axis a with V^a != 0, the nodes at
+    the downwind end along a of the cells at the downwind end of their
+    subdomain along a."""
     spec = c.spec
     d, P = c.dim, c.P
     v = np.asarray(spec["vel"], dtype=np.float64).reshape(-1, d)[k]
-    (a,) = np.nonzero(v)[0]
     N = [int(n) for n in spec["n_cells"][:d]]
-    S = int(spec["sub_cells"][a])
-    # cells and nodes numbered with axis 0 fastest: reverse the axes for numpy
-    X = T.reshape(N[::-1] + [P] * d)
-    ca, na = d - 1 - a, 2 * d - 1 - a
-    if v[a] > 0:
-        cells, node = np.arange(S - 1, N[a], S), P - 1
-    else:
-        cells, node = N[a] - 1 - np.arange(S - 1, N[a], S), 0
-    X = np.take(X, cells, axis=ca)
-    return np.take(X, node, axis=na).ravel()
+    S = [int(x) for x in spec["sub_cells"][:d]]
+    # cells and nodes numbered with axis 0 fastest
+    cc = np.indices(N[::-1]).reshape(d, -1)[::-1]        # [axis][cell]
+    nc = np.indices([P] * d).reshape(d, -1)[::-1]        # [axis][node]
+    mask = np.zeros((len(cc[0]), len(nc[0])), dtype=bool)
+    for a in range(d):
+        if v[a] > 0:
+            mask |= ((cc[a] % S[a]) == S[a] - 1)[:, None] & (nc[a] == P - 1)[None, :]
+        elif v[a] < 0:
+            mask |= ((cc[a] % S[a]) == 0)[:, None] & (nc[a] == 0)[None, :]
+    return T[mask]
 
 
 def oracle_residual(wcfg, ov, steps):
@@ -91,7 +101,34 @@ def test_trace_residual_against_oracle(name, prec, sched):
     assert np.array_equal(W1, W2)
 
 
-def test_trace_residual_converged_and_oblique():
+@pytest.mark.parametrize("name", list(OBLIQUE))
+@pytest.mark.parametrize("prec,kernel", [("fp64", 2), ("fp64", 1), ("fp32", 2),
+                                         ("fp32_split_f16", 2)])
+def test_trace_residual_oblique_against_oracle(name, prec, kernel):
+    import torch
+    from paper_2212_11010_amd import kds
+    wcfg, ov, steps = OBLIQUE[name]
+    spec, W0, dref, vref = oracle_residual(wcfg, ov, steps)
+    print("trace residual", name, prec, "front kernel", kernel, flush=True)
+    tol = {"fp64": 1e-12, "fp32": 2e-5, "fp32_split_f16": 2e-5}[prec]
+    with kds.Problem(spec, precision=prec, schedule="front") as pb:
+        plan = pb.get_plan()
+        plan["front_kernel"] = kernel
+        pb.set_plan(plan)
+        pb.set_state(torch.from_numpy(W0).cuda())
+        if steps:
+            pb.step(steps)
+        W1 = pb.moments()
+        d, v = pb.trace_residual()
+        assert np.array_equal(W1, pb.moments())
+    print("  residual %.6e (oracle %.6e), max trace %.6e (oracle %.6e)" % (d, dref, v, vref),
+          flush=True)
+    assert dref > 0.0
+    assert abs(v - vref) <= tol * vref
+    assert abs(d - dref) <= tol * vref
+
+
+def test_trace_residual_converged_and_no_state():
     import torch
     from paper_2212_11010_amd import kds, workloads as wl
     spec, W0 = wl.make_workload(2, n_cells=[16, 8], sub_cells=[4, 4], n_iter=0, steps=1)
@@ -101,9 +138,3 @@ def test_trace_residual_converged_and_oblique():
         assert ei.value.status == kds.KDS_E_STATE
         pb.set_state(torch.from_numpy(W0).cuda())
         assert pb.trace_residual() == (0.0, -1.0)
-    spec, W0 = wl.make_workload(6, n_cells=[4, 4, 4], sub_cells=[2, 2, 2], steps=1)
-    with kds.Problem(spec, precision="fp32") as pb:
-        pb.set_state(torch.from_numpy(W0).cuda())
-        with pytest.raises(kds.KdsError) as ei:
-            pb.trace_residual()
-        assert ei.value.status == kds.KDS_E_UNSUPPORTED
