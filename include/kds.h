@@ -211,10 +211,10 @@ kds_status kds_set_launch(kds_problem* p, int32_t step_eager, int32_t relax_vec)
  * ignored (kds_set_plan).  step_eager and relax_vec as in kds_set_launch.
  * front_kernel (front schedule; 0 elsewhere): 1 = one workgroup per
  * (velocity, subdomain), any cell size and precision; 2 = one wave per
- * (velocity, subdomain, component), the FP32 matrix-core forms and FP64 (on
- * the FP64 matrix cores) with cells of at most 32 nodes (p <= 2 in 3-D,
- * p <= 3 in 2-D) and frontiers that fit the LDS; kds_set_plan with
- * front_kernel = 0 keeps the current kernel.
+ * (velocity, subdomain, component): the FP32 matrix-core forms with cells of
+ * up to 64 nodes (p <= 3), FP64 (on the FP64 matrix cores) with cells of at
+ * most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D), frontiers that fit the LDS;
+ * kds_set_plan with front_kernel = 0 keeps the current kernel.
  * The FP64 results of every valid plan agree to rounding; FP32 results depend
  * on Q (the association of the line scan) and on the front kernel (the order
  * of the products' sums), so a plan saved with kds_get_plan and restored with

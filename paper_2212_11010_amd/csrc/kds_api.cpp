@@ -701,9 +701,9 @@ kds_status kds_create(const kds_config* cfg, void* hip_stream, kds_problem** out
   if (want_front) {
     p->sched = KDS_SCHED_FRONT;
     p->front_ndesc = (int)front_desc.size();
-    // the wave-per-task kernel where it applies (its records fit, FP32
-    // matrix-core modes or FP64, p <= 2 in 3-D), else one workgroup per
-    // subdomain
+    // the wave-per-task kernel where it applies (its records fit; FP32
+    // matrix-core forms up to 64-node cells, FP64 up to 32), else one
+    // workgroup per subdomain
     p->front_wave = front_wave_ok(p);
     if (!p->front_wave && !front_wg_ok(p)) {
       delete p;

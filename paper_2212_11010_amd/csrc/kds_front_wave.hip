@@ -1,7 +1,7 @@
 // kds_front_wave.hip -- the front schedule with one wave per
-// (velocity, subdomain, component): the FP32 matrix-core forms, and FP64 on
-// the FP64 matrix cores, for cells of at most 32 nodes (p <= 2 in 3-D,
-// p <= 3 in 2-D).
+// (velocity, subdomain, component): the FP32 matrix-core forms for cells of
+// up to 64 nodes (p <= 3), and FP64 on the FP64 matrix cores for cells of at
+// most 32 nodes (p <= 2 in 3-D, p <= 3 in 2-D).
 //
 // The same computation as k_sweep_front (the solves of one anti-diagonal
 // front of the V-oriented cell graph as one GEMM Y = W X per front, Sec. 3.2,
@@ -515,7 +515,7 @@ __device__ __forceinline__ void front_wave_task(
 // takes two registers per value: two waves
 template <typename T, int MODE, int DIM, int P>
 constexpr int wave_occupancy() {
-  return sizeof(T) == 8 ? 2 : (WaveShape<DIM, P>::NN > 16 ? 3 : 4);
+  return WaveShape<DIM, P>::NN > 32 ? 1 : (sizeof(T) == 8 ? 2 : (WaveShape<DIM, P>::NN > 16 ? 3 : 4));
 }
 
 // One task (velocity, subdomain, component) of one problem: the body of the
@@ -612,13 +612,15 @@ void k_sweep_front_wave_batch(const FrontWaveTask<T>* __restrict__ tasks,
                                     reinterpret_cast<T*>(wave_lds_b));
 }
 
-// the (dim, nodes per axis) shapes the kernel is built for: 0..4, or -1
+// the (dim, nodes per axis) shapes the kernel is built for: 0..5, or -1
+// (5: 64-node cells, the FP32 forms only)
 int front_wave_shape(const Geom& g) {
   if (g.dim == 3 && g.P == 2) return 0;
   if (g.dim == 3 && g.P == 3) return 1;
   if (g.dim == 2 && g.P == 2) return 2;
   if (g.dim == 2 && g.P == 3) return 3;
   if (g.dim == 2 && g.P == 4) return 4;
+  if (g.dim == 3 && g.P == 4) return 5;
   return -1;
 }
 
@@ -638,6 +640,7 @@ size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp, int prec) {
     case 2: return es * wave_lds_size<2, 2>(fp);
     case 3: return es * wave_lds_size<2, 3>(fp);
     case 4: return es * wave_lds_size<2, 4>(fp);
+    case 5: return es * wave_lds_size<3, 4>(fp);
     default: return 0;
   }
 }
@@ -645,7 +648,7 @@ size_t front_wave_lds_bytes(const Geom& g, const FrontParams& fp, int prec) {
 bool front_wave_fits(int prec, int mode, const Geom& g, const FrontParams& fp, int64_t nb) {
   // FP32: the matrix-core forms; FP64: the FP64 matrix cores, for the FMA mode
   const bool f32 = prec == KDS_FP32 && mode != kFrontFma;
-  const bool f64 = prec == KDS_FP64 && mode == kFrontFma;
+  const bool f64 = prec == KDS_FP64 && mode == kFrontFma && front_wave_shape(g) != 5;
   const int64_t plane = g.ncell * g.nn, es = f64 ? 8 : 4;
   return (f32 || f64) && front_wave_shape(g) >= 0 && fp.Kd == g.nn + 3 * fp.nf &&
          plane * es < ((int64_t)1 << 31) && nb * es < ((int64_t)1 << 31) && fp.fr_pos > 0 &&
@@ -675,7 +678,8 @@ hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const Fron
       case 1: KDS_WAVE64(3, 3); break;
       case 2: KDS_WAVE64(2, 2); break;
       case 3: KDS_WAVE64(2, 3); break;
-      default: KDS_WAVE64(2, 4); break;
+      case 4: KDS_WAVE64(2, 4); break;
+      default: return hipErrorInvalidValue;
     }
 #undef KDS_WAVE64
     return hipGetLastError();
@@ -694,7 +698,8 @@ hipError_t launch_sweep_front_wave(int prec, int mode, const Geom& g, const Fron
     case 1: KDS_WAVE_LAUNCH(MODE, 3, 3); break;     \
     case 2: KDS_WAVE_LAUNCH(MODE, 2, 2); break;     \
     case 3: KDS_WAVE_LAUNCH(MODE, 2, 3); break;     \
-    default: KDS_WAVE_LAUNCH(MODE, 2, 4); break;    \
+    case 4: KDS_WAVE_LAUNCH(MODE, 2, 4); break;     \
+    default: KDS_WAVE_LAUNCH(MODE, 3, 4); break;    \
   }
   switch (mode) {
     case kFrontMfma:
@@ -771,7 +776,8 @@ hipError_t launch_sweep_front_wave_batch(int prec, int mode, const Geom& g, cons
       case 1: KDS_WAVEB64(3, 3); break;
       case 2: KDS_WAVEB64(2, 2); break;
       case 3: KDS_WAVEB64(2, 3); break;
-      default: KDS_WAVEB64(2, 4); break;
+      case 4: KDS_WAVEB64(2, 4); break;
+      default: return hipErrorInvalidValue;
     }
 #undef KDS_WAVEB64
     return hipGetLastError();
@@ -786,7 +792,8 @@ hipError_t launch_sweep_front_wave_batch(int prec, int mode, const Geom& g, cons
     case 1: KDS_WAVEB_LAUNCH(MODE, 3, 3); break;    \
     case 2: KDS_WAVEB_LAUNCH(MODE, 2, 2); break;    \
     case 3: KDS_WAVEB_LAUNCH(MODE, 2, 3); break;    \
-    default: KDS_WAVEB_LAUNCH(MODE, 2, 4); break;   \
+    case 4: KDS_WAVEB_LAUNCH(MODE, 2, 4); break;    \
+    default: KDS_WAVEB_LAUNCH(MODE, 3, 4); break;   \
   }
   switch (mode) {
     case kFrontMfma:

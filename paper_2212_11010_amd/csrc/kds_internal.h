@@ -254,9 +254,9 @@ hipError_t launch_sweep_front(int prec, int mode, const Geom& g, const FrontPara
                               const void* f_old, const void* f_prev, void* f_cur,
                               const BndArgs& bnd, hipStream_t s);
 size_t front_lds_bytes(int prec, int mode, const Geom& g, const FrontParams& fp);
-// The wave-per-task form of the same sweep (FP32 matrix-core modes, and the
-// FMA mode in FP64 on the FP64 matrix cores; operators of at most 64 columns
-// and 32 rows).  desc: per cell in front order (the
+// The wave-per-task form of the same sweep (FP32 matrix-core modes for cells
+// of up to 64 nodes, and the FMA mode in FP64 on the FP64 matrix cores for
+// cells of up to 32 nodes).  desc: per cell in front order (the
 // order of lvl_cells) {element offset of the cell inside its subdomain,
 // downwind local coordinates lx | ly << 10 | lz << 20, frontier position on
 // axis 0 | on axis 1 << 16, on axis 2}; n_desc entries.  nb: boundary nodes.

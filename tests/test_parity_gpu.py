@@ -300,8 +300,8 @@ def front_case(name):
 def test_front_schedule_parity(name, prec, kernel):
     """Both front kernels, forced through the plan (1: workgroup per
     (velocity, subdomain); 2: wave per (velocity, subdomain, component), the
-    FP32 matrix-core forms and FP64 on the FP64 matrix cores, cells of at most
-    32 nodes only)."""
+    FP32 matrix-core forms and FP64 on the FP64 matrix cores for cells of at
+    most 32 nodes, the FP32 forms for 64-node cells)."""
     import torch
     from paper_2212_11010_amd import kds
     spec, W0, Fref, Wref = front_case(name)
@@ -315,9 +315,9 @@ def test_front_schedule_parity(name, prec, kernel):
         except kds.KdsError as e:
             assert e.status == kds.KDS_E_INVALID, e
             nodes = (spec["degree"] + 1) ** len(spec["n_cells"])
-            wave_ok = nodes <= 32
+            wave_ok = nodes <= 32 or (nodes == 64 and prec != "fp64")
             assert kernel == 2 and not wave_ok, "front kernel %d refused" % kernel
-            pytest.skip("the wave kernel does not apply (degree %d)" % spec["degree"])
+            pytest.skip("the wave kernel does not apply (%s, degree %d)" % (prec, spec["degree"]))
         assert pb.get_plan()["front_kernel"] == kernel
         pb.set_state(torch.from_numpy(W0).cuda())
         pb.step(spec["steps"])
@@ -336,6 +336,7 @@ def test_auto_picks_front_for_oblique_velocities():
         assert pb.get_plan()["front_kernel"] == 2
     with kds.Problem(spec, precision="fp64") as pb:
         assert pb.get_plan()["front_kernel"] == 2
-    spec3, _, _, _ = front_case("maxwell_q3")       # 64-node cells: workgroup kernel
-    with kds.Problem(spec3, precision="fp64") as pb:
-        assert pb.get_plan()["front_kernel"] == 1
+    spec3, _, _, _ = front_case("maxwell_q3")       # 64-node cells: FP32 forms only
+    for prec, kern in (("fp64", 1), ("fp32", 2), ("fp32_split_bf16", 2)):
+        with kds.Problem(spec3, precision=prec) as pb:
+            assert pb.get_plan()["front_kernel"] == kern
