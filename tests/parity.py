@@ -13,6 +13,9 @@ velocity that sits exactly on the sub-characteristic bound, whose equilibrium
 vanishes: its values are rounding noise) and is measured on the global scale.
 
 Layouts: W [cell][node][c], F [k][cell][node][c] (the C ABI's).
+
+outflow_nodes: the values of one velocity's field at the nodes on the
+subdomains' outflow faces (where the subdomain iteration's traces live).
 """
 from __future__ import annotations
 
@@ -52,3 +55,25 @@ def check(W, Wref, F, Fref, tol, label="", tol_plane=None):
           flush=True)
     assert max(ew, ef) <= tol and max(pw, pf) <= tol_plane, (ew, ef, pw, pf)
     return ew, ef, pw, pf
+
+
+def outflow_nodes(c, k, T):
+    """T[cell, node] of velocity k -> its values at the nodes on the
+    subdomains' outflow faces: for each axis a with V^a != 0, the nodes at
+    the downwind end along a of the cells at the downwind end of their
+    subdomain along a."""
+    spec = c.spec
+    d, P = c.dim, c.P
+    v = np.asarray(spec["vel"], dtype=np.float64).reshape(-1, d)[k]
+    N = [int(n) for n in spec["n_cells"][:d]]
+    S = [int(x) for x in spec["sub_cells"][:d]]
+    # cells and nodes numbered with axis 0 fastest
+    cc = np.indices(N[::-1]).reshape(d, -1)[::-1]        # [axis][cell]
+    nc = np.indices([P] * d).reshape(d, -1)[::-1]        # [axis][node]
+    mask = np.zeros((len(cc[0]), len(nc[0])), dtype=bool)
+    for a in range(d):
+        if v[a] > 0:
+            mask |= ((cc[a] % S[a]) == S[a] - 1)[:, None] & (nc[a] == P - 1)[None, :]
+        elif v[a] < 0:
+            mask |= ((cc[a] % S[a]) == 0)[:, None] & (nc[a] == 0)[None, :]
+    return T[mask]

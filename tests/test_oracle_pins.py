@@ -807,3 +807,38 @@ def test_converged_step_never_grows_the_entropy_norm(orc, omega, theta, beta):
         E.append(_entropy(F, D, w2))
     ratios = np.array(E[1:]) / np.array(E[:-1])
     assert ratios.max() <= 1.0 + 1e-12, ratios
+
+
+def test_trace_residual_contracts_by_the_subdomain_transmission(orc):
+    """Sec. 5.1 (eq:ibvp): iterate p of a subdomain takes its inflow from the
+    upwind subdomain's iterate p-1, and the transport is linear, so the
+    change of the outflow traces obeys d_s^p = G d_{s-1}^{p-1} with G the
+    transmission of the whole subdomain, the product of S identical cell
+    transmissions g (G = g^S).  On a periodic row the largest change
+    therefore shrinks by exactly |G| per iterate, whatever the data, and
+    halving S takes the square root of that factor.  A wrong lag (iterate p
+    reading iterate p), a dropped interface or a miscounted subdomain breaks
+    one of the three."""
+    from tests.parity import outflow_nodes
+    rng = np.random.default_rng(11)
+    f0 = rng.normal(size=(32, 3))
+
+    def factors(S):
+        base = spec1d(N=32, S=S, p=2, nu=6.0, K=1)
+        c = orc.Config(base)
+        prev = outflow_nodes(c, 0, f0)
+        d = []
+        for K in range(1, 5):
+            tk = outflow_nodes(c, 0, orc.transport(orc.Config(dict(base, n_iter=K)), 0, f0))
+            d.append(float(np.max(np.abs(tk - prev))))
+            prev = tk
+        return [d[i + 1] / d[i] for i in range(len(d) - 1)]
+
+    # (kinetic Courant number 6: G = 0.51, 0.26, 0.069 for S = 2, 4, 8, so
+    # four iterates stay far above rounding)
+    q2, q4, q8 = factors(2), factors(4), factors(8)
+    for q in (q2, q4, q8):
+        assert 0.0 < q[0] < 1.0
+        assert max(abs(x / q[0] - 1.0) for x in q) < 1e-9, q
+    assert abs(q4[0] / q2[0] ** 2 - 1.0) < 1e-9, (q2[0], q4[0])
+    assert abs(q8[0] / q4[0] ** 2 - 1.0) < 1e-9, (q4[0], q8[0])

@@ -10,6 +10,8 @@ the paper (front schedule)."""
 import numpy as np
 import pytest
 
+from tests.parity import outflow_nodes
+
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 2e-5}
@@ -26,28 +28,6 @@ OBLIQUE = {
     "maxwell_q2_K3": (6, dict(n_cells=[8, 8, 4], sub_cells=[4, 4, 2], n_iter=3), 1),
     "maxwell_q1_K1": (6, dict(n_cells=[6, 4, 4], sub_cells=[3, 2, 4], n_iter=1, degree=1), 0),
 }
-
-
-def outflow_nodes(c, k, T):
-    """T[cell, node] of velocity k -> its values at the nodes on the
-    subdomains' outflow faces: for each axis a with V^a != 0, the nodes at
-    the downwind end along a of the cells at the downwind end of their
-    subdomain along a."""
-    spec = c.spec
-    d, P = c.dim, c.P
-    v = np.asarray(spec["vel"], dtype=np.float64).reshape(-1, d)[k]
-    N = [int(n) for n in spec["n_cells"][:d]]
-    S = [int(x) for x in spec["sub_cells"][:d]]
-    # cells and nodes numbered with axis 0 fastest
-    cc = np.indices(N[::-1]).reshape(d, -1)[::-1]        # [axis][cell]
-    nc = np.indices([P] * d).reshape(d, -1)[::-1]        # [axis][node]
-    mask = np.zeros((len(cc[0]), len(nc[0])), dtype=bool)
-    for a in range(d):
-        if v[a] > 0:
-            mask |= ((cc[a] % S[a]) == S[a] - 1)[:, None] & (nc[a] == P - 1)[None, :]
-        elif v[a] < 0:
-            mask |= ((cc[a] % S[a]) == 0)[:, None] & (nc[a] == 0)[None, :]
-    return T[mask]
 
 
 def oracle_residual(wcfg, ov, steps):
