@@ -842,3 +842,25 @@ def test_trace_residual_contracts_by_the_subdomain_transmission(orc):
         assert max(abs(x / q[0] - 1.0) for x in q) < 1e-9, q
     assert abs(q4[0] / q2[0] ** 2 - 1.0) < 1e-9, (q2[0], q4[0])
     assert abs(q8[0] / q4[0] ** 2 - 1.0) < 1e-9, (q4[0], q8[0])
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+@pytest.mark.parametrize("S", [2, 4])
+def test_degree0_subdomain_transmission_closed_form(orc, theta, S):
+    """Degree 0 (the implicit upwind finite-volume theta-scheme): a cell's
+    value responds to its new inflow value by g = theta nu / (1 + theta nu)
+    (the cell update (1 + theta nu) f^n = theta nu t_in^n + terms of t^{n-1}),
+    so the trace residual contracts by exactly G = g^S per iterate."""
+    from tests.parity import outflow_nodes
+    nu = 6.0
+    f0 = np.random.default_rng(3).normal(size=(32, 1))
+    base = spec1d(N=32, S=S, p=0, nu=nu, K=1, theta=theta)
+    c = orc.Config(base)
+    prev, d = outflow_nodes(c, 0, f0), []
+    for K in range(1, 5):
+        tk = outflow_nodes(c, 0, orc.transport(orc.Config(dict(base, n_iter=K)), 0, f0))
+        d.append(float(np.max(np.abs(tk - prev))))
+        prev = tk
+    G = (theta * nu / (1.0 + theta * nu)) ** S
+    for i in range(3):
+        assert abs(d[i + 1] / d[i] / G - 1.0) < 1e-12, (i, d, G)
