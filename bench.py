@@ -474,6 +474,8 @@ def main():
                     help="skip the K = 1 and matrix-core front timings")
     ap.add_argument("--no-hbm-leg", action="store_true",
                     help="cfg2: skip the 128^3 Euler (HBM-bound) leg")
+    ap.add_argument("--no-front-leg", action="store_true",
+                    help="cfg2: skip the 64^3 D3Q4 Maxwell front-schedule leg")
     ap.add_argument("--no-gemm-variants", action="store_true",
                     help="cfg4: skip the front-schedule GEMM variants (FP32 / FP16 / BF16 split)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -617,6 +619,8 @@ def main():
         extra["front_gemm_variants"] = gemm_variants(spec, W0, U)
     if args.workload == "cfg2" and not args.no_hbm_leg and args.cells == 0:
         extra["hbm_leg_cfg3"] = hbm_leg(args)
+    if args.workload == "cfg2" and not args.no_front_leg and args.cells == 0:
+        extra["front_leg_maxwell64"] = front_leg(args)
     out = {
         "metric": METRIC, "value": U / (ms32 * 1e-3), "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
@@ -676,6 +680,32 @@ def hbm_leg(args):
             "step_hbm_frac": gbs(16.0 * U, ms) / HBM_PEAK_GBS,
             "literal_scheme_step_frac": gbs(32.0 * U, ms) / HBM_PEAK_GBS,
             "state_bytes": info["state_bytes"], "state_finite": ok}
+
+
+def front_leg(args):
+    """The paper's own velocity set: D3Q4 Maxwell, 64^3 cells, 8^3-cell
+    subdomains, p = 2, FP32 front schedule (one launch per subdomain
+    iteration, dense cell GEMMs on the matrix cores).  Algorithmic figures
+    per launch: one read and one write of the state (8 B per unknown) and
+    2 n_n (n_n + 3 n_f) flop per cell column of every (velocity, component)."""
+    from paper_2212_11010_amd import workloads as wl
+    spec, W0 = workload("maxwell", 64, 8)
+    U = wl.unknowns(spec)
+    ms, k, info, ok, plan = time_problem(spec, W0, "fp32", "front", max(5, args.steps // 4), 2,
+                                         tune=False)
+    log("maxwell 64^3 fp32 front: %.3f ms/step, kernels %s ms" % (ms, k))
+    nn = (spec["degree"] + 1) ** 3
+    nf = (spec["degree"] + 1) ** 2
+    cols = U // nn                               # cell columns over all (velocity, component)
+    flops = 2.0 * nn * (nn + 3 * nf) * cols
+    sweep_s = k[0] * 1e-3
+    return {"workload": spec["name"], "n_cells": spec["n_cells"], "sub_cells": spec["sub_cells"],
+            "degree": spec["degree"], "unknowns": U, "front_kernel": plan.get("front_kernel"),
+            "ms_per_step": ms, "value": U / (ms * 1e-3), "sweep_ms_per_iteration": k[0],
+            "relax_ms": k[1], "sweep_hbm_frac": 8.0 * U / sweep_s / 1e9 / HBM_PEAK_GBS,
+            "sweep_algorithmic_tflops": flops / sweep_s / 1e12,
+            "sweep_mfma_frac": flops / sweep_s / 1e12 / MFMA_PEAK_TFS["fp32"],
+            "state_finite": ok}
 
 
 if __name__ == "__main__":
